@@ -1,0 +1,775 @@
+/*
+ * impm_oracle.c -- plain, slow FP64 CPU oracle of the IMPM elastomer substep.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, includes or
+ * calls this file; only the test suite, the smoke check and the benchmark's CPU
+ * baseline leg load it (through ctypes).  It shares no header, helper, table or
+ * constant with the HIP path.
+ *
+ * What it computes (arXiv 2405.02914, Sec. III-A "Elastomer Simulation"):
+ *   particle-to-grid       Eq. (1)-(4)   grid mass M_i and momentum MG_i = MM_i + ME_i
+ *   boundary conditions    Eq. (5)       V_i = MG_i / M_i, boundary nodes zeroed
+ *   grid-to-particle       Eq. (6)-(7)   v_p and the affine matrix C_p
+ *   relative-rest check    Algorithm 1   repeat the exchange until the calibration
+ *                                        particle x_e moves with the object point x_o
+ *   particle movement      Eq. (8)-(9)   F_p <- (I + dt C_p) F_p,  x_p <- x_p + dt v_p
+ *
+ * Readings of the paper where it is silent or garbled (each is listed with its
+ * justification in the design notes of the repository):
+ *   - the weight w_ip is the quadratic B-spline on the 3x3x3 stencil (the 4/W^2
+ *     factor of Eq. (4) and (7) is the inverse of its inertia dx^2/4);
+ *   - Eq. (3) carries m_p on the affine term: MM_i = sum w m_p (v_p + C_p (X_i - x_p));
+ *   - X_g in Eq. (3)/(4) is the position of the summed node i; Eq. (7) sums V_g;
+ *   - S_p is the fixed-corotated Kirchhoff stress tau = 2mu (F-R) F^T + lambda J (J-1) I,
+ *     R the rotation of the polar decomposition of F (Newton iteration of Higham 1986);
+ *   - the object is a rigid kinematic collider: every grid node inside the indenter
+ *     at the start of the substep takes the rigid velocity (relative rest);
+ *   - the relative-rest test uses the tangential (x,y) velocity 2-vectors,
+ *     |v_e,t - v_o,t| <= threshold |v_o,t|, converged at once if |v_o,t| <= 1e-9 m/s;
+ *   - F and x are committed once per substep with the final pass's C and v;
+ *   - "bottom elastomer particles" are those whose rest height is below
+ *     fixed_z_fraction of the slab thickness; PLAIN mode (the paper's "normal" MPM)
+ *     does one pass and has no bottom rule.
+ *
+ * Particle initialisation draws its jitter from SplitMix64 (Steele, Lea, Flood,
+ * OOPSLA 2014) used as a counter-based generator: the t-th output of the stream
+ * seeded with s is mix(s + t * 0x9E3779B97F4A7C15).  Particle id
+ * ((k Ny + j) Nx + i) ppc + (sz m + sy) m + sx sits in cell (i,j,k), sub-cell
+ * (sx,sy,sz) of the m^3 stratification; its axis-a offset inside the cell is
+ * r_a = fl32((s_a + u) / m) with u the (3 id + a + 1)-th output's top 53 bits
+ * scaled to [0,1), and its position is (cell_a + r_a) dx.
+ *
+ * Coordinates: slab-local metres, origin at the slab's (-x,-y) bottom corner, z up.
+ * Grid node (i,j,k) sits at ((i-pl) dx, (j-pl) dx, (k-pb) dx).
+ * Compiled with -ffp-contract=off so every expression rounds as written.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---------------------------------------------------------------- params */
+
+typedef struct {
+    int32_t cells[3];
+    int32_t ppc;               /* particles per cell, a cube m^3 (1, 8, 27) */
+    double dx;
+    uint64_t seed;
+    double E, nu, rho, dt;
+    int32_t subcycle;          /* each configured substep = subcycle steps of dt/subcycle */
+    int32_t pad_lateral, pad_top, pad_bottom, band;
+    int32_t mode;              /* 0 = IMPM, 1 = PLAIN */
+    int32_t rest_limit;        /* LIMIT of Algorithm 1 */
+    double rest_threshold;     /* threshold of Algorithm 1 */
+    double fixed_z_fraction;
+    /* indenter */
+    int32_t shape;             /* 0 none, 1 sphere, 2 capsule rod, 3 rounded box */
+    int32_t _pad0;
+    double radius, half_length, half_extent[3], fillet;
+    double pose0[7];           /* position xyz (m), quaternion wxyz body->world */
+    int32_t stress_each_pass;  /* 1: every pass of the loop re-adds ME_i (literal Alg. 1) */
+    int32_t _pad1;
+} orc_params;
+
+typedef struct {
+    orc_params P;
+    int64_t n;                 /* particles */
+    int nn[3];                 /* nodes per axis */
+    int64_t n_nodes;
+    double *x, *v, *C, *F;     /* n*3, n*3, n*9, n*9 ; 3x3 row-major */
+    double *Xrest;             /* n*3 rest positions */
+    unsigned char *bottom, *surface;
+    double *M, *MG, *V;        /* n_nodes, n_nodes*3, n_nodes*3 */
+    double mu, lam, Vp, mp;
+    double pos[3], quat[4];    /* current pose */
+    double tpos[3], tquat[4];  /* target pose of the next orc_step */
+    double po_body[3];         /* x_o in the body frame */
+    int64_t e;                 /* calibration particle id */
+    int64_t substeps, steps, passes, limit_hits;
+    double last_r;
+    int32_t *forced;           /* forced pass counts (parity replay), may be NULL */
+    int64_t n_forced, forced_pos;
+    int32_t *pass_log;         /* passes of each executed step, capacity log_cap */
+    int64_t log_cap, log_len;
+    int32_t error;             /* 1: a stencil left the grid, 2: non-finite state, 3: det F <= 0 */
+} orc_sim;
+
+/* ---------------------------------------------------------------- SplitMix64 */
+
+static uint64_t sm64_mix(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+/* t-th output (t >= 1) of the SplitMix64 stream seeded with `seed`. */
+uint64_t orc_splitmix64_at(uint64_t seed, uint64_t t) {
+    return sm64_mix(seed + t * 0x9E3779B97F4A7C15ULL);
+}
+
+static double sm64_unit(uint64_t seed, uint64_t t) {
+    return (double)(orc_splitmix64_at(seed, t) >> 11) * (1.0 / 9007199254740992.0);
+}
+
+/* ---------------------------------------------------------------- 3x3 helpers */
+
+static double det3(const double *A) {
+    return A[0] * (A[4] * A[8] - A[5] * A[7])
+         - A[1] * (A[3] * A[8] - A[5] * A[6])
+         + A[2] * (A[3] * A[7] - A[4] * A[6]);
+}
+
+/* inverse transpose: A^{-T} = cof(A) / det(A) */
+static void inv_transpose3(const double *A, double *out) {
+    double d = det3(A);
+    out[0] = (A[4] * A[8] - A[5] * A[7]) / d;
+    out[1] = -(A[3] * A[8] - A[5] * A[6]) / d;
+    out[2] = (A[3] * A[7] - A[4] * A[6]) / d;
+    out[3] = -(A[1] * A[8] - A[2] * A[7]) / d;
+    out[4] = (A[0] * A[8] - A[2] * A[6]) / d;
+    out[5] = -(A[0] * A[7] - A[1] * A[6]) / d;
+    out[6] = (A[1] * A[5] - A[2] * A[4]) / d;
+    out[7] = -(A[0] * A[5] - A[2] * A[3]) / d;
+    out[8] = (A[0] * A[4] - A[1] * A[3]) / d;
+}
+
+/* Rotation factor of the polar decomposition F = R S (det F > 0):
+ * Newton iteration R <- (R + R^{-T}) / 2 from R = F (Higham 1986). */
+void orc_polar(const double *F, double *R) {
+    double X[9], Y[9];
+    memcpy(X, F, sizeof(X));
+    for (int it = 0; it < 100; ++it) {
+        inv_transpose3(X, Y);
+        double diff = 0.0, nrm = 0.0;
+        for (int k = 0; k < 9; ++k) {
+            double nx = 0.5 * (X[k] + Y[k]);
+            diff += (nx - X[k]) * (nx - X[k]);
+            nrm += nx * nx;
+            X[k] = nx;
+        }
+        if (diff <= 1e-30 * nrm) break;
+    }
+    memcpy(R, X, sizeof(X));
+}
+
+/* Fixed-corotated Kirchhoff stress tau = 2 mu (F - R) F^T + lambda J (J - 1) I. */
+void orc_kirchhoff(const double *F, double mu, double lam, double *tau) {
+    double R[9];
+    orc_polar(F, R);
+    double J = det3(F);
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double s = 0.0;
+            for (int c = 0; c < 3; ++c) s += (F[3 * a + c] - R[3 * a + c]) * F[3 * b + c];
+            tau[3 * a + b] = 2.0 * mu * s + (a == b ? lam * J * (J - 1.0) : 0.0);
+        }
+}
+
+/* Elastic energy density of the fixed-corotated model:
+ * psi = mu |F - R|^2 + lambda/2 (J - 1)^2. */
+static double energy_density(const double *F, double mu, double lam) {
+    double R[9];
+    orc_polar(F, R);
+    double s = 0.0;
+    for (int k = 0; k < 9; ++k) s += (F[k] - R[k]) * (F[k] - R[k]);
+    double J = det3(F);
+    return mu * s + 0.5 * lam * (J - 1.0) * (J - 1.0);
+}
+
+/* ---------------------------------------------------------------- quaternions */
+
+static void quat_mul(const double *a, const double *b, double *o) {
+    double w = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+    double x = a[0] * b[1] + a[1] * b[0] + a[2] * b[3] - a[3] * b[2];
+    double y = a[0] * b[2] - a[1] * b[3] + a[2] * b[0] + a[3] * b[1];
+    double z = a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0];
+    o[0] = w; o[1] = x; o[2] = y; o[3] = z;
+}
+
+static void quat_to_matrix(const double *q, double *R) {
+    double w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0] = 1.0 - 2.0 * (y * y + z * z); R[1] = 2.0 * (x * y - w * z);       R[2] = 2.0 * (x * z + w * y);
+    R[3] = 2.0 * (x * y + w * z);       R[4] = 1.0 - 2.0 * (x * x + z * z); R[5] = 2.0 * (y * z - w * x);
+    R[6] = 2.0 * (x * z - w * y);       R[7] = 2.0 * (y * z + w * x);       R[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+static void quat_normalize(double *q) {
+    double s = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    for (int k = 0; k < 4; ++k) q[k] /= s;
+}
+
+/* Relative rotation from q0 to q1 as (unit axis, angle in [0, pi]). */
+static void quat_rel_axis_angle(const double *q0, const double *q1, double *axis, double *angle) {
+    double q0c[4] = {q0[0], -q0[1], -q0[2], -q0[3]};
+    double r[4];
+    quat_mul(q1, q0c, r);
+    if (r[0] < 0.0) { r[0] = -r[0]; r[1] = -r[1]; r[2] = -r[2]; r[3] = -r[3]; }
+    double s = sqrt(r[1] * r[1] + r[2] * r[2] + r[3] * r[3]);
+    if (s <= 0.0) { axis[0] = 0.0; axis[1] = 0.0; axis[2] = 1.0; *angle = 0.0; return; }
+    axis[0] = r[1] / s; axis[1] = r[2] / s; axis[2] = r[3] / s;
+    *angle = 2.0 * atan2(s, r[0]);
+}
+
+/* ---------------------------------------------------------------- indenter */
+
+/* Signed-distance-like inside test in the body frame (phi <= 0 is inside). */
+static double body_phi(const orc_params *P, const double *p) {
+    if (P->shape == 1) {
+        return p[0] * p[0] + p[1] * p[1] + p[2] * p[2] - P->radius * P->radius;
+    } else if (P->shape == 2) {
+        double h = P->half_length;
+        double t = p[0] < -h ? -h : (p[0] > h ? h : p[0]);
+        double qx = p[0] - t;
+        return qx * qx + p[1] * p[1] + p[2] * p[2] - P->radius * P->radius;
+    } else if (P->shape == 3) {
+        double q[3], out2 = 0.0, inmax = -1e300;
+        for (int a = 0; a < 3; ++a) {
+            q[a] = fabs(p[a]) - (P->half_extent[a] - P->fillet);
+            double qp = q[a] > 0.0 ? q[a] : 0.0;
+            out2 += qp * qp;
+            if (q[a] > inmax) inmax = q[a];
+        }
+        double inside_part = inmax < 0.0 ? inmax : 0.0;
+        return sqrt(out2) + inside_part - P->fillet;
+    }
+    return 1.0; /* no indenter */
+}
+
+/* Body-frame lowest point of the indenter, ties broken towards the point
+ * farthest from the body z axis, then the lexicographic minimum of (x, y). */
+static void body_lowest_point(const orc_params *P, double *p) {
+    p[0] = 0.0; p[1] = 0.0; p[2] = 0.0;
+    if (P->shape == 1) { p[2] = -P->radius; }
+    else if (P->shape == 2) { p[0] = -P->half_length; p[2] = -P->radius; }
+    else if (P->shape == 3) {
+        p[0] = -(P->half_extent[0] - P->fillet);
+        p[1] = -(P->half_extent[1] - P->fillet);
+        p[2] = -P->half_extent[2];
+    }
+}
+
+/* Pose of the indenter for one executed step: centre c, rotation R (body->world),
+ * rigid translational velocity vo and angular velocity w over the step. */
+typedef struct { double c[3], R[9], vo[3], w[3]; } step_pose;
+
+static void make_step_pose(const orc_sim *s, int64_t j, int64_t N, double h, step_pose *sp) {
+    double frac = (double)j / (double)N;
+    for (int a = 0; a < 3; ++a) {
+        double d = s->tpos[a] - s->pos[a];
+        sp->c[a] = s->pos[a] + d * frac;
+        sp->vo[a] = d / ((double)N * h);
+    }
+    double axis[3], ang;
+    quat_rel_axis_angle(s->quat, s->tquat, axis, &ang);
+    double half = 0.5 * ang * frac;
+    double qs[4] = {cos(half), axis[0] * sin(half), axis[1] * sin(half), axis[2] * sin(half)};
+    double qj[4];
+    quat_mul(qs, s->quat, qj);
+    quat_to_matrix(qj, sp->R);
+    for (int a = 0; a < 3; ++a) sp->w[a] = axis[a] * ang / ((double)N * h);
+}
+
+static int node_inside(const orc_sim *s, const step_pose *sp, const double *X) {
+    if (s->P.shape == 0) return 0;
+    double d[3] = {X[0] - sp->c[0], X[1] - sp->c[1], X[2] - sp->c[2]};
+    double p[3];
+    for (int a = 0; a < 3; ++a) p[a] = sp->R[a] * d[0] + sp->R[3 + a] * d[1] + sp->R[6 + a] * d[2];
+    return body_phi(&s->P, p) <= 0.0;
+}
+
+static void rigid_velocity(const step_pose *sp, const double *X, double *out) {
+    double r[3] = {X[0] - sp->c[0], X[1] - sp->c[1], X[2] - sp->c[2]};
+    out[0] = sp->vo[0] + (sp->w[1] * r[2] - sp->w[2] * r[1]);
+    out[1] = sp->vo[1] + (sp->w[2] * r[0] - sp->w[0] * r[2]);
+    out[2] = sp->vo[2] + (sp->w[0] * r[1] - sp->w[1] * r[0]);
+}
+
+/* ---------------------------------------------------------------- grid geometry */
+
+static void node_pos(const orc_sim *s, int i, int j, int k, double *X) {
+    X[0] = (double)(i - s->P.pad_lateral) * s->P.dx;
+    X[1] = (double)(j - s->P.pad_lateral) * s->P.dx;
+    X[2] = (double)(k - s->P.pad_bottom) * s->P.dx;
+}
+
+static int is_boundary_node(const orc_sim *s, int i, int j, int k) {
+    int b = s->P.band;
+    if (i < b || i > s->nn[0] - 1 - b) return 1;
+    if (j < b || j > s->nn[1] - 1 - b) return 1;
+    if (k > s->nn[2] - 1 - b) return 1;
+    if (k <= s->P.pad_bottom) return 1;   /* the slab's bottom face is fixed */
+    return 0;
+}
+
+/* Quadratic B-spline stencil of a particle: base node and the 3 weights per axis. */
+static void stencil(const orc_sim *s, const double *xp, int *base, double w[3][3]) {
+    double off[3] = {(double)s->P.pad_lateral, (double)s->P.pad_lateral, (double)s->P.pad_bottom};
+    for (int a = 0; a < 3; ++a) {
+        double xg = xp[a] / s->P.dx + off[a];
+        int b = (int)floor(xg - 0.5);
+        double f = xg - (double)b;
+        base[a] = b;
+        w[a][0] = 0.5 * (1.5 - f) * (1.5 - f);
+        w[a][1] = 0.75 - (f - 1.0) * (f - 1.0);
+        w[a][2] = 0.5 * (f - 0.5) * (f - 0.5);
+    }
+}
+
+static int64_t node_index(const orc_sim *s, int i, int j, int k) {
+    return ((int64_t)k * s->nn[1] + j) * s->nn[0] + i;
+}
+
+/* ---------------------------------------------------------------- creation */
+
+static int cube_root_ppc(int ppc) {
+    for (int m = 1; m <= 8; ++m) if (m * m * m == ppc) return m;
+    return -1;
+}
+
+void orc_destroy(orc_sim *s) {
+    if (!s) return;
+    free(s->x); free(s->v); free(s->C); free(s->F); free(s->Xrest);
+    free(s->bottom); free(s->surface); free(s->M); free(s->MG); free(s->V);
+    free(s->forced); free(s->pass_log);
+    free(s);
+}
+
+orc_sim *orc_create(const orc_params *P) {
+    int m = cube_root_ppc(P->ppc);
+    if (m < 1 || P->cells[0] < 1 || P->cells[1] < 1 || P->cells[2] < 1 || !(P->dx > 0.0)) return NULL;
+    orc_sim *s = (orc_sim *)calloc(1, sizeof(orc_sim));
+    s->P = *P;
+    int Nx = P->cells[0], Ny = P->cells[1], Nz = P->cells[2];
+    s->n = (int64_t)Nx * Ny * Nz * P->ppc;
+    s->nn[0] = Nx + 2 * P->pad_lateral + 1;
+    s->nn[1] = Ny + 2 * P->pad_lateral + 1;
+    s->nn[2] = Nz + P->pad_bottom + P->pad_top + 1;
+    s->n_nodes = (int64_t)s->nn[0] * s->nn[1] * s->nn[2];
+    s->x = (double *)calloc(s->n * 3, sizeof(double));
+    s->v = (double *)calloc(s->n * 3, sizeof(double));
+    s->C = (double *)calloc(s->n * 9, sizeof(double));
+    s->F = (double *)calloc(s->n * 9, sizeof(double));
+    s->Xrest = (double *)calloc(s->n * 3, sizeof(double));
+    s->bottom = (unsigned char *)calloc(s->n, 1);
+    s->surface = (unsigned char *)calloc(s->n, 1);
+    s->M = (double *)calloc(s->n_nodes, sizeof(double));
+    s->MG = (double *)calloc(s->n_nodes * 3, sizeof(double));
+    s->V = (double *)calloc(s->n_nodes * 3, sizeof(double));
+    s->mu = P->E / (2.0 * (1.0 + P->nu));
+    s->lam = P->E * P->nu / ((1.0 + P->nu) * (1.0 - 2.0 * P->nu));
+    s->Vp = P->dx * P->dx * P->dx / (double)P->ppc;
+    s->mp = P->rho * s->Vp;
+    double H = (double)Nz * P->dx;
+
+    /* stratified jitter: m^3 sub-cells per cell, one particle uniform in each */
+    for (int k = 0; k < Nz; ++k)
+        for (int j = 0; j < Ny; ++j)
+            for (int i = 0; i < Nx; ++i)
+                for (int sz = 0; sz < m; ++sz)
+                    for (int sy = 0; sy < m; ++sy)
+                        for (int sx = 0; sx < m; ++sx) {
+                            int64_t cell = ((int64_t)k * Ny + j) * Nx + i;
+                            int64_t id = cell * P->ppc + (sz * m + sy) * m + sx;
+                            int cidx[3] = {i, j, k}, sidx[3] = {sx, sy, sz};
+                            for (int a = 0; a < 3; ++a) {
+                                /* in-cell offset r in [0,1), rounded to FP32 so that the
+                                 * start state is exactly representable on an FP32 device */
+                                double u = sm64_unit(P->seed, (uint64_t)(3 * id + a + 1));
+                                float r = (float)(((double)sidx[a] + u) / (double)m);
+                                double xa = ((double)cidx[a] + (double)r) * P->dx;
+                                s->x[3 * id + a] = xa;
+                                s->Xrest[3 * id + a] = xa;
+                            }
+                            s->F[9 * id + 0] = 1.0; s->F[9 * id + 4] = 1.0; s->F[9 * id + 8] = 1.0;
+                            s->bottom[id] = s->Xrest[3 * id + 2] < P->fixed_z_fraction * H;
+                            s->surface[id] = (k == Nz - 1 && sz == m - 1);
+                        }
+
+    memcpy(s->pos, P->pose0, 3 * sizeof(double));
+    memcpy(s->quat, P->pose0 + 3, 4 * sizeof(double));
+    quat_normalize(s->quat);
+    memcpy(s->tpos, s->pos, sizeof(s->pos));
+    memcpy(s->tquat, s->quat, sizeof(s->quat));
+
+    /* calibration points: x_o the body-fixed lowest point, x_e the nearest particle */
+    body_lowest_point(P, s->po_body);
+    double Rq[9], xo[3];
+    quat_to_matrix(s->quat, Rq);
+    for (int a = 0; a < 3; ++a)
+        xo[a] = s->pos[a] + Rq[3 * a] * s->po_body[0] + Rq[3 * a + 1] * s->po_body[1] + Rq[3 * a + 2] * s->po_body[2];
+    double best = 1e300;
+    s->e = 0;
+    for (int64_t p = 0; p < s->n; ++p) {
+        double d0 = s->x[3 * p] - xo[0], d1 = s->x[3 * p + 1] - xo[1], d2 = s->x[3 * p + 2] - xo[2];
+        double d = d0 * d0 + d1 * d1 + d2 * d2;
+        if (d < best) { best = d; s->e = p; }
+    }
+    return s;
+}
+
+/* ---------------------------------------------------------------- one exchange */
+
+/* Particle-to-grid, Eq. (1)-(4). h is the executed step length; with_stress = 0
+ * drops the elastic momentum ME_i (Eq. 4) and transfers MM_i alone. */
+static void p2g_ex(orc_sim *s, double h, int with_stress) {
+    memset(s->M, 0, s->n_nodes * sizeof(double));
+    memset(s->MG, 0, s->n_nodes * 3 * sizeof(double));
+    const double dx = s->P.dx;
+    const double coef = -4.0 * h / (dx * dx);
+    for (int64_t p = 0; p < s->n; ++p) {
+        const double *xp = s->x + 3 * p, *vp = s->v + 3 * p, *Cp = s->C + 9 * p, *Fp = s->F + 9 * p;
+        int base[3];
+        double w[3][3];
+        stencil(s, xp, base, w);
+        double tau[9], A[9];
+        if (with_stress) orc_kirchhoff(Fp, s->mu, s->lam, tau);
+        for (int k = 0; k < 9; ++k) A[k] = (with_stress ? coef * s->Vp * tau[k] : 0.0) + s->mp * Cp[k];
+        for (int c = 0; c < 3; ++c)
+            for (int b = 0; b < 3; ++b)
+                for (int a = 0; a < 3; ++a) {
+                    int i = base[0] + a, j = base[1] + b, k = base[2] + c;
+                    double X[3];
+                    node_pos(s, i, j, k, X);
+                    double d[3] = {X[0] - xp[0], X[1] - xp[1], X[2] - xp[2]};
+                    double wt = w[0][a] * w[1][b] * w[2][c];
+                    int64_t ni = node_index(s, i, j, k);
+                    s->M[ni] += wt * s->mp;
+                    for (int r = 0; r < 3; ++r)
+                        s->MG[3 * ni + r] += wt * (s->mp * vp[r] + (A[3 * r] * d[0] + A[3 * r + 1] * d[1] + A[3 * r + 2] * d[2]));
+                }
+    }
+}
+
+void orc_p2g(orc_sim *s, double h) { p2g_ex(s, h, 1); }
+
+/* Grid velocity, Eq. (5); relative-rest contact with the rigid indenter; zero
+ * velocity on boundary nodes.  Flags let the invariant tests switch parts off. */
+void orc_grid_update_ex(orc_sim *s, const step_pose *sp, int use_contact, int use_bc) {
+    for (int k = 0; k < s->nn[2]; ++k)
+        for (int j = 0; j < s->nn[1]; ++j)
+            for (int i = 0; i < s->nn[0]; ++i) {
+                int64_t ni = node_index(s, i, j, k);
+                double *V = s->V + 3 * ni;
+                if (s->M[ni] > 0.0) {
+                    for (int r = 0; r < 3; ++r) V[r] = s->MG[3 * ni + r] / s->M[ni];
+                } else {
+                    V[0] = V[1] = V[2] = 0.0;
+                }
+                if (use_contact && sp) {
+                    double X[3];
+                    node_pos(s, i, j, k, X);
+                    if (node_inside(s, sp, X)) rigid_velocity(sp, X, V);
+                }
+                if (use_bc && is_boundary_node(s, i, j, k)) V[0] = V[1] = V[2] = 0.0;
+            }
+}
+
+/* Grid-to-particle, Eq. (6)-(7), with the bottom rule of the relative-rest step. */
+void orc_g2p_ex(orc_sim *s, int bottom_rule) {
+    const double dx = s->P.dx;
+    const double cc = 4.0 / (dx * dx);
+    for (int64_t p = 0; p < s->n; ++p) {
+        const double *xp = s->x + 3 * p;
+        int base[3];
+        double w[3][3];
+        stencil(s, xp, base, w);
+        double vn[3] = {0, 0, 0}, Cn[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (int c = 0; c < 3; ++c)
+            for (int b = 0; b < 3; ++b)
+                for (int a = 0; a < 3; ++a) {
+                    int i = base[0] + a, j = base[1] + b, k = base[2] + c;
+                    double X[3];
+                    node_pos(s, i, j, k, X);
+                    double d[3] = {X[0] - xp[0], X[1] - xp[1], X[2] - xp[2]};
+                    double wt = w[0][a] * w[1][b] * w[2][c];
+                    const double *V = s->V + 3 * node_index(s, i, j, k);
+                    for (int r = 0; r < 3; ++r) {
+                        vn[r] += wt * V[r];
+                        for (int q = 0; q < 3; ++q) Cn[3 * r + q] += cc * wt * V[r] * d[q];
+                    }
+                }
+        if (bottom_rule && s->bottom[p]) vn[2] = 0.0;
+        memcpy(s->v + 3 * p, vn, sizeof(vn));
+        memcpy(s->C + 9 * p, Cn, sizeof(Cn));
+    }
+}
+
+/* Particle movement, Eq. (8)-(9). */
+void orc_commit(orc_sim *s, double h) {
+    for (int64_t p = 0; p < s->n; ++p) {
+        double *Fp = s->F + 9 * p, *Cp = s->C + 9 * p;
+        double Fn[9];
+        for (int r = 0; r < 3; ++r)
+            for (int q = 0; q < 3; ++q) {
+                double acc = Fp[3 * r + q];
+                for (int t = 0; t < 3; ++t) acc += h * Cp[3 * r + t] * Fp[3 * t + q];
+                Fn[3 * r + q] = acc;
+            }
+        memcpy(Fp, Fn, sizeof(Fn));
+        for (int a = 0; a < 3; ++a) s->x[3 * p + a] += h * s->v[3 * p + a];
+    }
+}
+
+/* Velocity the grid gives the calibration particle (its G2P velocity). */
+static void gather_velocity(const orc_sim *s, const double *xp, double *out) {
+    int base[3];
+    double w[3][3];
+    stencil(s, xp, base, w);
+    out[0] = out[1] = out[2] = 0.0;
+    for (int c = 0; c < 3; ++c)
+        for (int b = 0; b < 3; ++b)
+            for (int a = 0; a < 3; ++a) {
+                const double *V = s->V + 3 * node_index(s, base[0] + a, base[1] + b, base[2] + c);
+                double wt = w[0][a] * w[1][b] * w[2][c];
+                for (int r = 0; r < 3; ++r) out[r] += wt * V[r];
+            }
+}
+
+/* ---------------------------------------------------------------- Algorithm 1 */
+
+/* Every particle's stencil inside the grid, its state finite and det F > 0. */
+static int check_state(orc_sim *s) {
+    double off[3] = {(double)s->P.pad_lateral, (double)s->P.pad_lateral, (double)s->P.pad_bottom};
+    for (int64_t p = 0; p < s->n; ++p) {
+        for (int a = 0; a < 3; ++a) {
+            double xg = s->x[3 * p + a] / s->P.dx + off[a];
+            if (!isfinite(xg) || !isfinite(s->v[3 * p + a])) return 2;
+            double b = floor(xg - 0.5);
+            if (b < 0.0 || b + 2.0 > (double)(s->nn[a] - 1)) return 1;
+        }
+        for (int k = 0; k < 9; ++k)
+            if (!isfinite(s->C[9 * p + k]) || !isfinite(s->F[9 * p + k])) return 2;
+        if (!(det3(s->F + 9 * p) > 0.0)) return 3;
+    }
+    return 0;
+}
+
+/* One executed step (index j of N in the current orc_step call, length h). */
+static void impm_step(orc_sim *s, int64_t j, int64_t N, double h) {
+    step_pose sp;
+    make_step_pose(s, j, N, h, &sp);
+    /* object calibration point and its tangential velocity */
+    double xo[3], vo_at[3];
+    for (int a = 0; a < 3; ++a)
+        xo[a] = sp.c[a] + sp.R[3 * a] * s->po_body[0] + sp.R[3 * a + 1] * s->po_body[1] + sp.R[3 * a + 2] * s->po_body[2];
+    rigid_velocity(&sp, xo, vo_at);
+    double gnorm = sqrt(vo_at[0] * vo_at[0] + vo_at[1] * vo_at[1]);
+
+    int plain = s->P.mode == 1;
+    int forced = -1;
+    if (s->forced && s->forced_pos < s->n_forced) forced = s->forced[s->forced_pos++];
+
+    int cnt = 0;
+    for (;;) {
+        /* The elastic impulse of the step enters the first exchange; later passes
+         * only re-exchange momentum so that the velocity field relaxes towards the
+         * object's (unless the literal every-pass variant is asked for). */
+        p2g_ex(s, h, cnt == 0 || s->P.stress_each_pass);
+        orc_grid_update_ex(s, &sp, 1, 1);
+        /* relative-rest test on the calibration particle, before its G2P */
+        double ve[3];
+        gather_velocity(s, s->x + 3 * s->e, ve);
+        orc_g2p_ex(s, !plain);
+        cnt += 1;
+        int stop;
+        if (forced > 0) {
+            stop = cnt >= forced;
+        } else if (plain) {
+            stop = 1;
+        } else if (gnorm <= 1e-9) {
+            stop = 1;
+            s->last_r = 0.0;
+        } else {
+            double dvx = ve[0] - vo_at[0], dvy = ve[1] - vo_at[1];
+            double r = sqrt(dvx * dvx + dvy * dvy) / gnorm;
+            s->last_r = r;
+            stop = r <= s->P.rest_threshold;
+            if (!stop && cnt >= s->P.rest_limit) { stop = 1; s->limit_hits += 1; }
+        }
+        if (stop) break;
+    }
+    s->passes += cnt;
+    if (s->pass_log && s->log_len < s->log_cap) s->pass_log[s->log_len++] = cnt;
+    orc_commit(s, h);
+    s->steps += 1;
+}
+
+void orc_set_target_pose(orc_sim *s, const double *pos, const double *quat) {
+    memcpy(s->tpos, pos, 3 * sizeof(double));
+    memcpy(s->tquat, quat, 4 * sizeof(double));
+    quat_normalize(s->tquat);
+}
+
+/* Advance n configured substeps (each = subcycle executed steps), moving the
+ * indenter from the current pose to the target pose at constant velocity. */
+int orc_step(orc_sim *s, int32_t n_substeps) {
+    if (n_substeps <= 0) return -1;
+    int k = s->P.subcycle > 0 ? s->P.subcycle : 1;
+    int64_t N = (int64_t)n_substeps * k;
+    double h = s->P.dt / (double)k;
+    for (int64_t j = 0; j < N; ++j) {
+        if (s->error || (s->error = check_state(s)) != 0) return -2;
+        impm_step(s, j, N, h);
+    }
+    memcpy(s->pos, s->tpos, sizeof(s->pos));
+    memcpy(s->quat, s->tquat, sizeof(s->quat));
+    s->substeps += n_substeps;
+    return 0;
+}
+
+/* ---------------------------------------------------------------- accessors */
+
+int64_t orc_num_particles(const orc_sim *s) { return s->n; }
+int32_t orc_error(const orc_sim *s) { return s->error; }
+int64_t orc_calib_particle(const orc_sim *s) { return s->e; }
+void orc_grid_dims(const orc_sim *s, int32_t *out) { out[0] = s->nn[0]; out[1] = s->nn[1]; out[2] = s->nn[2]; }
+
+void orc_get_state(const orc_sim *s, double *x, double *v, double *C, double *F) {
+    if (x) memcpy(x, s->x, s->n * 3 * sizeof(double));
+    if (v) memcpy(v, s->v, s->n * 3 * sizeof(double));
+    if (C) memcpy(C, s->C, s->n * 9 * sizeof(double));
+    if (F) memcpy(F, s->F, s->n * 9 * sizeof(double));
+}
+
+void orc_set_state(orc_sim *s, const double *x, const double *v, const double *C, const double *F) {
+    if (x) memcpy(s->x, x, s->n * 3 * sizeof(double));
+    if (v) memcpy(s->v, v, s->n * 3 * sizeof(double));
+    if (C) memcpy(s->C, C, s->n * 9 * sizeof(double));
+    if (F) memcpy(s->F, F, s->n * 9 * sizeof(double));
+}
+
+void orc_get_rest(const orc_sim *s, double *Xrest, unsigned char *bottom, unsigned char *surface) {
+    if (Xrest) memcpy(Xrest, s->Xrest, s->n * 3 * sizeof(double));
+    if (bottom) memcpy(bottom, s->bottom, s->n);
+    if (surface) memcpy(surface, s->surface, s->n);
+}
+
+void orc_get_grid(const orc_sim *s, double *M, double *MG, double *V) {
+    if (M) memcpy(M, s->M, s->n_nodes * sizeof(double));
+    if (MG) memcpy(MG, s->MG, s->n_nodes * 3 * sizeof(double));
+    if (V) memcpy(V, s->V, s->n_nodes * 3 * sizeof(double));
+}
+
+void orc_get_counters(const orc_sim *s, int64_t *out4, double *last_r) {
+    out4[0] = s->substeps; out4[1] = s->steps; out4[2] = s->passes; out4[3] = s->limit_hits;
+    if (last_r) *last_r = s->last_r;
+}
+
+void orc_get_pose(const orc_sim *s, double *pose7) {
+    memcpy(pose7, s->pos, 3 * sizeof(double));
+    memcpy(pose7 + 3, s->quat, 4 * sizeof(double));
+}
+
+/* x_o at the current pose */
+void orc_get_xo(const orc_sim *s, double *xo) {
+    double R[9];
+    quat_to_matrix(s->quat, R);
+    for (int a = 0; a < 3; ++a)
+        xo[a] = s->pos[a] + R[3 * a] * s->po_body[0] + R[3 * a + 1] * s->po_body[1] + R[3 * a + 2] * s->po_body[2];
+}
+
+void orc_force_passes(orc_sim *s, const int32_t *passes, int64_t n) {
+    free(s->forced);
+    s->forced = NULL; s->n_forced = 0; s->forced_pos = 0;
+    if (n > 0) {
+        s->forced = (int32_t *)malloc(n * sizeof(int32_t));
+        memcpy(s->forced, passes, n * sizeof(int32_t));
+        s->n_forced = n;
+    }
+}
+
+void orc_enable_pass_log(orc_sim *s, int64_t cap) {
+    free(s->pass_log);
+    s->pass_log = cap > 0 ? (int32_t *)calloc(cap, sizeof(int32_t)) : NULL;
+    s->log_cap = cap; s->log_len = 0;
+}
+
+int64_t orc_get_pass_log(const orc_sim *s, int32_t *out, int64_t cap) {
+    int64_t n = s->log_len < cap ? s->log_len : cap;
+    if (n > 0) memcpy(out, s->pass_log, n * sizeof(int32_t));
+    return s->log_len;
+}
+
+/* Phase entry points for the invariant tests: one exchange with optional parts.
+ * A NULL pose disables the contact rule. */
+void orc_phase_p2g(orc_sim *s, double h) { orc_p2g(s, h); }
+void orc_phase_p2g_momentum(orc_sim *s) { p2g_ex(s, 0.0, 0); }
+void orc_phase_grid(orc_sim *s, int use_contact, int use_bc) {
+    step_pose sp;
+    make_step_pose(s, 0, 1, s->P.dt, &sp);
+    orc_grid_update_ex(s, &sp, use_contact, use_bc);
+}
+void orc_phase_g2p(orc_sim *s, int bottom_rule) { orc_g2p_ex(s, bottom_rule); }
+void orc_phase_commit(orc_sim *s, double h) { orc_commit(s, h); }
+
+/* Node inside-mask at the start of a 1-step move to the target pose. */
+void orc_inside_mask(const orc_sim *s, unsigned char *mask) {
+    step_pose sp;
+    make_step_pose(s, 0, 1, s->P.dt, &sp);
+    for (int k = 0; k < s->nn[2]; ++k)
+        for (int j = 0; j < s->nn[1]; ++j)
+            for (int i = 0; i < s->nn[0]; ++i) {
+                double X[3];
+                node_pos(s, i, j, k, X);
+                mask[node_index(s, i, j, k)] = (unsigned char)node_inside(s, &sp, X);
+            }
+}
+
+/* Total energy: kinetic + fixed-corotated elastic. */
+double orc_energy(const orc_sim *s) {
+    double ek = 0.0, ee = 0.0;
+    for (int64_t p = 0; p < s->n; ++p) {
+        const double *v = s->v + 3 * p;
+        ek += 0.5 * s->mp * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        ee += s->Vp * energy_density(s->F + 9 * p, s->mu, s->lam);
+    }
+    return ek + ee;
+}
+
+/* ---------------------------------------------------------------- surface maps */
+
+static double bspline2(double t) {
+    double a = fabs(t);
+    if (a < 0.5) return 0.75 - a * a;
+    if (a < 1.5) return 0.5 * (1.5 - a) * (1.5 - a);
+    return 0.0;
+}
+
+/* Surface displacement field: at pixel centres ((u+1/2) L/W, (v+1/2) L/H) the
+ * Shepard-normalised 2-D quadratic B-spline average (pitch = pixel size) of the
+ * surface particles' displacement x - X_rest.  Out is H x W x 3 (row v, column u);
+ * pixels without weight get 0. */
+void orc_surface_displacement(const orc_sim *s, double *out, int W, int H) {
+    double Lx = (double)s->P.cells[0] * s->P.dx, Ly = (double)s->P.cells[1] * s->P.dx;
+    double px = Lx / (double)W, py = Ly / (double)H;
+    double *acc = (double *)calloc((size_t)W * H * 4, sizeof(double));
+    for (int64_t p = 0; p < s->n; ++p) {
+        if (!s->surface[p]) continue;
+        const double *xp = s->x + 3 * p, *X0 = s->Xrest + 3 * p;
+        for (int v = 0; v < H; ++v) {
+            double wy = bspline2((xp[1] - ((double)v + 0.5) * py) / py);
+            if (wy == 0.0) continue;
+            for (int u = 0; u < W; ++u) {
+                double wx = bspline2((xp[0] - ((double)u + 0.5) * px) / px);
+                if (wx == 0.0) continue;
+                double wt = wx * wy;
+                double *a = acc + 4 * ((size_t)v * W + u);
+                a[0] += wt;
+                for (int r = 0; r < 3; ++r) a[1 + r] += wt * (xp[r] - X0[r]);
+            }
+        }
+    }
+    for (size_t q = 0; q < (size_t)W * H; ++q)
+        for (int r = 0; r < 3; ++r)
+            out[3 * q + r] = acc[4 * q] > 0.0 ? acc[4 * q + 1 + r] / acc[4 * q] : 0.0;
+    free(acc);
+}
+
+/* Height map h = H_slab + u_z (row v, column u). */
+void orc_surface_heightmap(const orc_sim *s, double *out, int W, int H) {
+    double *d = (double *)calloc((size_t)W * H * 3, sizeof(double));
+    orc_surface_displacement(s, d, W, H);
+    double top = (double)s->P.cells[2] * s->P.dx;
+    for (size_t q = 0; q < (size_t)W * H; ++q) out[q] = top + d[3 * q + 2];
+    free(d);
+}

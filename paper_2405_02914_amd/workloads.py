@@ -1,0 +1,190 @@
+"""Seeded synthetic workloads: sensor parameters, indenter motion schedules and
+random particle states.
+
+This module is the only one that the oracle side and the HIP side both use.  It
+holds input recipes (sizes, material constants, poses, random numbers) and none
+of the method's arithmetic.
+
+Units are SI (m, s, kg, Pa).  Coordinates are slab-local: the origin is the
+slab's (-x, -y) bottom corner and z points up.  Quaternions are body->world,
+(w, x, y, z).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+SHAPE_NONE, SHAPE_SPHERE, SHAPE_CAPSULE, SHAPE_BOX = 0, 1, 2, 3
+MODE_IMPM, MODE_PLAIN = 0, 1
+
+
+@dataclasses.dataclass
+class SensorParams:
+    """One elastomer slab, its background grid, material and indenter."""
+    cells: tuple = (32, 32, 8)        # slab cells per axis
+    dx: float = 0.5e-3                # grid spacing (m)
+    ppc: int = 8                      # particles per cell (a cube: 1, 8, 27)
+    seed: int = 2405
+    E: float = 3.0e5                  # Young's modulus (Pa)
+    nu: float = 0.45                  # Poisson's ratio
+    rho: float = 1000.0               # density (kg/m^3)
+    dt: float = 2.0e-5                # configured substep (s)
+    subcycle: int = 1                 # executed steps per configured substep
+    pad_lateral: int = 4              # empty cells beside the slab
+    pad_top: int = 4                  # empty cells above the slab
+    pad_bottom: int = 2               # cells below the slab's bottom face
+    band: int = 2                     # boundary band of zero-velocity nodes
+    mode: int = MODE_IMPM
+    rest_limit: int = 10              # LIMIT of the IMPM loop
+    rest_threshold: float = 0.5       # threshold of the relative-rest test
+    fixed_z_fraction: float = 0.5     # "lower half layer" whose z velocity is zeroed
+    shape: int = SHAPE_SPHERE
+    radius: float = 4.0e-3
+    half_length: float = 0.0
+    half_extent: tuple = (0.0, 0.0, 0.0)
+    fillet: float = 0.0
+    pose0: tuple = (8.0e-3, 8.0e-3, 8.0e-3, 1.0, 0.0, 0.0, 0.0)
+    stress_each_pass: int = 0         # 1: every IMPM pass re-adds the elastic impulse
+
+    @property
+    def n_particles(self) -> int:
+        return self.cells[0] * self.cells[1] * self.cells[2] * self.ppc
+
+    @property
+    def nodes(self) -> tuple:
+        return (self.cells[0] + 2 * self.pad_lateral + 1,
+                self.cells[1] + 2 * self.pad_lateral + 1,
+                self.cells[2] + self.pad_bottom + self.pad_top + 1)
+
+    @property
+    def height(self) -> float:
+        return self.cells[2] * self.dx
+
+    @property
+    def lengths(self) -> tuple:
+        return tuple(c * self.dx for c in self.cells)
+
+    def replace(self, **kw) -> "SensorParams":
+        return dataclasses.replace(self, **kw)
+
+
+def padding_for(dx: float) -> int:
+    """Lateral and top padding in cells: at least 4 cells and at least 2 mm."""
+    return max(4, int(math.ceil(2.0e-3 / dx - 1e-9)))
+
+
+def quat_about_z(deg: float) -> tuple:
+    h = math.radians(deg) * 0.5
+    return (math.cos(h), 0.0, 0.0, math.sin(h))
+
+
+def config1(subcycle: int = 1, **kw) -> SensorParams:
+    """Single sensor: slab 16x16x4 mm, grid 32x32x8 (dx 0.5 mm), 65,536 particles,
+    sphere r = 4 mm whose lowest point starts on the slab's top surface over the centre."""
+    dx = 0.5e-3
+    pad = padding_for(dx)
+    p = SensorParams(cells=(32, 32, 8), dx=dx, pad_lateral=pad, pad_top=pad,
+                     shape=SHAPE_SPHERE, radius=4.0e-3,
+                     pose0=(8.0e-3, 8.0e-3, 4.0e-3 + 4.0e-3, 1.0, 0.0, 0.0, 0.0),
+                     subcycle=subcycle)
+    return p.replace(**kw) if kw else p
+
+
+def config1_schedule(n_substeps: int = 100, depth: float = 1.0e-3):
+    """Press the sphere `depth` straight down at constant speed over n substeps.
+    Returns a list of (n_substeps, target_pos, target_quat) segments."""
+    p = config1()
+    x, y, z = p.pose0[:3]
+    return [(n_substeps, (x, y, z - depth), (1.0, 0.0, 0.0, 0.0))]
+
+
+def config2(subcycle: int = 1, **kw) -> SensorParams:
+    """Full sensor resolution: slab 32x32x8 mm on a 128x128x32 grid (dx 0.25 mm),
+    4,194,304 particles; capsule rod r = 3 mm (straight half-length 6 mm along
+    body x) lying over the centre with its lowest line on the top surface."""
+    dx = 0.25e-3
+    pad = padding_for(dx)
+    p = SensorParams(cells=(128, 128, 32), dx=dx, pad_lateral=pad, pad_top=pad,
+                     shape=SHAPE_CAPSULE, radius=3.0e-3, half_length=6.0e-3,
+                     pose0=(16.0e-3, 16.0e-3, 8.0e-3 + 3.0e-3, 1.0, 0.0, 0.0, 0.0),
+                     subcycle=subcycle)
+    return p.replace(**kw) if kw else p
+
+
+def config2_schedule(total: int = 2000, frame: int = 50, press: float = 1.5e-3,
+                     slip: float = 2.0e-3, rot_deg: float = 30.0):
+    """Press `press` over the first quarter of the substeps, then slip `slip` along
+    +x while rotating `rot_deg` about the normal over the rest, one segment per
+    output frame.  Returns a list of (n_substeps, target_pos, target_quat)."""
+    p = config2()
+    x0, y0, z0 = p.pose0[:3]
+    n_press = total // 4
+    segs = []
+    done = 0
+    while done < total:
+        n = min(frame, total - done)
+        end = done + n
+        if end <= n_press:
+            a = end / n_press
+            pos = (x0, y0, z0 - press * a)
+            q = (1.0, 0.0, 0.0, 0.0)
+        else:
+            if done < n_press:          # a frame that straddles the phase change
+                n = n_press - done
+                end = n_press
+                pos, q = (x0, y0, z0 - press), (1.0, 0.0, 0.0, 0.0)
+                segs.append((n, pos, q))
+                done = end
+                continue
+            b = (end - n_press) / (total - n_press)
+            pos = (x0 + slip * b, y0, z0 - press)
+            q = quat_about_z(rot_deg * b)
+        segs.append((n, pos, q))
+        done = end
+    return segs
+
+
+def small_sensor(cells=(8, 8, 4), dx=0.5e-3, **kw) -> SensorParams:
+    """A slab small enough for the oracle to step in well under a second."""
+    pad = kw.pop("pad", 4)
+    L = [c * dx for c in cells]
+    H = cells[2] * dx
+    radius = kw.pop("radius", 1.5e-3)
+    p = SensorParams(cells=tuple(cells), dx=dx, pad_lateral=pad, pad_top=pad,
+                     shape=kw.pop("shape", SHAPE_SPHERE), radius=radius,
+                     pose0=(L[0] / 2, L[1] / 2, H + radius, 1.0, 0.0, 0.0, 0.0))
+    return p.replace(**kw) if kw else p
+
+
+def representable_positions(params: SensorParams, x: np.ndarray) -> np.ndarray:
+    """Round positions (metres, FP64) to the lattice a device holding each particle
+    as an integer cell plus an FP32 offset inside it can store exactly:
+    x = (cell + fl32(offset)) dx in slab coordinates."""
+    x = np.asarray(x, dtype=np.float64)
+    g = x / params.dx
+    cell = np.floor(g)
+    off = (g - cell).astype(np.float32).astype(np.float64)
+    return (cell + off) * params.dx
+
+
+def random_state(params: SensorParams, x_rest: np.ndarray, seed: int,
+                 v_scale: float = 1e-2, c_scale: float = 20.0, g_scale: float = 1e-2,
+                 x_scale: float = 0.05):
+    """A seeded random particle state around the rest configuration.
+
+    x_rest is (n, 3) in metres.  Returns (x, v, C, G) with x float64 (n,3) on the
+    device-representable lattice, and float32 v (n,3), C (n,3,3) and G = F - I
+    (n,3,3): positions jittered by up to x_scale*dx, velocities ~ N(0, v_scale)
+    m/s, C ~ N(0, c_scale) 1/s, G ~ N(0, g_scale).  Both sides start from exactly
+    these values (F = I + G is exact in FP64).
+    """
+    rng = np.random.default_rng(seed)
+    n = x_rest.shape[0]
+    x = x_rest + rng.uniform(-x_scale, x_scale, size=(n, 3)) * params.dx
+    v = rng.normal(0.0, v_scale, size=(n, 3))
+    C = rng.normal(0.0, c_scale, size=(n, 3, 3))
+    G = rng.normal(0.0, g_scale, size=(n, 3, 3))
+    return (representable_positions(params, x), v.astype(np.float32),
+            C.astype(np.float32), G.astype(np.float32))
