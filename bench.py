@@ -1,0 +1,193 @@
+"""Benchmark of the IMPM hot path on one MI355X.
+
+Workload (the full-resolution sensor): elastomer slab 32 x 32 x 8 mm on a
+128 x 128 x 32 grid (dx = 0.25 mm), 8 particles per cell (4,194,304
+particles), fixed-corotated E = 0.3 MPa, nu = 0.45, rho = 1000 kg/m^3, bottom
+face fixed; a capsule rod (r = 3 mm) pressed 1.5 mm over the first 500
+substeps, then slipped 2 mm along +x while rotating 30 degrees about the
+normal over the remaining 1500 substeps (dt = 2e-5 s per configured substep,
+4 executed steps each for stability), sticking contact; a 256 x 256 surface
+height map every 50 substeps.
+
+A benchmark "step" is one configured substep of that schedule (all executed
+steps, every pass of the relative-rest loop, the commit and the binning),
+with the height map of each 50-substep frame included.  The reported value is
+particle-updates per second: particles x executed steps / wall time.
+
+    python bench.py [--gpus 1] [--steps 2000] [--warmup 50]
+    python bench.py --copy-calibration     # 1 GiB device copy for counter scaling
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+SUBCYCLE = 4          # executed steps per configured substep at dx = 0.25 mm (CFL 0.67)
+FRAME = 50            # substeps between height maps
+HM = 256              # height map resolution
+PEAK_HBM_GBS = 8000.0
+# Algorithmic HBM bytes of one particle through one exchange pass: read x, v,
+# C, F (3 + 3 + 9 + 9 floats = 96 B) and write v, C, F, x (96 B), plus the
+# grid's share (two 16 B node records per 8 particles, read and written, ~7 B).
+ALG_BYTES_PER_PARTICLE_PASS = 192.0 + 7.0
+# rocprofv3 counter readings of the fused kernel for this workload (KiB per
+# dispatch), and the scale the same counters show for a copy of known size;
+# None until measured on this build of the kernel.
+PMC = None
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=4, help="oracle executed steps timed")
+    ap.add_argument("--copy-calibration", action="store_true")
+    return ap.parse_args()
+
+
+def copy_calibration():
+    import torch
+    n = 1 << 28                       # 1 GiB of float32
+    a = torch.ones(n, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n}))
+
+
+def run_frames(sim, segs, first, count, hm_out):
+    """Advance `count` configured substeps starting at substep `first` of the
+    schedule; a height map at every frame boundary."""
+    done = 0
+    k = first
+    # locate the segment containing substep `first`
+    bounds = []
+    s0 = 0
+    for n, pos, q in segs:
+        bounds.append((s0, s0 + n, pos, q))
+        s0 += n
+    total = s0
+    while done < count:
+        if k >= total:                      # past the schedule: hold the final pose
+            n = min(FRAME, count - done)
+            sim.sim_set_indenter_pose(bounds[-1][2], bounds[-1][3])
+            sim.sim_step(n)
+            sim.sim_surface_heightmap(HM, HM, out=hm_out)
+            done += n
+            k += n
+            continue
+        for a, b, pos, q in bounds:
+            if a <= k < b:
+                n = b - k
+                if k != a or n > count - done:
+                    raise ValueError("steps must cover whole frames of the schedule")
+                sim.sim_set_indenter_pose(pos, q)
+                sim.sim_step(n)
+                sim.sim_surface_heightmap(HM, HM, out=hm_out)
+                done += n
+                k += n
+                break
+    return done
+
+
+def main():
+    args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not supported",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2405_02914_amd import impm, workloads as W
+
+    if args.steps % FRAME or args.warmup % FRAME:
+        sys.exit("--steps and --warmup must be multiples of 50 (whole height-map frames)")
+    torch.cuda.set_device(0)
+    p = W.config2(subcycle=SUBCYCLE)
+    segs = W.config2_schedule()
+    hm = torch.empty(HM * HM, device="cuda", dtype=torch.float32)
+
+    # warm-up on a throw-away sensor (allocation, code load, caches)
+    if args.warmup:
+        w = impm.Sim(p)
+        run_frames(w, segs, 0, args.warmup, hm)
+        w.sim_synchronize()
+        w.close()
+        del w
+
+    sim = impm.Sim(p)
+    sim.sim_profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run_frames(sim, segs, 0, args.steps, hm)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sim.sim_synchronize()
+    st = sim.sim_get_stats()
+    kern_ms, kern_launches = sim.sim_profile_read()
+    wall = t1 - t0
+    n = sim.n
+    steps_exec = st["steps"]
+    value = n * steps_exec / wall
+    avg_ms = kern_ms / max(kern_launches, 1)
+    achieved = ALG_BYTES_PER_PARTICLE_PASS * n / (avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": "k_g2p2g<false>", "achieved": round(achieved, 1),
+                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                "traffic": None, "avg_kernel_ms": round(avg_ms, 5),
+                "alg_bytes_per_launch": ALG_BYTES_PER_PARTICLE_PASS * n}
+    if PMC is not None:
+        roofline["traffic"] = PMC
+    out = {
+        "metric": "IMPM particle-updates/s",
+        "value": value,
+        "unit": "particle-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "IMPM sensor 128x128x32 cells dx 0.25 mm, 4194304 particles, capsule "
+                               "press 1.5 mm then slip 2 mm + rotate 30 deg, 256x256 height map "
+                               "every 50 substeps",
+                   "particles": n, "subcycle": SUBCYCLE, "executed_steps": steps_exec,
+                   "passes": st["passes"], "limit_hits": st["limit_hits"],
+                   "particle_substeps_per_s": n * args.steps / wall,
+                   "particle_passes_per_s": n * st["passes"] / wall},
+        "roofline": roofline,
+    }
+    sim.close()
+    if not args.no_cpu_baseline:
+        from oracle import impm_ref
+        o = impm_ref.OracleSim(p)
+        n_, pos, q = segs[0]
+        subs = max(1, args.cpu_steps // SUBCYCLE)
+        a = subs / n_
+        o.set_target_pose(tuple(p0 + (p1 - p0) * a for p0, p1 in zip(p.pose0[:3], pos)), q)
+        c0 = time.perf_counter()
+        o.step(subs)
+        c1 = time.perf_counter()
+        ex = o.counters()["steps"]
+        out["cpu_baseline"] = {"value": o.n * ex / (c1 - c0), "unit": "particle-updates/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"first {ex} executed steps of the same workload "
+                                         f"({o.n} particles), FP64, one thread, {c1 - c0:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

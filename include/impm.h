@@ -1,0 +1,174 @@
+/*
+ * impm.h -- C ABI of the MI355X IMPM elastomer simulator (libimpm.so).
+ *
+ * The library simulates the elastomer layer of an optical tactile sensor with
+ * the improved Material Point Method of arXiv 2405.02914, Sec. III-A:
+ * particle-to-grid (Eq. 1-4), grid velocity and boundary handling (Eq. 5),
+ * grid-to-particle (Eq. 6-7), the relative-rest loop of Algorithm 1 (the
+ * elastomer held at rest relative to the indenter during slip and rotation),
+ * and particle movement (Eq. 8-9).  The indenter is a rigid kinematic body
+ * whose pose the caller sets; the output is the elastomer surface height map
+ * (Sec. IV-B, the depth data taken from the surface particles).
+ *
+ * Conventions
+ *   Units are SI (m, s, kg, Pa).  Coordinates are slab-local: origin at the
+ *   slab's (-x,-y) bottom corner, z up.  Quaternions are body->world (w,x,y,z).
+ *   Matrices are 3x3 row-major.  Particles are addressed by id:
+ *   id = ((k*Ny + j)*Nx + i)*ppc + (sz*m + sy)*m + sx for cell (i,j,k) and
+ *   sub-cell (sx,sy,sz) of the m^3 = ppc stratification.
+ *
+ * Ownership
+ *   The library owns every device buffer it allocates.  The caller owns every
+ *   buffer it passes in; the library never frees caller memory and writes an
+ *   output buffer only when the call succeeds.  Pointers flagged *_on_device
+ *   are device pointers (for example torch tensors on the same HIP device).
+ *
+ * Streams and errors
+ *   All device work is enqueued on the stream given to sim_create (NULL: a
+ *   stream the library creates).  sim_step only enqueues; device-side failures
+ *   (non-finite state, det F <= 0, a particle moving more than one cell in a
+ *   step) are latched on the device and reported as SIM_ENUMERIC by the next
+ *   synchronising call (sim_synchronize, sim_read_*, sim_surface_* with a host
+ *   output, sim_get_stats).  Every call returns SIM_OK (0) or a negative code;
+ *   sim_last_error gives a message for the last failure on that handle.
+ *   A sim_t is not thread-safe; distinct handles are independent.
+ */
+#ifndef IMPM_H
+#define IMPM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SIM_OK = 0,
+    SIM_EINVAL = -1,    /* bad argument or parameter */
+    SIM_ENOMEM = -2,    /* device allocation failed */
+    SIM_EHIP = -3,      /* a HIP runtime call failed */
+    SIM_ENUMERIC = -4,  /* latched device-side numerical failure */
+    SIM_ESTATE = -5     /* call not valid in the handle's state */
+};
+
+enum { SIM_SHAPE_NONE = 0, SIM_SHAPE_SPHERE = 1, SIM_SHAPE_CAPSULE = 2, SIM_SHAPE_BOX = 3 };
+enum { SIM_MODE_IMPM = 0, SIM_MODE_PLAIN = 1 };
+
+/* Device error bits reported by sim_get_stats (SIM_ENUMERIC when non-zero). */
+enum { SIM_DEV_CFL = 1, SIM_DEV_NONFINITE = 2, SIM_DEV_DETF = 4 };
+
+typedef struct {
+    int32_t cells[3];          /* slab cells per axis (Nx, Ny, Nz), each >= 1 */
+    int32_t ppc;               /* particles per cell: 1, 8 or 27 (a cube m^3) */
+    double dx;                 /* grid spacing W of Eq. 4 and 7 (m), > 0 */
+    uint64_t seed;             /* SplitMix64 seed of the particle jitter */
+    double E, nu, rho;         /* Young's modulus (Pa), Poisson ratio (0, 0.5), density */
+    double dt;                 /* configured substep (s), > 0 */
+    int32_t subcycle;          /* executed steps per configured substep (>= 1), each dt/subcycle */
+    int32_t pad_lateral;       /* empty cells on each lateral side of the slab (>= 1) */
+    int32_t pad_top;           /* empty cells above the slab (>= 1) */
+    int32_t pad_bottom;        /* cells below the slab's bottom face (>= 1); nodes with z <= 0 are fixed */
+    int32_t band;              /* zero-velocity node band at the lateral and top domain faces */
+    int32_t mode;              /* SIM_MODE_IMPM (Algorithm 1) or SIM_MODE_PLAIN (one exchange) */
+    int32_t rest_limit;        /* LIMIT of Algorithm 1 (>= 1) */
+    double rest_threshold;     /* threshold of the relative-rest test (>= 0) */
+    double fixed_z_fraction;   /* particles with rest height < fraction * slab height get v_z = 0 */
+    int32_t shape;             /* SIM_SHAPE_* */
+    int32_t _pad0;
+    double radius;             /* sphere / capsule radius (m) */
+    double half_length;        /* capsule: straight half-length along body x (m) */
+    double half_extent[3];     /* box half extents (m) */
+    double fillet;             /* box edge rounding radius (m), <= min half extent */
+    double pose0[7];           /* initial indenter pose: position xyz (m), quaternion wxyz */
+    int32_t stress_each_pass;  /* 1: every pass of the loop re-adds the elastic impulse */
+    int32_t _pad1;
+} sim_params;
+
+typedef struct {
+    int64_t substeps;          /* configured substeps completed */
+    int64_t steps;             /* executed (sub-cycled) steps */
+    int64_t passes;            /* exchange passes of Algorithm 1, summed over steps */
+    int64_t limit_hits;        /* steps that ended at LIMIT without meeting the test */
+    double last_r;             /* last relative-rest ratio |v_e,t - v_o,t| / |v_o,t| */
+    int32_t device_error;      /* SIM_DEV_* bits */
+    int32_t _pad;
+    double pose[7];            /* current commanded indenter pose */
+    double xo[3];              /* object calibration point x_o at the current pose */
+    int64_t calib_particle;    /* id of the elastomer calibration particle x_e */
+} sim_stats;
+
+typedef struct sim_s sim_t;
+
+/* Fill *p with the 16x16x4 mm, dx 0.5 mm sensor and a sphere indenter. */
+int sim_params_default(sim_params* p);
+
+/* Build the grid and the jittered particle cloud (Sec. IV-B: the elastomer
+ * cuboid and the object at its initial pose; the calibration points x_o, the
+ * object's lowest point, and x_e, the nearest elastomer particle, Algorithm 1).
+ * hip_stream: a hipStream_t, or NULL for a library-owned stream. */
+int sim_create(const sim_params* p, void* hip_stream, sim_t** out);
+
+/* Free every device buffer of the handle (NULL is ignored). */
+void sim_destroy(sim_t* s);
+
+/* Target pose reached at the end of the next sim_step: the indenter moves from
+ * its current pose at constant linear and angular velocity (linear position
+ * interpolation, rotation about one fixed axis). */
+int sim_set_indenter_pose(sim_t* s, const double pos[3], const double quat_wxyz[4]);
+
+/* Enqueue n_substeps configured substeps (n_substeps * subcycle executed steps
+ * of Algorithm 1). */
+int sim_step(sim_t* s, int32_t n_substeps);
+
+/* Wait for enqueued work; return SIM_ENUMERIC if a device error was latched. */
+int sim_synchronize(sim_t* s);
+
+/* Surface height map, H rows x W columns, row v and column u at the pixel
+ * centre ((u+1/2) Lx/W, (v+1/2) Ly/H): slab height + the Shepard-normalised
+ * 2-D quadratic B-spline average (pitch = pixel size) of the top surface
+ * particles' z displacement; pixels with no particle weight get the slab
+ * height.  out: W*H floats, host or device memory. */
+int sim_surface_heightmap(sim_t* s, float* out, int32_t W, int32_t H, int32_t out_on_device);
+
+/* The same interpolation of the full displacement x - X_rest: H*W*3 floats. */
+int sim_surface_displacement(sim_t* s, float* out, int32_t W, int32_t H, int32_t out_on_device);
+
+int sim_get_stats(sim_t* s, sim_stats* out);
+int sim_num_particles(const sim_t* s, int64_t* n);
+int sim_grid_dims(const sim_t* s, int32_t nodes[3]);
+
+/* Particle state in id order, host memory; any pointer may be NULL.
+ * x: n*3 doubles (m); v: n*3 floats; C: n*9 floats; G = F - I: n*9 floats. */
+int sim_read_particles(sim_t* s, double* x, float* v, float* C, float* G);
+int sim_write_particles(sim_t* s, const double* x, const float* v, const float* C, const float* G);
+
+/* Rest positions (n*3 doubles) and flags (bit 0 bottom layer, bit 1 surface). */
+int sim_read_rest(sim_t* s, double* X, uint8_t* flags);
+
+/* Keep the grid mass M (n_nodes), momentum MG (n_nodes*3) and velocity V
+ * (n_nodes*3) of the last pass for sim_read_grid (costs bandwidth). */
+int sim_debug_keep_grid(sim_t* s, int32_t on);
+int sim_read_grid(sim_t* s, float* M, float* MG, float* V);
+
+/* Replay a pass schedule: the next n executed steps do exactly passes[i]
+ * exchanges each (parity runs near the relative-rest threshold). */
+int sim_debug_force_passes(sim_t* s, const int32_t* passes, int32_t n);
+
+/* Tile shape (cells per axis) of the binned particle order; call before the
+ * first sim_step or after sim_write_particles.  Default 8 x 8 x 4. */
+int sim_set_tile(sim_t* s, int32_t tx, int32_t ty, int32_t tz);
+
+/* Time every first-pass fused exchange kernel (grid-to-particle, commit,
+ * particle-to-grid) with HIP events on the handle's stream (on != 0).
+ * sim_profile_read synchronises, returns the summed kernel time (ms) and the
+ * number of timed launches since the last read, and resets them. */
+int sim_profile(sim_t* s, int32_t on);
+int sim_profile_read(sim_t* s, double* ms_total, int64_t* launches);
+
+const char* sim_last_error(const sim_t* s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IMPM_H */

@@ -1,0 +1,896 @@
+// impm_host.hip -- host runtime and C ABI (include/impm.h) of the IMPM
+// elastomer simulator: particle initialisation, the per-step indenter pose
+// table, the device-side relative-rest loop driver, the binned particle order
+// and the surface raster (arXiv 2405.02914, Sec. III-A and Sec. IV-B).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/impm.h"
+#include "impm_device.h"
+
+namespace impm {
+__global__ void k_fill(float* p, long long n, float val);
+__global__ void k_p2g(KArgs a, const uint32_t* order, const uint32_t* bstart);
+template <bool EXTRA>
+__global__ void k_grid(KArgs a, const uint32_t* bstart, int step, int pass);
+template <bool EXTRA>
+__global__ void k_g2p2g(KArgs a, const uint32_t* order, const uint32_t* bstart, int step,
+                        long long gstep, int pass, int store_vc);
+__global__ void k_scan(KArgs a, uint32_t* bstart_next, int limit_slots);
+__global__ void k_scatter(KArgs a, const uint32_t* order, const uint32_t* bstart,
+                          uint32_t* order_next);
+__global__ void k_surface_accum(KArgs a, SurfArgs s);
+__global__ void k_surface_finish(const float4* acc, int npix, float top, int mode, float* out);
+}  // namespace impm
+
+using namespace impm;
+
+struct sim_s {
+    sim_params P;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int device = 0;
+    long long n = 0;
+    int m = 0;
+    int nn[3] = {0, 0, 0};
+    long long n_nodes = 0;
+    double mu = 0, lam = 0, Vp = 0, mp = 0;
+    // tiles
+    int T[3] = {8, 8, 4};
+    int NT[3] = {0, 0, 0};
+    int n_tiles = 0;
+    // device buffers
+    float* soa = nullptr;
+    uint32_t* cell = nullptr;
+    uint8_t* flags = nullptr;
+    uint32_t* order[2] = {nullptr, nullptr};
+    uint32_t* bstart[2] = {nullptr, nullptr};
+    int cur = 0;
+    uint32_t* dirrank = nullptr;
+    uint32_t* dircount = nullptr;
+    uint32_t* diroff = nullptr;
+    float4* scratch = nullptr;
+    size_t scratch_cap = 0;   // float4 elements
+    float4* gridV = nullptr;
+    float* dbgM = nullptr;
+    float* dbgMG = nullptr;
+    DevState* st = nullptr;
+    StepPose* poses = nullptr;
+    long long pose_cap = 0;
+    float* surf_rest = nullptr;
+    long long n_surf = 0;
+    float4* surf_acc = nullptr;
+    long long surf_cap = 0;
+    float* out_tmp = nullptr;
+    long long out_cap = 0;
+    // host state
+    double pos[3], quat[4], tpos[3], tquat[4], po_body[3];
+    long long e = 0;
+    bool pending = false;        // scratch holds the first exchange of the next step
+    int sbin = 0;                // binning under which the scratch was written
+    bool keep_grid = false;
+    std::vector<int> forced;
+    size_t forced_pos = 0;
+    long long substeps = 0;
+    long long gstep = 0;
+    std::string err;
+    // pose upload staging: two pinned host buffers, each reused only after the
+    // copy that last read it has completed
+    StepPose* stage[2] = {nullptr, nullptr};
+    long long stage_cap[2] = {0, 0};
+    hipEvent_t stage_ev[2] = {nullptr, nullptr};
+    int stage_next = 0;
+    // optional timing of the first-pass fused kernel with events on the stream
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    double prof_ms = 0.0;
+    long long prof_launches = 0;
+};
+
+// ------------------------------------------------------------------ helpers
+
+static int fail(sim_t* s, int code, const std::string& msg) {
+    if (s) s->err = msg;
+    return code;
+}
+
+#define HIPCHK(s, call)                                                                   \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail((s), SIM_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// SplitMix64 (Steele, Lea, Flood 2014) as a counter-based generator: the t-th
+// output of the stream seeded with `seed`.
+static uint64_t splitmix64_at(uint64_t seed, uint64_t t) {
+    uint64_t z = seed + t * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+static float rest_offset(uint64_t seed, long long id, int axis, int sub_a, int m) {
+    const double u = (double)(splitmix64_at(seed, (uint64_t)(3 * id + axis + 1)) >> 11) *
+                     (1.0 / 9007199254740992.0);
+    return (float)(((double)sub_a + u) / (double)m);
+}
+
+static void quat_mul(const double* a, const double* b, double* o) {
+    const double w = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+    const double x = a[0] * b[1] + a[1] * b[0] + a[2] * b[3] - a[3] * b[2];
+    const double y = a[0] * b[2] - a[1] * b[3] + a[2] * b[0] + a[3] * b[1];
+    const double z = a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0];
+    o[0] = w; o[1] = x; o[2] = y; o[3] = z;
+}
+
+static void quat_matrix(const double* q, double* R) {
+    const double w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0] = 1.0 - 2.0 * (y * y + z * z); R[1] = 2.0 * (x * y - w * z); R[2] = 2.0 * (x * z + w * y);
+    R[3] = 2.0 * (x * y + w * z); R[4] = 1.0 - 2.0 * (x * x + z * z); R[5] = 2.0 * (y * z - w * x);
+    R[6] = 2.0 * (x * z - w * y); R[7] = 2.0 * (y * z + w * x); R[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+static void quat_normalise(double* q) {
+    const double s = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    for (int k = 0; k < 4; ++k) q[k] /= s;
+}
+
+// Relative rotation q0 -> q1 as a unit axis and an angle in [0, pi].
+static void rel_axis_angle(const double* q0, const double* q1, double* axis, double* angle) {
+    const double q0c[4] = {q0[0], -q0[1], -q0[2], -q0[3]};
+    double r[4];
+    quat_mul(q1, q0c, r);
+    if (r[0] < 0.0) for (int k = 0; k < 4; ++k) r[k] = -r[k];
+    const double s = std::sqrt(r[1] * r[1] + r[2] * r[2] + r[3] * r[3]);
+    if (s <= 0.0) { axis[0] = 0.0; axis[1] = 0.0; axis[2] = 1.0; *angle = 0.0; return; }
+    axis[0] = r[1] / s; axis[1] = r[2] / s; axis[2] = r[3] / s;
+    *angle = 2.0 * std::atan2(s, r[0]);
+}
+
+// Body-frame lowest point of the indenter (the object calibration point x_o of
+// Algorithm 1); ties go to the point farthest from the body z axis, then to the
+// lexicographic minimum of (x, y).
+static void lowest_point(const sim_params& P, double* p) {
+    p[0] = p[1] = p[2] = 0.0;
+    if (P.shape == SIM_SHAPE_SPHERE) {
+        p[2] = -P.radius;
+    } else if (P.shape == SIM_SHAPE_CAPSULE) {
+        p[0] = -P.half_length; p[2] = -P.radius;
+    } else if (P.shape == SIM_SHAPE_BOX) {
+        p[0] = -(P.half_extent[0] - P.fillet);
+        p[1] = -(P.half_extent[1] - P.fillet);
+        p[2] = -P.half_extent[2];
+    }
+}
+
+static void body_to_world(const double* c, const double* R, const double* pb, double* out) {
+    for (int a = 0; a < 3; ++a) out[a] = c[a] + R[3 * a] * pb[0] + R[3 * a + 1] * pb[1] + R[3 * a + 2] * pb[2];
+}
+
+// Pose table of one sim_step call: N executed steps of length h moving the
+// body from (pos, quat) to (tpos, tquat) at constant velocity (Sec. IV-B:
+// press, slide and rotate step by step until the target pose).
+static void make_pose(const sim_t* s, long long j, long long N, double h, StepPose* sp) {
+    const double frac = (double)j / (double)N;
+    for (int a = 0; a < 3; ++a) {
+        const double d = s->tpos[a] - s->pos[a];
+        sp->c[a] = s->pos[a] + d * frac;
+        sp->vo[a] = d / ((double)N * h);
+    }
+    double axis[3], ang;
+    rel_axis_angle(s->quat, s->tquat, axis, &ang);
+    const double half = 0.5 * ang * frac;
+    const double qs[4] = {std::cos(half), axis[0] * std::sin(half), axis[1] * std::sin(half),
+                          axis[2] * std::sin(half)};
+    double qj[4];
+    quat_mul(qs, s->quat, qj);
+    quat_matrix(qj, sp->R);
+    for (int a = 0; a < 3; ++a) sp->w[a] = axis[a] * ang / ((double)N * h);
+    double xo[3];
+    body_to_world(sp->c, sp->R, s->po_body, xo);
+    const double r[3] = {xo[0] - sp->c[0], xo[1] - sp->c[1], xo[2] - sp->c[2]};
+    const double vx = sp->vo[0] + (sp->w[1] * r[2] - sp->w[2] * r[1]);
+    const double vy = sp->vo[1] + (sp->w[2] * r[0] - sp->w[0] * r[2]);
+    sp->vot[0] = vx;
+    sp->vot[1] = vy;
+    sp->gnorm = std::sqrt(vx * vx + vy * vy);
+    sp->forced = 0;
+    sp->_pad = 0;
+}
+
+static KArgs kargs(const sim_t* s) {
+    KArgs a;
+    std::memset(&a, 0, sizeof(a));
+    const sim_params& P = s->P;
+    for (int q = 0; q < 3; ++q) {
+        a.nn[q] = s->nn[q];
+        a.T[q] = s->T[q];
+        a.NT[q] = s->NT[q];
+        a.FP[q] = s->T[q] + 5;
+        a.FG[q] = s->T[q] + 3;
+    }
+    a.n_tiles = s->n_tiles;
+    a.FPvol = a.FP[0] * a.FP[1] * a.FP[2];
+    a.FGvol = a.FG[0] * a.FG[1] * a.FG[2];
+    a.pad_l = P.pad_lateral;
+    a.pad_b = P.pad_bottom;
+    a.band = P.band;
+    a.mode = P.mode;
+    a.bottom_rule = P.mode == SIM_MODE_IMPM ? 1 : 0;
+    a.rest_limit = P.rest_limit;
+    a.stress_each_pass = P.stress_each_pass;
+    a.shape = P.shape;
+    const double h = P.dt / (double)P.subcycle;
+    a.dx = (float)P.dx;
+    a.inv_dx = (float)(1.0 / P.dx);
+    a.h = (float)h;
+    a.h_over_dx = (float)(h / P.dx);
+    a.kst = (float)(4.0 * h / (P.rho * P.dx));
+    a.mu2 = (float)(2.0 * s->mu);
+    a.lam = (float)s->lam;
+    a.c4dx = (float)(4.0 / P.dx);
+    a.dxd = P.dx;
+    a.rest_threshold = P.rest_threshold;
+    a.radius = P.radius;
+    a.half_length = P.half_length;
+    for (int q = 0; q < 3; ++q) a.he[q] = P.half_extent[q];
+    a.fillet = P.fillet;
+    a.mp = (float)s->mp;
+    a.n = s->n;
+    a.e = s->e;
+    a.soa = s->soa;
+    a.cell = s->cell;
+    a.flags = s->flags;
+    a.scratch = s->scratch;
+    a.gridV = s->gridV;
+    a.dbgM = s->keep_grid ? s->dbgM : nullptr;
+    a.dbgMG = s->keep_grid ? s->dbgMG : nullptr;
+    a.dirrank = s->dirrank;
+    a.dircount = s->dircount;
+    a.diroff = s->diroff;
+    a.st = s->st;
+    a.poses = s->poses;
+    return a;
+}
+
+static size_t g2p2g_lds(const KArgs& a) {
+    return (size_t)(a.FPvol + a.FGvol) * sizeof(float4) + 81 * sizeof(float) +
+           (kWaves * kDirs + kDirs + 4) * sizeof(int);
+}
+
+// Host-side counting sort of the particles by tile (stable in id order).
+static int rebin_host(sim_t* s, const std::vector<uint32_t>& cells) {
+    std::vector<uint32_t> cnt(s->n_tiles + 1, 0), tile(s->n);
+    for (long long id = 0; id < s->n; ++id) {
+        const uint32_t c = cells[id];
+        const int cx = c & 1023, cy = (c >> 10) & 1023, cz = (c >> 20) & 1023;
+        const int t = ((cz / s->T[2]) * s->NT[1] + cy / s->T[1]) * s->NT[0] + cx / s->T[0];
+        tile[id] = t;
+        cnt[t + 1]++;
+    }
+    for (int t = 0; t < s->n_tiles; ++t) cnt[t + 1] += cnt[t];
+    std::vector<uint32_t> order(s->n), pos(cnt.begin(), cnt.end() - 1);
+    for (long long id = 0; id < s->n; ++id) order[pos[tile[id]]++] = (uint32_t)id;
+    HIPCHK(s, hipMemcpyAsync(s->order[s->cur], order.data(), s->n * 4, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipMemcpyAsync(s->bstart[s->cur], cnt.data(), (s->n_tiles + 1) * 4, hipMemcpyHostToDevice,
+                             s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    return SIM_OK;
+}
+
+static int set_xe_snapshot(sim_t* s, uint32_t cell, const float f[3]) {
+    // both parities hold x_e so that the next step reads it whichever it is
+    uint32_t c2[2] = {cell, cell};
+    float f2[6] = {f[0], f[1], f[2], f[0], f[1], f[2]};
+    HIPCHK(s, hipMemcpyAsync(s->st->xe_cell, c2, sizeof(c2), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipMemcpyAsync(s->st->xe_f, f2, sizeof(f2), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    return SIM_OK;
+}
+
+static int alloc_tiles(sim_t* s) {
+    for (int q = 0; q < 3; ++q) s->NT[q] = (s->nn[q] - 1 + s->T[q] - 1) / s->T[q];
+    s->n_tiles = s->NT[0] * s->NT[1] * s->NT[2];
+    const size_t fpvol = (size_t)(s->T[0] + 5) * (s->T[1] + 5) * (s->T[2] + 5);
+    const size_t need = fpvol * s->n_tiles;
+    for (int k = 0; k < 2; ++k) {
+        if (s->bstart[k]) (void)hipFree(s->bstart[k]);
+        s->bstart[k] = nullptr;
+        HIPCHK(s, hipMalloc(&s->bstart[k], (s->n_tiles + 1) * sizeof(uint32_t)));
+    }
+    if (s->dircount) (void)hipFree(s->dircount);
+    if (s->diroff) (void)hipFree(s->diroff);
+    s->dircount = s->diroff = nullptr;
+    HIPCHK(s, hipMalloc(&s->dircount, (size_t)s->n_tiles * kDirs * sizeof(uint32_t)));
+    HIPCHK(s, hipMalloc(&s->diroff, (size_t)s->n_tiles * kDirs * sizeof(uint32_t)));
+    HIPCHK(s, hipMemset(s->dircount, 0, (size_t)s->n_tiles * kDirs * sizeof(uint32_t)));
+    if (need > s->scratch_cap) {
+        if (s->scratch) (void)hipFree(s->scratch);
+        s->scratch = nullptr;
+        HIPCHK(s, hipMalloc(&s->scratch, need * sizeof(float4)));
+        s->scratch_cap = need;
+    }
+    return SIM_OK;
+}
+
+static int read_cells(sim_t* s, std::vector<uint32_t>& cells) {
+    cells.resize(s->n);
+    HIPCHK(s, hipMemcpyAsync(cells.data(), s->cell, s->n * 4, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    return SIM_OK;
+}
+
+static int refresh_binning(sim_t* s) {
+    std::vector<uint32_t> cells;
+    int rc = read_cells(s, cells);
+    if (rc) return rc;
+    rc = rebin_host(s, cells);
+    if (rc) return rc;
+    uint32_t ce;
+    float fe[3];
+    HIPCHK(s, hipMemcpy(&ce, s->cell + s->e, 4, hipMemcpyDeviceToHost));
+    for (int q = 0; q < 3; ++q)
+        HIPCHK(s, hipMemcpy(&fe[q], s->soa + (size_t)(F0 + q) * s->n + s->e, 4, hipMemcpyDeviceToHost));
+    s->pending = false;
+    return set_xe_snapshot(s, ce, fe);
+}
+
+static int check_device_error(sim_t* s) {
+    int32_t e = 0;
+    HIPCHK(s, hipMemcpyAsync(&e, &s->st->error, 4, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    if (e) {
+        char buf[160];
+        std::snprintf(buf, sizeof(buf),
+                      "device error 0x%x (1: particle moved more than a cell or left the grid, "
+                      "2: non-finite state, 4: det F <= 0)", e);
+        return fail(s, SIM_ENUMERIC, buf);
+    }
+    return SIM_OK;
+}
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+int sim_params_default(sim_params* p) {
+    if (!p) return SIM_EINVAL;
+    std::memset(p, 0, sizeof(*p));
+    p->cells[0] = 32; p->cells[1] = 32; p->cells[2] = 8;
+    p->ppc = 8;
+    p->dx = 0.5e-3;
+    p->seed = 2405;
+    p->E = 3.0e5; p->nu = 0.45; p->rho = 1000.0;
+    p->dt = 2.0e-5;
+    p->subcycle = 2;
+    p->pad_lateral = 4; p->pad_top = 4; p->pad_bottom = 2; p->band = 2;
+    p->mode = SIM_MODE_IMPM;
+    p->rest_limit = 10;
+    p->rest_threshold = 0.5;
+    p->fixed_z_fraction = 0.5;
+    p->shape = SIM_SHAPE_SPHERE;
+    p->radius = 4.0e-3;
+    p->pose0[0] = 8.0e-3; p->pose0[1] = 8.0e-3; p->pose0[2] = 8.0e-3; p->pose0[3] = 1.0;
+    return SIM_OK;
+}
+
+static int validate(const sim_params* p, std::string& why) {
+    if (!p) { why = "null params"; return SIM_EINVAL; }
+    for (int q = 0; q < 3; ++q)
+        if (p->cells[q] < 1) { why = "cells must be >= 1"; return SIM_EINVAL; }
+    int m = 0;
+    for (int k = 1; k <= 4; ++k) if (k * k * k == p->ppc) m = k;
+    if (!m) { why = "ppc must be 1, 8, 27 or 64"; return SIM_EINVAL; }
+    if (!(p->dx > 0) || !(p->dt > 0) || !(p->E > 0) || !(p->rho > 0)) { why = "dx, dt, E, rho must be > 0"; return SIM_EINVAL; }
+    if (!(p->nu > 0 && p->nu < 0.5)) { why = "nu must be in (0, 0.5)"; return SIM_EINVAL; }
+    if (p->subcycle < 1) { why = "subcycle must be >= 1"; return SIM_EINVAL; }
+    if (p->pad_lateral < 1 || p->pad_top < 1 || p->pad_bottom < 1 || p->band < 0) { why = "pads must be >= 1"; return SIM_EINVAL; }
+    if (p->rest_limit < 1 || p->rest_limit > 32) { why = "rest_limit must be in [1, 32]"; return SIM_EINVAL; }
+    if (!(p->rest_threshold >= 0)) { why = "rest_threshold must be >= 0"; return SIM_EINVAL; }
+    if (p->mode != SIM_MODE_IMPM && p->mode != SIM_MODE_PLAIN) { why = "bad mode"; return SIM_EINVAL; }
+    if (p->shape < 0 || p->shape > 3) { why = "bad shape"; return SIM_EINVAL; }
+    const int nn[3] = {p->cells[0] + 2 * p->pad_lateral + 1, p->cells[1] + 2 * p->pad_lateral + 1,
+                       p->cells[2] + p->pad_bottom + p->pad_top + 1};
+    for (int q = 0; q < 3; ++q)
+        if (nn[q] > 1023) { why = "grid too large (at most 1023 nodes per axis)"; return SIM_EINVAL; }
+    const long long n = (long long)p->cells[0] * p->cells[1] * p->cells[2] * p->ppc;
+    if (n >= (1LL << 31)) { why = "too many particles"; return SIM_EINVAL; }
+    double qn = 0;
+    for (int k = 3; k < 7; ++k) qn += p->pose0[k] * p->pose0[k];
+    if (!(qn > 0)) { why = "pose0 quaternion is zero"; return SIM_EINVAL; }
+    return SIM_OK;
+}
+
+int sim_create(const sim_params* p, void* hip_stream, sim_t** out) {
+    if (!out) return SIM_EINVAL;
+    *out = nullptr;
+    std::string why;
+    if (validate(p, why) != SIM_OK) {
+        std::fprintf(stderr, "sim_create: %s\n", why.c_str());
+        return SIM_EINVAL;
+    }
+    sim_t* s = new sim_t();
+    s->P = *p;
+    const sim_params& P = s->P;
+    for (int k = 1; k <= 4; ++k) if (k * k * k == P.ppc) s->m = k;
+    const int m = s->m;
+    const int Nx = P.cells[0], Ny = P.cells[1], Nz = P.cells[2];
+    s->n = (long long)Nx * Ny * Nz * P.ppc;
+    s->nn[0] = Nx + 2 * P.pad_lateral + 1;
+    s->nn[1] = Ny + 2 * P.pad_lateral + 1;
+    s->nn[2] = Nz + P.pad_bottom + P.pad_top + 1;
+    s->n_nodes = (long long)s->nn[0] * s->nn[1] * s->nn[2];
+    s->mu = P.E / (2.0 * (1.0 + P.nu));
+    s->lam = P.E * P.nu / ((1.0 + P.nu) * (1.0 - 2.0 * P.nu));
+    s->Vp = P.dx * P.dx * P.dx / (double)P.ppc;
+    s->mp = P.rho * s->Vp;
+    if (hipGetDevice(&s->device) != hipSuccess) { delete s; return SIM_EHIP; }
+    if (hip_stream) {
+        s->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreate(&s->stream) != hipSuccess) { delete s; return SIM_EHIP; }
+        s->own_stream = true;
+    }
+    auto bail = [&](int rc) { sim_destroy(s); return rc; };
+    const size_t n = (size_t)s->n;
+    if (hipMalloc(&s->soa, n * NPLANES * sizeof(float)) != hipSuccess ||
+        hipMalloc(&s->cell, n * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&s->flags, n) != hipSuccess ||
+        hipMalloc(&s->order[0], n * 4) != hipSuccess || hipMalloc(&s->order[1], n * 4) != hipSuccess ||
+        hipMalloc(&s->dirrank, n * 4) != hipSuccess ||
+        hipMalloc(&s->gridV, (size_t)s->n_nodes * sizeof(float4)) != hipSuccess ||
+        hipMalloc(&s->st, sizeof(DevState)) != hipSuccess)
+        return bail(SIM_ENOMEM);
+    if (alloc_tiles(s) != SIM_OK) return bail(SIM_ENOMEM);
+
+    // stratified jittered particles: one per sub-cell of the m^3 split of each cell
+    std::vector<float> host(n * NPLANES, 0.0f);
+    std::vector<uint32_t> cells(n);
+    std::vector<uint8_t> flags(n);
+    s->n_surf = (long long)Nx * Ny * m * m;
+    std::vector<float> srest((size_t)s->n_surf * 3);
+    const double H = (double)Nz * P.dx;
+    for (int k = 0; k < Nz; ++k)
+        for (int j = 0; j < Ny; ++j)
+            for (int i = 0; i < Nx; ++i)
+                for (int sz = 0; sz < m; ++sz)
+                    for (int sy = 0; sy < m; ++sy)
+                        for (int sx = 0; sx < m; ++sx) {
+                            const long long cid = ((long long)k * Ny + j) * Nx + i;
+                            const long long id = cid * P.ppc + (sz * m + sy) * m + sx;
+                            const int ci[3] = {i, j, k}, si[3] = {sx, sy, sz};
+                            const int gc[3] = {i + P.pad_lateral, j + P.pad_lateral, k + P.pad_bottom};
+                            float r[3];
+                            for (int a = 0; a < 3; ++a) {
+                                r[a] = rest_offset(P.seed, id, a, si[a], m);
+                                host[(size_t)(F0 + a) * n + id] = r[a];
+                            }
+                            cells[id] = pack_cell(gc);
+                            const double z = ((double)ci[2] + (double)r[2]) * P.dx;
+                            uint8_t fl = 0;
+                            if (z < P.fixed_z_fraction * H) fl |= FLAG_BOTTOM;
+                            if (k == Nz - 1 && sz == m - 1) {
+                                fl |= FLAG_SURFACE;
+                                const long long sidx = ((long long)j * Nx + i) * m * m + sy * m + sx;
+                                for (int a = 0; a < 3; ++a) srest[3 * sidx + a] = r[a];
+                            }
+                            flags[id] = fl;
+                        }
+    // indenter pose and calibration points
+    std::memcpy(s->pos, P.pose0, sizeof(s->pos));
+    std::memcpy(s->quat, P.pose0 + 3, sizeof(s->quat));
+    quat_normalise(s->quat);
+    std::memcpy(s->tpos, s->pos, sizeof(s->pos));
+    std::memcpy(s->tquat, s->quat, sizeof(s->quat));
+    lowest_point(P, s->po_body);
+    double R0[9], xo[3];
+    quat_matrix(s->quat, R0);
+    body_to_world(s->pos, R0, s->po_body, xo);
+    double best = 1e300;
+    s->e = 0;
+    for (long long id = 0; id < s->n; ++id) {
+        const uint32_t c = cells[id];
+        const int cc[3] = {(int)(c & 1023) - P.pad_lateral, (int)((c >> 10) & 1023) - P.pad_lateral,
+                           (int)((c >> 20) & 1023) - P.pad_bottom};
+        double d2 = 0;
+        for (int a = 0; a < 3; ++a) {
+            const double xa = ((double)cc[a] + (double)host[(size_t)(F0 + a) * n + id]) * P.dx;
+            const double d = xa - xo[a];
+            d2 += d * d;
+        }
+        if (d2 < best) { best = d2; s->e = id; }
+    }
+    // G = 0 (F = I), v = 0, C = 0 already
+    if (hipMemcpy(s->soa, host.data(), n * NPLANES * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(s->cell, cells.data(), n * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(s->flags, flags.data(), n, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(s->st, 0, sizeof(DevState)) != hipSuccess)
+        return bail(SIM_EHIP);
+    if (hipMalloc(&s->surf_rest, srest.size() * sizeof(float)) != hipSuccess) return bail(SIM_ENOMEM);
+    if (hipMemcpy(s->surf_rest, srest.data(), srest.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+        return bail(SIM_EHIP);
+    if (rebin_host(s, cells) != SIM_OK) return bail(SIM_EHIP);
+    const float fe[3] = {host[(size_t)F0 * n + s->e], host[(size_t)(F0 + 1) * n + s->e],
+                         host[(size_t)(F0 + 2) * n + s->e]};
+    if (set_xe_snapshot(s, cells[s->e], fe) != SIM_OK) return bail(SIM_EHIP);
+    *out = s;
+    return SIM_OK;
+}
+
+void sim_destroy(sim_t* s) {
+    if (!s) return;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    void* bufs[] = {s->soa, s->cell, s->flags, s->order[0], s->order[1], s->bstart[0], s->bstart[1],
+                    s->dirrank, s->dircount, s->diroff, s->scratch, s->gridV, s->dbgM, s->dbgMG,
+                    s->st, s->poses, s->surf_rest, s->surf_acc, s->out_tmp};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    for (int k = 0; k < 2; ++k) {
+        if (s->stage[k]) (void)hipHostFree(s->stage[k]);
+        if (s->stage_ev[k]) (void)hipEventDestroy(s->stage_ev[k]);
+    }
+    for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
+    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+}
+
+int sim_set_indenter_pose(sim_t* s, const double pos[3], const double quat_wxyz[4]) {
+    if (!s || !pos || !quat_wxyz) return fail(s, SIM_EINVAL, "null argument");
+    double q[4] = {quat_wxyz[0], quat_wxyz[1], quat_wxyz[2], quat_wxyz[3]};
+    const double qn = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+    if (!(qn > 0) || !std::isfinite(pos[0] + pos[1] + pos[2])) return fail(s, SIM_EINVAL, "bad pose");
+    quat_normalise(q);
+    std::memcpy(s->tpos, pos, sizeof(s->tpos));
+    std::memcpy(s->tquat, q, sizeof(s->tquat));
+    return SIM_OK;
+}
+
+int sim_set_tile(sim_t* s, int32_t tx, int32_t ty, int32_t tz) {
+    if (!s) return SIM_EINVAL;
+    if (tx < 2 || ty < 2 || tz < 2 || tx > 32 || ty > 32 || tz > 32)
+        return fail(s, SIM_EINVAL, "tile sizes must be in [2, 32]");
+    const size_t lds = (size_t)((tx + 5) * (ty + 5) * (tz + 5) + (tx + 3) * (ty + 3) * (tz + 3)) *
+                       sizeof(float4) + 1024;
+    if (lds > 160 * 1024) return fail(s, SIM_EINVAL, "tile needs more LDS than a workgroup has");
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    s->T[0] = tx; s->T[1] = ty; s->T[2] = tz;
+    int rc = alloc_tiles(s);
+    if (rc) return rc;
+    return refresh_binning(s);
+}
+
+int sim_step(sim_t* s, int32_t n_substeps) {
+    if (!s) return SIM_EINVAL;
+    if (n_substeps < 1) return fail(s, SIM_EINVAL, "n_substeps must be >= 1");
+    const sim_params& P = s->P;
+    const long long N = (long long)n_substeps * P.subcycle;
+    const double h = P.dt / (double)P.subcycle;
+    if (N > s->pose_cap) {
+        HIPCHK(s, hipStreamSynchronize(s->stream));
+        if (s->poses) (void)hipFree(s->poses);
+        s->poses = nullptr;
+        HIPCHK(s, hipMalloc(&s->poses, N * sizeof(StepPose)));
+        s->pose_cap = N;
+    }
+    const int b = s->stage_next;
+    s->stage_next ^= 1;
+    if (!s->stage_ev[b]) HIPCHK(s, hipEventCreateWithFlags(&s->stage_ev[b], hipEventDisableTiming));
+    HIPCHK(s, hipEventSynchronize(s->stage_ev[b]));   // the copy that last read this buffer
+    if (N > s->stage_cap[b]) {
+        if (s->stage[b]) (void)hipHostFree(s->stage[b]);
+        s->stage[b] = nullptr;
+        HIPCHK(s, hipHostMalloc(&s->stage[b], N * sizeof(StepPose), hipHostMallocDefault));
+        s->stage_cap[b] = N;
+    }
+    StepPose* poses = s->stage[b];
+    std::vector<int> npass(N);
+    for (long long j = 0; j < N; ++j) {
+        StepPose& sp = poses[j];
+        make_pose(s, j, N, h, &sp);
+        if (s->forced_pos < s->forced.size()) sp.forced = s->forced[s->forced_pos++];
+        if (sp.forced > 0) npass[j] = sp.forced;
+        else if (P.mode == SIM_MODE_PLAIN || sp.gnorm <= 1e-9) npass[j] = 1;
+        else npass[j] = P.rest_limit;
+    }
+    HIPCHK(s, hipMemcpyAsync(s->poses, poses, N * sizeof(StepPose), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipEventRecord(s->stage_ev[b], s->stream));
+    KArgs a = kargs(s);
+    const size_t lds_g = g2p2g_lds(a);
+    const size_t lds_p = (size_t)a.FPvol * sizeof(float4);
+    const int node_blocks = (int)((s->n_nodes + kBlock - 1) / kBlock);
+    if (!s->pending) {
+        hipLaunchKernelGGL(k_p2g, dim3(s->n_tiles), dim3(kBlock), lds_p, s->stream, a,
+                           s->order[s->cur], s->bstart[s->cur]);
+        HIPCHK(s, hipGetLastError());
+        s->sbin = s->cur;
+    }
+    const int limit_slots = std::min(34, P.rest_limit + 2);
+    for (long long j = 0; j < N; ++j) {
+        const int c = s->cur;
+        const int store = j == N - 1 ? 1 : 0;
+        // the partials were written under the binning of the pass that made them
+        hipLaunchKernelGGL(k_grid<false>, dim3(node_blocks), dim3(kBlock), 0, s->stream, a,
+                           s->bstart[s->sbin], (int)j, 0);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (s->prof) {
+            while (s->ev_pool.size() < s->ev_used + 2) {
+                hipEvent_t e;
+                HIPCHK(s, hipEventCreate(&e));
+                s->ev_pool.push_back(e);
+            }
+            e0 = s->ev_pool[s->ev_used++];
+            e1 = s->ev_pool[s->ev_used++];
+            HIPCHK(s, hipEventRecord(e0, s->stream));
+        }
+        hipLaunchKernelGGL(k_g2p2g<false>, dim3(s->n_tiles), dim3(kBlock), lds_g, s->stream, a,
+                           s->order[c], s->bstart[c], (int)j, s->gstep, 0, store);
+        if (s->prof) HIPCHK(s, hipEventRecord(e1, s->stream));
+        for (int pass = 1; pass < npass[j]; ++pass) {
+            hipLaunchKernelGGL(k_grid<true>, dim3(node_blocks), dim3(kBlock), 0, s->stream, a,
+                               s->bstart[c], (int)j, pass);
+            hipLaunchKernelGGL(k_g2p2g<true>, dim3(s->n_tiles), dim3(kBlock), lds_g, s->stream, a,
+                               s->order[c], s->bstart[c], (int)j, s->gstep, pass, store);
+        }
+        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s->stream, a, s->bstart[c ^ 1], limit_slots);
+        hipLaunchKernelGGL(k_scatter, dim3(s->n_tiles), dim3(kBlock), 0, s->stream, a, s->order[c],
+                           s->bstart[c], s->order[c ^ 1]);
+        HIPCHK(s, hipGetLastError());
+        s->sbin = c;
+        s->cur ^= 1;
+        s->gstep += 1;
+    }
+    s->pending = true;
+    std::memcpy(s->pos, s->tpos, sizeof(s->pos));
+    std::memcpy(s->quat, s->tquat, sizeof(s->quat));
+    s->substeps += n_substeps;
+    return SIM_OK;
+}
+
+int sim_synchronize(sim_t* s) {
+    if (!s) return SIM_EINVAL;
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    return check_device_error(s);
+}
+
+static int surface_raster(sim_t* s, float* out, int W, int H, int on_device, int mode) {
+    if (!s || !out || W < 1 || H < 1) return fail(s, SIM_EINVAL, "bad raster arguments");
+    const long long npix = (long long)W * H;
+    if (npix > s->surf_cap) {
+        if (s->surf_acc) (void)hipFree(s->surf_acc);
+        s->surf_acc = nullptr;
+        HIPCHK(s, hipMalloc(&s->surf_acc, npix * sizeof(float4)));
+        s->surf_cap = npix;
+    }
+    const long long nout = npix * (mode == 0 ? 1 : 3);
+    float* dst = out;
+    if (!on_device) {
+        if (nout > s->out_cap) {
+            if (s->out_tmp) (void)hipFree(s->out_tmp);
+            s->out_tmp = nullptr;
+            HIPCHK(s, hipMalloc(&s->out_tmp, nout * sizeof(float)));
+            s->out_cap = nout;
+        }
+        dst = s->out_tmp;
+    }
+    KArgs a = kargs(s);
+    SurfArgs sa;
+    sa.W = W; sa.H = H; sa.Nx = s->P.cells[0]; sa.Ny = s->P.cells[1]; sa.m = s->m;
+    sa.pad_l = s->P.pad_lateral; sa.pad_b = s->P.pad_bottom;
+    sa.pitch_x = (double)s->P.cells[0] / (double)W;
+    sa.pitch_y = (double)s->P.cells[1] / (double)H;
+    sa.dx = (float)s->P.dx;
+    sa.n = s->n;
+    sa.rest_r = s->surf_rest;
+    sa.acc = s->surf_acc;
+    hipLaunchKernelGGL(k_fill, dim3(std::min<long long>((npix * 4 + 255) / 256, 4096)), dim3(256), 0, s->stream,
+                       reinterpret_cast<float*>(s->surf_acc), npix * 4, 0.0f);
+    hipLaunchKernelGGL(k_surface_accum, dim3((unsigned)((s->n + 255) / 256)), dim3(256), 0, s->stream, a, sa);
+    hipLaunchKernelGGL(k_surface_finish, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, s->stream,
+                       s->surf_acc, (int)npix, (float)(s->P.cells[2] * s->P.dx), mode, dst);
+    HIPCHK(s, hipGetLastError());
+    if (!on_device) {
+        HIPCHK(s, hipMemcpyAsync(out, dst, nout * sizeof(float), hipMemcpyDeviceToHost, s->stream));
+        HIPCHK(s, hipStreamSynchronize(s->stream));
+        return check_device_error(s);
+    }
+    return SIM_OK;
+}
+
+int sim_surface_heightmap(sim_t* s, float* out, int32_t W, int32_t H, int32_t out_on_device) {
+    return surface_raster(s, out, W, H, out_on_device, 0);
+}
+
+int sim_surface_displacement(sim_t* s, float* out, int32_t W, int32_t H, int32_t out_on_device) {
+    return surface_raster(s, out, W, H, out_on_device, 1);
+}
+
+int sim_get_stats(sim_t* s, sim_stats* out) {
+    if (!s || !out) return fail(s, SIM_EINVAL, "null argument");
+    DevState d;
+    HIPCHK(s, hipMemcpyAsync(&d, s->st, sizeof(d), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    std::memset(out, 0, sizeof(*out));
+    out->substeps = s->substeps;
+    out->steps = (int64_t)d.steps;
+    out->passes = (int64_t)d.passes;
+    out->limit_hits = (int64_t)d.limit_hits;
+    out->last_r = d.last_r;
+    out->device_error = d.error;
+    std::memcpy(out->pose, s->pos, sizeof(s->pos));
+    std::memcpy(out->pose + 3, s->quat, sizeof(s->quat));
+    double R[9];
+    quat_matrix(s->quat, R);
+    body_to_world(s->pos, R, s->po_body, out->xo);
+    out->calib_particle = s->e;
+    return d.error ? fail(s, SIM_ENUMERIC, "device error latched") : SIM_OK;
+}
+
+int sim_num_particles(const sim_t* s, int64_t* n) {
+    if (!s || !n) return SIM_EINVAL;
+    *n = s->n;
+    return SIM_OK;
+}
+
+int sim_grid_dims(const sim_t* s, int32_t nodes[3]) {
+    if (!s || !nodes) return SIM_EINVAL;
+    for (int q = 0; q < 3; ++q) nodes[q] = s->nn[q];
+    return SIM_OK;
+}
+
+int sim_read_particles(sim_t* s, double* x, float* v, float* C, float* G) {
+    if (!s) return SIM_EINVAL;
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    const size_t n = (size_t)s->n;
+    if (x) {
+        std::vector<uint32_t> cells(n);
+        std::vector<float> f(3 * n);
+        HIPCHK(s, hipMemcpy(cells.data(), s->cell, n * 4, hipMemcpyDeviceToHost));
+        HIPCHK(s, hipMemcpy(f.data(), s->soa + (size_t)F0 * n, 3 * n * 4, hipMemcpyDeviceToHost));
+        const int off[3] = {s->P.pad_lateral, s->P.pad_lateral, s->P.pad_bottom};
+        for (size_t id = 0; id < n; ++id) {
+            const uint32_t c = cells[id];
+            const int cc[3] = {(int)(c & 1023), (int)((c >> 10) & 1023), (int)((c >> 20) & 1023)};
+            for (int a = 0; a < 3; ++a)
+                x[3 * id + a] = ((double)(cc[a] - off[a]) + (double)f[a * n + id]) * s->P.dx;
+        }
+    }
+    auto planes = [&](float* dst, int p0, int np) -> int {
+        std::vector<float> tmp((size_t)np * n);
+        HIPCHK(s, hipMemcpy(tmp.data(), s->soa + (size_t)p0 * n, (size_t)np * n * 4, hipMemcpyDeviceToHost));
+        for (size_t id = 0; id < n; ++id)
+            for (int q = 0; q < np; ++q) dst[np * id + q] = tmp[(size_t)q * n + id];
+        return SIM_OK;
+    };
+    int rc;
+    if (v && (rc = planes(v, V0, 3))) return rc;
+    if (C && (rc = planes(C, C0, 9))) return rc;
+    if (G && (rc = planes(G, G0, 9))) return rc;
+    return check_device_error(s);
+}
+
+int sim_write_particles(sim_t* s, const double* x, const float* v, const float* C, const float* G) {
+    if (!s) return SIM_EINVAL;
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    const size_t n = (size_t)s->n;
+    if (x) {
+        std::vector<uint32_t> cells(n);
+        std::vector<float> f(3 * n);
+        const int off[3] = {s->P.pad_lateral, s->P.pad_lateral, s->P.pad_bottom};
+        for (size_t id = 0; id < n; ++id) {
+            int cc[3];
+            for (int a = 0; a < 3; ++a) {
+                const double g = x[3 * id + a] / s->P.dx;
+                double fl = std::floor(g);
+                float fr = (float)(g - fl);
+                if (fr >= 1.0f) { fr = 0.0f; fl += 1.0; }
+                cc[a] = (int)fl + off[a];
+                if (!std::isfinite(g) || cc[a] < 1 || cc[a] > s->nn[a] - 3)
+                    return fail(s, SIM_EINVAL, "particle position outside the grid");
+                f[a * n + id] = fr;
+            }
+            cells[id] = pack_cell(cc);
+        }
+        HIPCHK(s, hipMemcpy(s->cell, cells.data(), n * 4, hipMemcpyHostToDevice));
+        HIPCHK(s, hipMemcpy(s->soa + (size_t)F0 * n, f.data(), 3 * n * 4, hipMemcpyHostToDevice));
+    }
+    auto planes = [&](const float* src, int p0, int np) -> int {
+        std::vector<float> tmp((size_t)np * n);
+        for (size_t id = 0; id < n; ++id)
+            for (int q = 0; q < np; ++q) tmp[(size_t)q * n + id] = src[np * id + q];
+        HIPCHK(s, hipMemcpy(s->soa + (size_t)p0 * n, tmp.data(), (size_t)np * n * 4, hipMemcpyHostToDevice));
+        return SIM_OK;
+    };
+    int rc;
+    if (v && (rc = planes(v, V0, 3))) return rc;
+    if (C && (rc = planes(C, C0, 9))) return rc;
+    if (G && (rc = planes(G, G0, 9))) return rc;
+    return refresh_binning(s);
+}
+
+int sim_read_rest(sim_t* s, double* X, uint8_t* flags) {
+    if (!s) return SIM_EINVAL;
+    const sim_params& P = s->P;
+    const int m = s->m;
+    if (X) {
+        for (long long id = 0; id < s->n; ++id) {
+            const long long cid = id / P.ppc;
+            const int sub = (int)(id % P.ppc);
+            const int ci[3] = {(int)(cid % P.cells[0]), (int)((cid / P.cells[0]) % P.cells[1]),
+                               (int)(cid / ((long long)P.cells[0] * P.cells[1]))};
+            const int si[3] = {sub % m, (sub / m) % m, sub / (m * m)};
+            for (int a = 0; a < 3; ++a)
+                X[3 * id + a] = ((double)ci[a] + (double)rest_offset(P.seed, id, a, si[a], m)) * P.dx;
+        }
+    }
+    if (flags) HIPCHK(s, hipMemcpy(flags, s->flags, s->n, hipMemcpyDeviceToHost));
+    return SIM_OK;
+}
+
+int sim_debug_keep_grid(sim_t* s, int32_t on) {
+    if (!s) return SIM_EINVAL;
+    if (on && !s->dbgM) {
+        HIPCHK(s, hipMalloc(&s->dbgM, (size_t)s->n_nodes * sizeof(float)));
+        HIPCHK(s, hipMalloc(&s->dbgMG, (size_t)s->n_nodes * 3 * sizeof(float)));
+    }
+    s->keep_grid = on != 0;
+    return SIM_OK;
+}
+
+int sim_read_grid(sim_t* s, float* M, float* MG, float* V) {
+    if (!s) return SIM_EINVAL;
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    if ((M || MG) && !s->dbgM) return fail(s, SIM_ESTATE, "grid keeping is off");
+    const size_t nn = (size_t)s->n_nodes;
+    if (M) HIPCHK(s, hipMemcpy(M, s->dbgM, nn * 4, hipMemcpyDeviceToHost));
+    if (MG) HIPCHK(s, hipMemcpy(MG, s->dbgMG, nn * 12, hipMemcpyDeviceToHost));
+    if (V) {
+        std::vector<float4> tmp(nn);
+        HIPCHK(s, hipMemcpy(tmp.data(), s->gridV, nn * sizeof(float4), hipMemcpyDeviceToHost));
+        for (size_t k = 0; k < nn; ++k) { V[3 * k] = tmp[k].x; V[3 * k + 1] = tmp[k].y; V[3 * k + 2] = tmp[k].z; }
+    }
+    return SIM_OK;
+}
+
+int sim_debug_force_passes(sim_t* s, const int32_t* passes, int32_t n) {
+    if (!s || n < 0 || (n > 0 && !passes)) return SIM_EINVAL;
+    for (int i = 0; i < n; ++i)
+        if (passes[i] < 1 || passes[i] > 32) return fail(s, SIM_EINVAL, "forced passes must be in [1, 32]");
+    s->forced.assign(passes, passes + n);
+    s->forced_pos = 0;
+    return SIM_OK;
+}
+
+int sim_profile(sim_t* s, int32_t on) {
+    if (!s) return SIM_EINVAL;
+    s->prof = on != 0;
+    return SIM_OK;
+}
+
+int sim_profile_read(sim_t* s, double* ms_total, int64_t* launches) {
+    if (!s || !ms_total || !launches) return SIM_EINVAL;
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    for (size_t k = 0; k + 1 < s->ev_used; k += 2) {
+        float ms = 0.f;
+        HIPCHK(s, hipEventElapsedTime(&ms, s->ev_pool[k], s->ev_pool[k + 1]));
+        s->prof_ms += ms;
+        s->prof_launches += 1;
+    }
+    s->ev_used = 0;
+    *ms_total = s->prof_ms;
+    *launches = s->prof_launches;
+    s->prof_ms = 0.0;
+    s->prof_launches = 0;
+    return SIM_OK;
+}
+
+const char* sim_last_error(const sim_t* s) { return s ? s->err.c_str() : "null handle"; }
+
+}  // extern "C"

@@ -1,0 +1,589 @@
+// impm_kernels.hip -- gfx950 kernels of one IMPM step (arXiv 2405.02914,
+// Sec. III-A): per-tile particle-to-grid into LDS (Eq. 1-4), a node kernel that
+// sums the tile partials and applies Eq. 5, the sticking contact and the
+// boundary rule, and a fused per-tile kernel that runs the relative-rest test of
+// Algorithm 1, grid-to-particle (Eq. 6-7), the commit (Eq. 8-9) and the
+// particle-to-grid transfer of the next exchange.  Particles are binned by tile
+// with a counting sort every committed step.
+#include "impm_device.h"
+
+namespace impm {
+
+__device__ __forceinline__ int tile_linear(const KArgs& a, const int tc[3]) {
+    return (tc[2] * a.NT[1] + tc[1]) * a.NT[0] + tc[0];
+}
+__device__ __forceinline__ void tile_coords(const KArgs& a, int t, int tc[3]) {
+    tc[0] = t % a.NT[0];
+    tc[1] = (t / a.NT[0]) % a.NT[1];
+    tc[2] = t / (a.NT[0] * a.NT[1]);
+}
+
+// Particle-to-grid contribution of one particle (Eq. 1-4) into an LDS node
+// block whose first node is `org` and whose size is `fp`.  Masses are carried
+// as weights (every particle has the same m_p): node (W, P) with
+// W = sum w, P = sum w (v + B d), d = X_i - x_p in cell units and
+// B = dx C - (4 h / (rho dx)) tau, so that M_i = m_p W and MG_i = m_p P.
+__device__ __forceinline__ bool p2g_particle(float4* acc, const int org[3], const int fp[3],
+                                             const int cell[3], const float f[3],
+                                             const float v[3], const float C[9],
+                                             const float G[9], bool with_stress,
+                                             const KArgs& a) {
+    int base[3];
+    float fx[3], w[3][3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) bspline_axis(cell[q], f[q], base[q], fx[q], w[q]);
+    int l[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        l[q] = base[q] - org[q];
+        if (l[q] < 0 || l[q] + 2 >= fp[q]) return false;
+    }
+    float B[9];
+    if (with_stress) {
+        float tau[9];
+        kirchhoff(G, a.mu2, a.lam, tau);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) B[k] = a.dx * C[k] - a.kst * tau[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) B[k] = a.dx * C[k];
+    }
+#pragma unroll
+    for (int cz = 0; cz < 3; ++cz) {
+        const float dz = (float)cz - fx[2];
+#pragma unroll
+        for (int cy = 0; cy < 3; ++cy) {
+            const float dy = (float)cy - fx[1];
+            const float wyz = w[1][cy] * w[2][cz];
+            const int row = ((l[2] + cz) * fp[1] + (l[1] + cy)) * fp[0] + l[0];
+#pragma unroll
+            for (int cx = 0; cx < 3; ++cx) {
+                const float dxx = (float)cx - fx[0];
+                const float wt = w[0][cx] * wyz;
+                const float px = v[0] + (B[0] * dxx + B[1] * dy + B[2] * dz);
+                const float py = v[1] + (B[3] * dxx + B[4] * dy + B[5] * dz);
+                const float pz = v[2] + (B[6] * dxx + B[7] * dy + B[8] * dz);
+                float* nd = reinterpret_cast<float*>(acc + row + cx);
+                atomicAdd(nd + 0, wt);
+                atomicAdd(nd + 1, wt * px);
+                atomicAdd(nd + 2, wt * py);
+                atomicAdd(nd + 3, wt * pz);
+            }
+        }
+    }
+    return true;
+}
+
+__device__ __forceinline__ void load_particle(const KArgs& a, long long id, int cell[3],
+                                              float f[3]) {
+    unpack_cell(a.cell[id], cell);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) f[q] = a.soa[(size_t)(F0 + q) * a.n + id];
+}
+
+__global__ void k_fill(float* p, long long n, float val) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        p[i] = val;
+}
+
+// Stand-alone particle-to-grid of the first exchange of a step (after creation or
+// an external state write): one block per tile, partials to the tile's scratch.
+__global__ __launch_bounds__(kBlock) void k_p2g(KArgs a, const uint32_t* __restrict__ order,
+                                                const uint32_t* __restrict__ bstart) {
+    extern __shared__ float4 lds[];
+    float4* acc = lds;
+    const int t = blockIdx.x;
+    const uint32_t s0 = bstart[t], cnt = bstart[t + 1] - s0;
+    if (cnt == 0) return;
+    int tc[3];
+    tile_coords(a, t, tc);
+    int org[3];
+    for (int q = 0; q < 3; ++q) org[q] = tc[q] * a.T[q] - 2;
+    for (int k = threadIdx.x; k < a.FPvol; k += kBlock) acc[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < cnt; i += kBlock) {
+        const long long id = order[s0 + i];
+        int cell[3];
+        float f[3], v[3], C[9], G[9];
+        load_particle(a, id, cell, f);
+        for (int q = 0; q < 3; ++q) v[q] = a.soa[(size_t)(V0 + q) * a.n + id];
+        for (int q = 0; q < 9; ++q) C[q] = a.soa[(size_t)(C0 + q) * a.n + id];
+        for (int q = 0; q < 9; ++q) G[q] = a.soa[(size_t)(G0 + q) * a.n + id];
+        if (!p2g_particle(acc, org, a.FP, cell, f, v, C, G, true, a)) atomicOr(&a.st->error, DEV_CFL);
+    }
+    __syncthreads();
+    float4* dst = a.scratch + (size_t)t * a.FPvol;
+    for (int k = threadIdx.x; k < a.FPvol; k += kBlock) dst[k] = acc[k];
+}
+
+// Node kernel (EXTRA: passes after the first of a step, which run only while
+// the relative-rest test fails): sum the partials of the tiles whose P2G footprint covers the node
+// (fixed order), V = MG / M (Eq. 5), nodes inside the indenter take its rigid
+// velocity (relative rest with the object), boundary nodes get zero velocity.
+template <bool EXTRA>
+__global__ __launch_bounds__(kBlock) void k_grid(KArgs a, const uint32_t* __restrict__ bstart,
+                                                 int step, int pass) {
+    if (a.st->finished[pass]) return;
+    const long long nid = blockIdx.x * (long long)kBlock + threadIdx.x;
+    const long long n_nodes = (long long)a.nn[0] * a.nn[1] * a.nn[2];
+    if (nid >= n_nodes) return;
+    const int i = (int)(nid % a.nn[0]);
+    const int j = (int)((nid / a.nn[0]) % a.nn[1]);
+    const int k = (int)(nid / ((long long)a.nn[0] * a.nn[1]));
+    const int nd[3] = {i, j, k};
+    int lo[3], hi[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const int m = nd[q] - a.T[q] - 2;
+        lo[q] = m <= 0 ? 0 : (m + a.T[q] - 1) / a.T[q];
+        hi[q] = min((nd[q] + 2) / a.T[q], a.NT[q] - 1);
+    }
+    float W = 0.f, P0 = 0.f, P1 = 0.f, P2 = 0.f;
+    for (int tz = lo[2]; tz <= hi[2]; ++tz)
+        for (int ty = lo[1]; ty <= hi[1]; ++ty)
+            for (int tx = lo[0]; tx <= hi[0]; ++tx) {
+                const int t = (tz * a.NT[1] + ty) * a.NT[0] + tx;
+                if (bstart[t + 1] == bstart[t]) continue;
+                const int l0 = i - (tx * a.T[0] - 2), l1 = j - (ty * a.T[1] - 2),
+                          l2 = k - (tz * a.T[2] - 2);
+                const float4 c = a.scratch[(size_t)t * a.FPvol + (l2 * a.FP[1] + l1) * a.FP[0] + l0];
+                W += c.x; P0 += c.y; P1 += c.z; P2 += c.w;
+            }
+    float V[3] = {0.f, 0.f, 0.f};
+    if (W > 0.f) {
+        const float inv = 1.0f / W;
+        V[0] = P0 * inv; V[1] = P1 * inv; V[2] = P2 * inv;
+        const StepPose& sp = a.poses[step];
+        if (node_inside(a, sp, i, j, k)) rigid_velocity(a, sp, i, j, k, V);
+        const bool bnd = i < a.band || i > a.nn[0] - 1 - a.band || j < a.band ||
+                         j > a.nn[1] - 1 - a.band || k > a.nn[2] - 1 - a.band || k <= a.pad_b;
+        if (bnd) V[0] = V[1] = V[2] = 0.f;
+    }
+    a.gridV[nid] = make_float4(V[0], V[1], V[2], W);
+    if (a.dbgM) {
+        a.dbgM[nid] = a.mp * W;
+        a.dbgMG[3 * nid + 0] = a.mp * P0;
+        a.dbgMG[3 * nid + 1] = a.mp * P1;
+        a.dbgMG[3 * nid + 2] = a.mp * P2;
+    }
+}
+
+// Fused per-tile kernel of one exchange pass.
+//  1. The relative-rest test of Algorithm 1 on the calibration particle x_e:
+//     every block evaluates it from the same grid velocities in the same order,
+//     so all blocks take the same decision without a grid-wide barrier.
+//  2. Grid-to-particle (Eq. 6-7) and the bottom rule.
+//  3. If the step ends here: commit F and x (Eq. 8-9), bin the particle for the
+//     next step, and transfer it to the grid of the next step's first pass;
+//     otherwise transfer it (same x and F, new v and C) to the next pass's grid.
+template <bool EXTRA>
+__global__ __launch_bounds__(kBlock) void k_g2p2g(KArgs a, const uint32_t* __restrict__ order,
+                                                  const uint32_t* __restrict__ bstart, int step,
+                                                  long long gstep, int pass, int store_vc) {
+    if (a.st->finished[pass]) {
+        // carry the flag to the next pass slot so that every later pass of the
+        // step is skipped as well
+        if (blockIdx.x == 0 && threadIdx.x == 0) a.st->finished[pass + 1] = 1;
+        return;
+    }
+    extern __shared__ float4 lds[];
+    float4* acc = lds;                       // FPvol
+    float4* gv = lds + a.FPvol;              // FGvol
+    float* ve_part = reinterpret_cast<float*>(gv + a.FGvol);   // 27 * 3
+    int* wc = reinterpret_cast<int*>(ve_part + 81);            // kWaves * 27
+    int* running = wc + kWaves * kDirs;                        // 27
+    int* sh = running + kDirs;                                 // [0] = final
+
+    const int tid = threadIdx.x;
+    const int t = blockIdx.x;
+    const StepPose& sp = a.poses[step];
+    const int par = (int)(gstep & 1);
+
+    // ---- 1. relative-rest decision
+    if (tid < 27) {
+        int cell[3];
+        unpack_cell(a.st->xe_cell[par], cell);
+        int base[3];
+        float fx[3], w[3][3];
+        for (int q = 0; q < 3; ++q) bspline_axis(cell[q], a.st->xe_f[par][q], base[q], fx[q], w[q]);
+        const int cx = tid % 3, cy = (tid / 3) % 3, cz = tid / 9;
+        const long long nid = ((long long)(base[2] + cz) * a.nn[1] + (base[1] + cy)) * a.nn[0] +
+                              (base[0] + cx);
+        const float4 V = a.gridV[nid];
+        const float wt = w[0][cx] * w[1][cy] * w[2][cz];
+        ve_part[3 * tid + 0] = wt * V.x;
+        ve_part[3 * tid + 1] = wt * V.y;
+        ve_part[3 * tid + 2] = wt * V.z;
+    }
+    if (tid < kDirs) running[tid] = 0;
+    if (tid < kWaves * kDirs) wc[tid] = 0;
+    __syncthreads();
+    if (tid == 0) {
+        float ve0 = 0.f, ve1 = 0.f;
+        for (int q = 0; q < 27; ++q) { ve0 += ve_part[3 * q]; ve1 += ve_part[3 * q + 1]; }
+        int fin;
+        double r = -1.0;
+        bool limit = false;
+        if (sp.forced > 0) {
+            fin = pass + 1 >= sp.forced;
+        } else if (a.mode == 1) {
+            fin = 1;
+        } else if (sp.gnorm <= 1e-9) {
+            fin = 1;
+            r = 0.0;
+        } else {
+            const double d0 = (double)ve0 - sp.vot[0], d1 = (double)ve1 - sp.vot[1];
+            r = sqrt(d0 * d0 + d1 * d1) / sp.gnorm;
+            fin = r <= a.rest_threshold;
+            if (!fin && pass + 1 >= a.rest_limit) { fin = 1; limit = true; }
+        }
+        sh[0] = fin;
+        if (t == 0) {
+            a.st->finished[pass + 1] = fin;
+            if (r >= 0.0) a.st->last_r = r;
+            if (fin) {
+                a.st->steps += 1;
+                a.st->passes += (unsigned long long)(pass + 1);
+                if (limit) a.st->limit_hits += 1;
+            }
+        }
+    }
+    __syncthreads();
+    const bool fin = sh[0] != 0;
+
+    const uint32_t s0 = bstart[t], cnt = bstart[t + 1] - s0;
+    if (cnt == 0) {
+        if (fin && tid < kDirs) a.dircount[(size_t)t * kDirs + tid] = 0;
+        return;
+    }
+    int tc[3];
+    tile_coords(a, t, tc);
+    int orgP[3], orgG[3];
+    for (int q = 0; q < 3; ++q) {
+        orgP[q] = tc[q] * a.T[q] - 2;
+        orgG[q] = tc[q] * a.T[q] - 1;
+    }
+    // ---- stage the grid velocities of the tile's G2P footprint, clear the P2G block
+    for (int kk = tid; kk < a.FGvol; kk += kBlock) {
+        const int lx = kk % a.FG[0], ly = (kk / a.FG[0]) % a.FG[1], lz = kk / (a.FG[0] * a.FG[1]);
+        const int gx = orgG[0] + lx, gy = orgG[1] + ly, gz = orgG[2] + lz;
+        float4 V = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (gx >= 0 && gy >= 0 && gz >= 0 && gx < a.nn[0] && gy < a.nn[1] && gz < a.nn[2])
+            V = a.gridV[((long long)gz * a.nn[1] + gy) * a.nn[0] + gx];
+        gv[kk] = V;
+    }
+    for (int kk = tid; kk < a.FPvol; kk += kBlock) acc[kk] = make_float4(0.f, 0.f, 0.f, 0.f);
+    __syncthreads();
+
+    const bool with_stress = fin || a.stress_each_pass;
+    const int lane = tid & 63, wid = tid >> 6;
+    int err = 0;
+    for (uint32_t i0 = 0; i0 < cnt; i0 += kBlock) {
+        const uint32_t i = i0 + tid;
+        int dir = -1;
+        if (i < cnt) {
+            const long long id = order[s0 + i];
+            int cell[3];
+            float f[3];
+            load_particle(a, id, cell, f);
+            // ---- 2. grid-to-particle (Eq. 6-7)
+            int base[3];
+            float fx[3], w[3][3];
+            for (int q = 0; q < 3; ++q) bspline_axis(cell[q], f[q], base[q], fx[q], w[q]);
+            int l[3];
+            bool ok = true;
+            for (int q = 0; q < 3; ++q) {
+                l[q] = base[q] - orgG[q];
+                ok = ok && l[q] >= 0 && l[q] + 2 < a.FG[q];
+            }
+            float v[3] = {0.f, 0.f, 0.f}, C[9];
+            for (int q = 0; q < 9; ++q) C[q] = 0.f;
+            if (ok) {
+#pragma unroll
+                for (int cz = 0; cz < 3; ++cz)
+#pragma unroll
+                    for (int cy = 0; cy < 3; ++cy) {
+                        const float wyz = w[1][cy] * w[2][cz];
+                        const int row = ((l[2] + cz) * a.FG[1] + (l[1] + cy)) * a.FG[0] + l[0];
+#pragma unroll
+                        for (int cx = 0; cx < 3; ++cx) {
+                            const float4 V = gv[row + cx];
+                            const float wt = w[0][cx] * wyz;
+                            v[0] += wt * V.x; v[1] += wt * V.y; v[2] += wt * V.z;
+                        }
+                    }
+                // C = (4/dx^2) sum w V d^T, evaluated as (4/dx) sum w (V - v) d^T in
+                // cell units (equal because sum w d = 0; less cancellation)
+#pragma unroll
+                for (int cz = 0; cz < 3; ++cz) {
+                    const float dz = (float)cz - fx[2];
+#pragma unroll
+                    for (int cy = 0; cy < 3; ++cy) {
+                        const float dy = (float)cy - fx[1];
+                        const float wyz = w[1][cy] * w[2][cz];
+                        const int row = ((l[2] + cz) * a.FG[1] + (l[1] + cy)) * a.FG[0] + l[0];
+#pragma unroll
+                        for (int cx = 0; cx < 3; ++cx) {
+                            const float dxx = (float)cx - fx[0];
+                            const float4 V = gv[row + cx];
+                            const float wt = w[0][cx] * wyz;
+                            const float u0 = wt * (V.x - v[0]), u1 = wt * (V.y - v[1]),
+                                        u2 = wt * (V.z - v[2]);
+                            C[0] += u0 * dxx; C[1] += u0 * dy; C[2] += u0 * dz;
+                            C[3] += u1 * dxx; C[4] += u1 * dy; C[5] += u1 * dz;
+                            C[6] += u2 * dxx; C[7] += u2 * dy; C[8] += u2 * dz;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 9; ++q) C[q] *= a.c4dx;
+            } else {
+                err |= DEV_CFL;
+            }
+            const uint8_t fl = a.flags[id];
+            if (a.bottom_rule && (fl & FLAG_BOTTOM)) v[2] = 0.f;
+            float G[9];
+            for (int q = 0; q < 9; ++q) G[q] = a.soa[(size_t)(G0 + q) * a.n + id];
+            if (fin) {
+                // ---- 3. commit: F <- (I + h C) F, x <- x + h v
+                float Gn[9];
+#pragma unroll
+                for (int r = 0; r < 3; ++r)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        Gn[3 * r + c] = G[3 * r + c] +
+                                        a.h * (C[3 * r + c] + (C[3 * r] * G[c] + C[3 * r + 1] * G[3 + c] +
+                                                               C[3 * r + 2] * G[6 + c]));
+                bool finite = true;
+                for (int q = 0; q < 9; ++q) { G[q] = Gn[q]; finite = finite && isfinite(Gn[q]); }
+                for (int q = 0; q < 3; ++q) finite = finite && isfinite(v[q]);
+                if (!finite) err |= DEV_NONFINITE;
+                if (!(1.0f + det_minus_one(G) > 0.0f)) err |= DEV_DETF;
+                int perr = finite ? 0 : DEV_NONFINITE;
+                int moved[3];
+                float nfr[3];
+                for (int q = 0; q < 3; ++q) {
+                    const float step_cells = a.h_over_dx * v[q];
+                    if (!(fabsf(step_cells) < 1.0f)) perr |= DEV_CFL;
+                    float nf = f[q] + step_cells;
+                    const float fl0 = floorf(nf);
+                    int c = cell[q] + (int)fl0;
+                    nf -= fl0;
+                    if (nf >= 1.0f) { nf -= 1.0f; c += 1; }
+                    moved[q] = c;
+                    nfr[q] = nf;
+                }
+                bool inside = true;
+                for (int q = 0; q < 3; ++q) inside = inside && moved[q] >= 1 && moved[q] <= a.nn[q] - 3;
+                if (!inside) perr |= DEV_CFL;
+                err |= perr;
+                if (perr == 0) {
+                    for (int q = 0; q < 3; ++q) { cell[q] = moved[q]; f[q] = nfr[q]; }
+                    a.cell[id] = pack_cell(cell);
+                    for (int q = 0; q < 3; ++q) a.soa[(size_t)(F0 + q) * a.n + id] = f[q];
+                    for (int q = 0; q < 9; ++q) a.soa[(size_t)(G0 + q) * a.n + id] = G[q];
+                }
+                if (id == a.e) {
+                    a.st->xe_cell[par ^ 1] = pack_cell(cell);
+                    for (int q = 0; q < 3; ++q) a.st->xe_f[par ^ 1][q] = f[q];
+                }
+                int nt[3];
+                dir = 0;
+                for (int q = 2; q >= 0; --q) {
+                    nt[q] = cell[q] / a.T[q];
+                    int dd = nt[q] - tc[q];
+                    dd = dd < -1 ? -1 : (dd > 1 ? 1 : dd);
+                    dir = dir * 3 + (dd + 1);
+                }
+            }
+            if (store_vc && fin) {
+                for (int q = 0; q < 3; ++q) a.soa[(size_t)(V0 + q) * a.n + id] = v[q];
+                for (int q = 0; q < 9; ++q) a.soa[(size_t)(C0 + q) * a.n + id] = C[q];
+            }
+            // ---- transfer to the grid of the next exchange
+            if (!p2g_particle(acc, orgP, a.FP, cell, f, v, C, G, with_stress, a)) err |= DEV_CFL;
+        }
+        if (fin) {
+            // deterministic rank of this particle among the block's particles that
+            // move to the same neighbour tile (binned order of the next step)
+            int my_rank = 0;
+            unsigned long long act = __ballot(dir >= 0);
+            while (act) {
+                const int leader = __ffsll((long long)act) - 1;
+                const int d0 = __shfl(dir, leader);
+                const unsigned long long m = __ballot(dir == d0);
+                if (dir == d0) my_rank = __popcll(m & ((1ull << lane) - 1ull));
+                if (lane == leader) wc[wid * kDirs + d0] = __popcll(m);
+                act &= ~m;
+            }
+            __syncthreads();
+            if (dir >= 0) {
+                int base_r = running[dir];
+                for (int w2 = 0; w2 < wid; ++w2) base_r += wc[w2 * kDirs + dir];
+                a.dirrank[s0 + i] = ((uint32_t)(base_r + my_rank) << 5) | (uint32_t)dir;
+            }
+            __syncthreads();
+            if (tid < kDirs) {
+                int s = 0;
+                for (int w2 = 0; w2 < kWaves; ++w2) { s += wc[w2 * kDirs + tid]; wc[w2 * kDirs + tid] = 0; }
+                running[tid] += s;
+            }
+            __syncthreads();
+        }
+    }
+    if (err) atomicOr(&a.st->error, err);
+    __syncthreads();
+    float4* dst = a.scratch + (size_t)t * a.FPvol;
+    for (int kk = tid; kk < a.FPvol; kk += kBlock) dst[kk] = acc[kk];
+    if (fin && tid < kDirs) a.dircount[(size_t)t * kDirs + tid] = running[tid];
+}
+
+// Counting sort, scan part: new tile sizes from the per-(tile, direction)
+// counts, their exclusive prefix sum, and the destination offset of every
+// (source tile, direction) run.  One block; resets the per-step loop flags.
+__global__ __launch_bounds__(1024) void k_scan(KArgs a, uint32_t* __restrict__ bstart_next,
+                                               int limit_slots) {
+    __shared__ uint32_t part[1024];
+    __shared__ uint32_t carry;
+    const int tid = threadIdx.x;
+    if (tid == 0) carry = 0;
+    if (tid < limit_slots) a.st->finished[tid] = 0;
+    __syncthreads();
+    for (int t0 = 0; t0 < a.n_tiles; t0 += 1024) {
+        const int u = t0 + tid;
+        uint32_t cnt = 0;
+        int tc[3];
+        if (u < a.n_tiles) {
+            tile_coords(a, u, tc);
+            for (int d = 0; d < kDirs; ++d) {
+                const int dd[3] = {d % 3 - 1, (d / 3) % 3 - 1, d / 9 - 1};
+                int sc[3];
+                bool ok = true;
+                for (int q = 0; q < 3; ++q) {
+                    sc[q] = tc[q] - dd[q];
+                    ok = ok && sc[q] >= 0 && sc[q] < a.NT[q];
+                }
+                if (ok) cnt += a.dircount[(size_t)tile_linear(a, sc) * kDirs + d];
+            }
+        }
+        part[tid] = cnt;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const uint32_t x = tid >= off ? part[tid - off] : 0;
+            __syncthreads();
+            part[tid] += x;
+            __syncthreads();
+        }
+        const uint32_t excl = carry + part[tid] - cnt;
+        if (u < a.n_tiles) {
+            bstart_next[u] = excl;
+            uint32_t run = excl;
+            for (int d = 0; d < kDirs; ++d) {
+                const int dd[3] = {d % 3 - 1, (d / 3) % 3 - 1, d / 9 - 1};
+                int sc[3];
+                bool ok = true;
+                for (int q = 0; q < 3; ++q) {
+                    sc[q] = tc[q] - dd[q];
+                    ok = ok && sc[q] >= 0 && sc[q] < a.NT[q];
+                }
+                if (ok) {
+                    const size_t src = (size_t)tile_linear(a, sc) * kDirs + d;
+                    a.diroff[src] = run;
+                    run += a.dircount[src];
+                }
+            }
+        }
+        __syncthreads();
+        if (tid == 1023) carry += part[1023];
+        __syncthreads();
+    }
+    if (tid == 0) bstart_next[a.n_tiles] = carry;
+}
+
+// Counting sort, scatter part: every binned position moves its particle id to
+// the next order at offset(source tile, direction) + rank.
+__global__ __launch_bounds__(kBlock) void k_scatter(KArgs a, const uint32_t* __restrict__ order,
+                                                    const uint32_t* __restrict__ bstart,
+                                                    uint32_t* __restrict__ order_next) {
+    const int t = blockIdx.x;
+    const uint32_t s0 = bstart[t], cnt = bstart[t + 1] - s0;
+    for (uint32_t i = threadIdx.x; i < cnt; i += kBlock) {
+        const uint32_t dr = a.dirrank[s0 + i];
+        const uint32_t dst = a.diroff[(size_t)t * kDirs + (dr & 31u)] + (dr >> 5);
+        if (dst < (uint32_t)a.n) order_next[dst] = order[s0 + i];
+        else atomicOr(&a.st->error, DEV_CFL);
+    }
+}
+
+// Surface raster: every surface particle adds its quadratic B-spline weights
+// (pitch = pixel size) and weighted displacement to a W x H accumulator.
+__global__ void k_surface_accum(KArgs a, SurfArgs s) {
+    const long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (id >= a.n) return;
+    if (!(a.flags[id] & FLAG_SURFACE)) return;
+    const int ppc = s.m * s.m * s.m;
+    const long long cell_id = id / ppc;
+    const int sub = (int)(id % ppc);
+    const int ci = (int)(cell_id % s.Nx), cj = (int)((cell_id / s.Nx) % s.Ny);
+    const int ck = (int)(cell_id / ((long long)s.Nx * s.Ny));
+    const int sx = sub % s.m, sy = (sub / s.m) % s.m;
+    const long long sidx = ((long long)cj * s.Nx + ci) * s.m * s.m + sy * s.m + sx;
+    int cell[3];
+    float f[3];
+    load_particle(a, id, cell, f);
+    const int rc[3] = {ci + s.pad_l, cj + s.pad_l, ck + s.pad_b};
+    float u[3];
+    for (int q = 0; q < 3; ++q)
+        u[q] = ((float)(cell[q] - rc[q]) + (f[q] - s.rest_r[3 * sidx + q])) * s.dx;
+    const double px = ((double)(cell[0] - s.pad_l) + (double)f[0]) / s.pitch_x - 0.5;
+    const double py = ((double)(cell[1] - s.pad_l) + (double)f[1]) / s.pitch_y - 0.5;
+    const int bx = (int)floor(px + 0.5) - 1, by = (int)floor(py + 0.5) - 1;
+    const float fx = (float)(px - bx), fy = (float)(py - by);
+    float wx[3], wy[3];
+    {
+        const float a0 = 1.5f - fx, b0 = fx - 1.0f, c0 = fx - 0.5f;
+        wx[0] = 0.5f * a0 * a0; wx[1] = 0.75f - b0 * b0; wx[2] = 0.5f * c0 * c0;
+        const float a1 = 1.5f - fy, b1 = fy - 1.0f, c1 = fy - 0.5f;
+        wy[0] = 0.5f * a1 * a1; wy[1] = 0.75f - b1 * b1; wy[2] = 0.5f * c1 * c1;
+    }
+    for (int cy = 0; cy < 3; ++cy) {
+        const int vy = by + cy;
+        if (vy < 0 || vy >= s.H) continue;
+        for (int cx = 0; cx < 3; ++cx) {
+            const int ux = bx + cx;
+            if (ux < 0 || ux >= s.W) continue;
+            const float wt = wx[cx] * wy[cy];
+            if (wt == 0.f) continue;
+            float* d = reinterpret_cast<float*>(s.acc + (size_t)vy * s.W + ux);
+            atomicAdd(d + 0, wt);
+            atomicAdd(d + 1, wt * u[0]);
+            atomicAdd(d + 2, wt * u[1]);
+            atomicAdd(d + 3, wt * u[2]);
+        }
+    }
+}
+
+__global__ void k_surface_finish(const float4* __restrict__ acc, int npix, float top, int mode,
+                                 float* __restrict__ out) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= npix) return;
+    const float4 c = acc[q];
+    const float inv = c.x > 0.f ? 1.0f / c.x : 0.f;
+    if (mode == 0) {
+        out[q] = top + c.w * inv;
+    } else {
+        out[3 * q + 0] = c.y * inv;
+        out[3 * q + 1] = c.z * inv;
+        out[3 * q + 2] = c.w * inv;
+    }
+}
+
+template __global__ void k_grid<false>(KArgs, const uint32_t*, int, int);
+template __global__ void k_grid<true>(KArgs, const uint32_t*, int, int);
+template __global__ void k_g2p2g<false>(KArgs, const uint32_t*, const uint32_t*, int, long long, int,
+                                        int);
+template __global__ void k_g2p2g<true>(KArgs, const uint32_t*, const uint32_t*, int, long long, int,
+                                       int);
+
+}  // namespace impm

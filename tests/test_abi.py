@@ -1,0 +1,47 @@
+"""The C ABI library loads and exports every entry point include/impm.h
+declares (no device calls: runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "impm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sim_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("sim_create", "sim_set_indenter_pose", "sim_step", "sim_surface_heightmap"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2405_02914_amd import impm
+    if not os.path.exists(impm.LIB_PATH):
+        pytest.fail("libimpm.so is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(impm.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(declared_functions()) <= set(impm.EXPORTS)
+
+
+def test_binding_struct_layouts_match_header():
+    """The ctypes records have the sizes the header's field lists imply."""
+    from paper_2405_02914_amd import impm
+    assert ctypes.sizeof(impm.sim_params) == 12 + 4 + 8 + 8 + 8 * 4 + 4 * 8 + 8 * 2 + 8 + 8 * 2 + 24 + 8 + 56 + 8
+    assert ctypes.sizeof(impm.sim_stats) == 8 * 5 + 8 + 56 + 24 + 8
+
+
+def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
+    from paper_2405_02914_amd import impm
+    monkeypatch.setattr(impm, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(impm, "_lib", None)
+    with pytest.raises(RuntimeError):
+        impm.lib()

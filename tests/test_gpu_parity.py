@@ -1,0 +1,250 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Both sides start from the same seeded inputs (the jittered particle cloud each
+side generates from SplitMix64, or a random state from the workloads module)
+and run the same indenter schedule.  Tolerances:
+  - single configured substep: normwise relative error <= 1e-5 per field
+    (velocity, C, F - I, displacement over the substep);
+  - 100 substeps of config 1: max |x_gpu - x_ref| <= 1e-3 dx;
+  - initial state: bitwise.
+"""
+import numpy as np
+import pytest
+
+from paper_2405_02914_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL_STEP = 1e-5
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2405_02914_amd import impm
+    impm.lib()
+    return impm
+
+
+@pytest.fixture(scope="module")
+def ref(oracle_lib):
+    return oracle_lib
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64); b = np.asarray(b, np.float64)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def both(gpu, ref, p):
+    print(f"[parity] cells={p.cells} dx={p.dx} shape={p.shape} subcycle={p.subcycle}", flush=True)
+    return gpu.Sim(p), ref.OracleSim(p)
+
+
+# Positions are held as an integer cell plus an FP32 offset in [0, 1): each
+# committed step rounds the offset by at most 2^-24 cells, so after a few steps
+# positions agree to ~1e-7 cells plus the velocity error times the step; one
+# substep moves a particle only ~1e-3 cells, so its displacement is compared by
+# absolute position error rather than relative to itself.
+TOL_X_STEP = 1e-5    # cells, one configured substep
+
+
+def compare_states(g, o, x0, label, tol=TOL_STEP, dx=None):
+    xg, vg, Cg, Gg = g.sim_read_particles()
+    xo, vo, Co, Fo = o.state()
+    Go = Fo - np.eye(3)[None]
+    errs = dict(v=rel(vg, vo), C=rel(Cg, Co), G=rel(Gg, Go))
+    xerr = np.abs(xg - xo).max() / dx
+    print(label, {k: f"{e:.2e}" for k, e in errs.items()}, f"max|x| {xerr:.2e} dx",
+          f"disp rel {rel(xg - x0, xo - x0):.2e}", flush=True)
+    for k, e in errs.items():
+        assert e <= tol, (label, k, e)
+    assert xerr <= TOL_X_STEP, (label, "x", xerr)
+    return errs
+
+
+def test_initial_state_bitwise(gpu, ref):
+    p = W.config1()
+    g, o = both(gpu, ref, p)
+    xg, vg, Cg, Gg = g.sim_read_particles()
+    xo, _, _, _ = o.state()
+    assert np.array_equal(xg, xo)
+    assert not vg.any() and not Cg.any() and not Gg.any()
+    Xo, bottom, surface = o.rest()
+    Xg, fl = g.sim_read_rest()
+    assert np.array_equal(Xg, Xo)
+    assert np.array_equal((fl & 1) != 0, bottom) and np.array_equal((fl & 2) != 0, surface)
+    assert g.sim_get_stats()["calib_particle"] == o.calib_particle
+
+
+@pytest.mark.parametrize("cells,tile", [((12, 10, 5), (8, 8, 4)), ((13, 9, 6), (4, 4, 4)),
+                                         ((7, 11, 3), (5, 3, 2))])
+def test_single_substep_from_random_state(gpu, ref, cells, tile):
+    """One substep (sub-cycled twice) of a press from a random state, on grids
+    that span several tiles with ragged edges."""
+    p = W.small_sensor(cells=cells, radius=1.5e-3, subcycle=2)
+    g, o = both(gpu, ref, p)
+    g.sim_set_tile(*tile)
+    X, _, _ = o.rest()
+    x, v, Cm, G = W.random_state(p, X, seed=11)
+    F = np.eye(3)[None] + G.astype(np.float64)
+    o.set_state(x=x, v=v, Cm=Cm, F=F)
+    g.sim_write_particles(x, v, Cm, G)
+    tgt = (p.pose0[0], p.pose0[1], p.pose0[2] - 0.05e-3)
+    g.sim_set_indenter_pose(tgt, (1, 0, 0, 0))
+    o.set_target_pose(tgt, (1, 0, 0, 0))
+    g.sim_step(1)
+    o.step(1)
+    compare_states(g, o, x, f"single substep {cells} tile {tile}", dx=p.dx)
+
+
+def test_grid_after_p2g(gpu, ref):
+    """Grid mass, momentum and velocity of the first exchange (Eq. 1-5)."""
+    p = W.small_sensor(cells=(10, 9, 4), radius=1.5e-3, subcycle=1, mode=W.MODE_PLAIN)
+    g, o = both(gpu, ref, p)
+    X, _, _ = o.rest()
+    x, v, Cm, G = W.random_state(p, X, seed=3)
+    F = np.eye(3)[None] + G.astype(np.float64)
+    o.set_state(x=x, v=v, Cm=Cm, F=F)
+    g.sim_write_particles(x, v, Cm, G)
+    g.sim_debug_keep_grid(True)
+    g.sim_set_indenter_pose(p.pose0[:3], p.pose0[3:])
+    g.sim_step(1)
+    Mg, MGg, Vg = g.sim_read_grid()
+    o.p2g(p.dt)
+    o.grid_update(contact=True, bc=True)
+    Mo, MGo, Vo = o.grid()
+    m = Mo > 0
+    print("grid", rel(Mg, Mo), rel(MGg[m], MGo[m]), rel(Vg[m], Vo[m]), flush=True)
+    assert np.array_equal(Mg > 0, m)
+    assert rel(Mg, Mo) <= 1e-6
+    assert rel(MGg[m], MGo[m]) <= TOL_STEP
+    assert rel(Vg[m], Vo[m]) <= TOL_STEP
+
+
+def test_config1_100_substeps(gpu, ref):
+    """Config 1: sphere r = 4 mm pressed 1 mm over 100 substeps (sub-cycle 2):
+    particle positions within 1e-3 dx of the FP64 oracle; height maps agree."""
+    p = W.config1(subcycle=2)
+    g, o = both(gpu, ref, p)
+    X0, _, _ = o.rest()
+    sched = W.config1_schedule()
+    g.run_schedule(sched)
+    o.run_schedule(sched)
+    xg, vg, Cg, Gg = g.sim_read_particles()
+    xo, vo, Co, Fo = o.state()
+    err = np.abs(xg - xo).max()
+    print(f"config1 100 substeps: max|dx| = {err / p.dx:.3e} dx, v rel {rel(vg, vo):.2e}", flush=True)
+    assert err <= 1e-3 * p.dx
+    st = g.sim_get_stats()
+    oc = o.counters()
+    assert st["steps"] == oc["steps"] == 200 and st["passes"] == oc["passes"]
+    hg = g.sim_surface_heightmap(64, 64)
+    ho = o.surface_heightmap(64, 64)
+    print("heightmap max err", np.abs(hg - ho).max(), flush=True)
+    assert np.abs(hg - ho).max() <= 1e-3 * p.dx
+    dg = g.sim_surface_displacement(32, 32)
+    do = o.surface_displacement(32, 32)
+    assert np.abs(dg - do).max() <= 1e-3 * p.dx
+
+
+def test_slip_and_rotation_with_oracle_pass_schedule(gpu, ref):
+    """Press, then slip with rotation (the IMPM loop iterates).  The pass count
+    per step is a threshold decision taken in FP64 by the oracle and FP32 on the
+    device; the device replays the oracle's schedule so that both integrate the
+    same loop, and the pass counts it would pick itself are checked separately."""
+    p = W.small_sensor(cells=(16, 16, 6), radius=1.5e-3, subcycle=2)
+    c = np.array(p.pose0[:3])
+    segs = [(20, tuple(c + [0, 0, -0.4e-3]), (1, 0, 0, 0)),
+            (30, tuple(c + [0.4e-3, 0, -0.4e-3]), W.quat_about_z(20))]
+    o = ref.OracleSim(p)
+    o.enable_pass_log(10000)
+    o.run_schedule(segs)
+    sched = o.pass_log()
+    assert sched.max() > 1, "the slip phase should need more than one pass somewhere"
+    g = gpu.Sim(p)
+    g.sim_debug_force_passes(sched)
+    g.run_schedule(segs)
+    X0, _, _ = o.rest()
+    xg, vg, _, _ = g.sim_read_particles()
+    xo, vo, _, _ = o.state()
+    err = np.abs(xg - xo).max()
+    print(f"slip+rotate: max|dx| = {err / p.dx:.3e} dx, passes {sched.sum()}", flush=True)
+    assert err <= 1e-3 * p.dx
+    assert g.sim_get_stats()["passes"] == o.counters()["passes"]
+    # free-running device loop: same schedule except where r is near the threshold
+    g2 = gpu.Sim(p)
+    g2.run_schedule(segs)
+    st = g2.sim_get_stats()
+    oc = o.counters()
+    print("free-running device loop", {k: st[k] for k in ("steps", "passes", "limit_hits", "last_r")},
+          "oracle", oc, flush=True)
+    assert st["steps"] == oc["steps"]
+    assert abs(st["passes"] - oc["passes"]) <= 0.1 * oc["passes"]
+    x2 = g2.sim_read_particles()[0]
+    assert np.abs(x2 - xo).max() <= 1e-2 * p.dx
+
+
+def test_rest_is_bitwise_preserved(gpu):
+    p = W.small_sensor(cells=(12, 12, 4), shape=W.SHAPE_NONE, subcycle=2)
+    g = gpu.Sim(p)
+    x0, v0, C0, G0 = g.sim_read_particles()
+    g.sim_set_indenter_pose(p.pose0[:3], p.pose0[3:])
+    g.sim_step(100)
+    x1, v1, C1, G1 = g.sim_read_particles()
+    assert np.array_equal(x0, x1) and not v1.any() and not C1.any() and not G1.any()
+
+
+def test_plain_mode_single_pass(gpu, ref):
+    p = W.small_sensor(cells=(10, 10, 4), radius=1.2e-3, subcycle=2, mode=W.MODE_PLAIN)
+    g, o = both(gpu, ref, p)
+    X0, _, _ = o.rest()
+    segs = [(10, (p.pose0[0] + 0.2e-3, p.pose0[1], p.pose0[2] - 0.3e-3), W.quat_about_z(10))]
+    g.run_schedule(segs); o.run_schedule(segs)
+    xg = g.sim_read_particles()[0]; xo = o.state()[0]
+    assert np.abs(xg - xo).max() <= 1e-3 * p.dx
+    assert g.sim_get_stats()["passes"] == 20
+
+
+def test_device_error_is_latched(gpu):
+    p = W.small_sensor(cells=(6, 6, 3), radius=1.2e-3)
+    g = gpu.Sim(p)
+    x, v, Cm, G = g.sim_read_particles()
+    v[5, 0] = np.nan
+    g.sim_write_particles(x, v, Cm, G)
+    g.sim_set_indenter_pose(p.pose0[:3], p.pose0[3:])
+    g.sim_step(1)
+    with pytest.raises(gpu.SimError) as e:
+        g.sim_synchronize()
+    assert e.value.code == gpu.SIM_ENUMERIC
+
+
+def test_bad_arguments_rejected(gpu):
+    p = W.small_sensor(cells=(6, 6, 3))
+    with pytest.raises(gpu.SimError):
+        gpu.Sim(p.replace(nu=0.5))
+    g = gpu.Sim(p)
+    with pytest.raises(gpu.SimError):
+        g.sim_step(0)
+    with pytest.raises(gpu.SimError):
+        g.sim_set_tile(1, 8, 8)
+
+
+@pytest.mark.slow
+def test_config2_full_size_first_substep(gpu, ref):
+    """Config 2 at full size (4,194,304 particles, 145 x 145 x 43 nodes) in the
+    benchmark's launch configuration: one configured substep (4 executed steps)
+    of the press, compared element by element with the oracle."""
+    p = W.config2(subcycle=4)
+    g, o = both(gpu, ref, p)
+    xo0, _, _, _ = o.state()
+    n, pos, q = W.config2_schedule()[0]
+    # the first substep of the first frame's motion
+    x0, y0, z0 = p.pose0[:3]
+    tgt = (pos[0], pos[1], z0 + (pos[2] - z0) / n)
+    g.sim_set_indenter_pose(tgt, q); g.sim_step(1)
+    o.set_target_pose(tgt, q); o.step(1)
+    compare_states(g, o, xo0, "config2 first substep", dx=p.dx)
