@@ -52,7 +52,7 @@ struct KArgs {
     int T[3];         // tile size in cells
     int NT[3];        // tiles per axis
     int n_tiles;
-    int FP[3];        // P2G footprint (nodes) of a tile: T + 5, origin tile_origin - 2
+    int FP[3];        // P2G footprint (nodes) of a tile: T + 5, origin tile_origin - 2 (LDS: 32 B/node)
     int FG[3];        // G2P footprint (nodes) of a tile: T + 3, origin tile_origin - 1
     int FPvol, FGvol;
     int pad_l, pad_b, band;
@@ -72,8 +72,8 @@ struct KArgs {
     float* dbgM;               // n_nodes or null
     float* dbgMG;              // 3 * n_nodes or null
     uint32_t* dirrank;         // per binned position: rank << 5 | dir
-    uint32_t* dircount;        // n_tiles * 27
-    uint32_t* diroff;          // n_tiles * 27
+    uint32_t* dircount;        // n_tiles * 27: particles of a tile moving in each direction
+    uint32_t* newcnt;          // n_tiles: next step's tile sizes (accumulated)
     DevState* st;
     const StepPose* poses;
 };

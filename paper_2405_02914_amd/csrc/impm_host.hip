@@ -24,7 +24,7 @@ __global__ void k_g2p2g(KArgs a, const uint32_t* order, const uint32_t* bstart, 
                         long long gstep, int pass, int store_vc);
 __global__ void k_scan(KArgs a, uint32_t* bstart_next, int limit_slots);
 __global__ void k_scatter(KArgs a, const uint32_t* order, const uint32_t* bstart,
-                          uint32_t* order_next);
+                          const uint32_t* bstart_next, uint32_t* order_next);
 __global__ void k_surface_accum(KArgs a, SurfArgs s);
 __global__ void k_surface_finish(const float4* acc, int npix, float top, int mode, float* out);
 }  // namespace impm
@@ -54,7 +54,7 @@ struct sim_s {
     int cur = 0;
     uint32_t* dirrank = nullptr;
     uint32_t* dircount = nullptr;
-    uint32_t* diroff = nullptr;
+    uint32_t* newcnt = nullptr;
     float4* scratch = nullptr;
     size_t scratch_cap = 0;   // float4 elements
     float4* gridV = nullptr;
@@ -255,14 +255,14 @@ static KArgs kargs(const sim_t* s) {
     a.dbgMG = s->keep_grid ? s->dbgMG : nullptr;
     a.dirrank = s->dirrank;
     a.dircount = s->dircount;
-    a.diroff = s->diroff;
+    a.newcnt = s->newcnt;
     a.st = s->st;
     a.poses = s->poses;
     return a;
 }
 
 static size_t g2p2g_lds(const KArgs& a) {
-    return (size_t)(a.FPvol + a.FGvol) * sizeof(float4) + 81 * sizeof(float) +
+    return (size_t)(2 * a.FPvol + a.FGvol) * sizeof(float4) + 81 * sizeof(float) +
            (kWaves * kDirs + kDirs + 4) * sizeof(int);
 }
 
@@ -307,11 +307,12 @@ static int alloc_tiles(sim_t* s) {
         HIPCHK(s, hipMalloc(&s->bstart[k], (s->n_tiles + 1) * sizeof(uint32_t)));
     }
     if (s->dircount) (void)hipFree(s->dircount);
-    if (s->diroff) (void)hipFree(s->diroff);
-    s->dircount = s->diroff = nullptr;
+    if (s->newcnt) (void)hipFree(s->newcnt);
+    s->dircount = s->newcnt = nullptr;
     HIPCHK(s, hipMalloc(&s->dircount, (size_t)s->n_tiles * kDirs * sizeof(uint32_t)));
-    HIPCHK(s, hipMalloc(&s->diroff, (size_t)s->n_tiles * kDirs * sizeof(uint32_t)));
+    HIPCHK(s, hipMalloc(&s->newcnt, (size_t)s->n_tiles * sizeof(uint32_t)));
     HIPCHK(s, hipMemset(s->dircount, 0, (size_t)s->n_tiles * kDirs * sizeof(uint32_t)));
+    HIPCHK(s, hipMemset(s->newcnt, 0, (size_t)s->n_tiles * sizeof(uint32_t)));
     if (need > s->scratch_cap) {
         if (s->scratch) (void)hipFree(s->scratch);
         s->scratch = nullptr;
@@ -529,7 +530,7 @@ void sim_destroy(sim_t* s) {
     if (!s) return;
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     void* bufs[] = {s->soa, s->cell, s->flags, s->order[0], s->order[1], s->bstart[0], s->bstart[1],
-                    s->dirrank, s->dircount, s->diroff, s->scratch, s->gridV, s->dbgM, s->dbgMG,
+                    s->dirrank, s->dircount, s->newcnt, s->scratch, s->gridV, s->dbgM, s->dbgMG,
                     s->st, s->poses, s->surf_rest, s->surf_acc, s->out_tmp};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
@@ -557,7 +558,7 @@ int sim_set_tile(sim_t* s, int32_t tx, int32_t ty, int32_t tz) {
     if (!s) return SIM_EINVAL;
     if (tx < 2 || ty < 2 || tz < 2 || tx > 32 || ty > 32 || tz > 32)
         return fail(s, SIM_EINVAL, "tile sizes must be in [2, 32]");
-    const size_t lds = (size_t)((tx + 5) * (ty + 5) * (tz + 5) + (tx + 3) * (ty + 3) * (tz + 3)) *
+    const size_t lds = (size_t)(2 * (tx + 5) * (ty + 5) * (tz + 5) + (tx + 3) * (ty + 3) * (tz + 3)) *
                        sizeof(float4) + 1024;
     if (lds > 160 * 1024) return fail(s, SIM_EINVAL, "tile needs more LDS than a workgroup has");
     HIPCHK(s, hipStreamSynchronize(s->stream));
@@ -604,7 +605,7 @@ int sim_step(sim_t* s, int32_t n_substeps) {
     HIPCHK(s, hipEventRecord(s->stage_ev[b], s->stream));
     KArgs a = kargs(s);
     const size_t lds_g = g2p2g_lds(a);
-    const size_t lds_p = (size_t)a.FPvol * sizeof(float4);
+    const size_t lds_p = (size_t)a.FPvol * 2 * sizeof(float4);
     const int node_blocks = (int)((s->n_nodes + kBlock - 1) / kBlock);
     if (!s->pending) {
         hipLaunchKernelGGL(k_p2g, dim3(s->n_tiles), dim3(kBlock), lds_p, s->stream, a,
@@ -641,7 +642,7 @@ int sim_step(sim_t* s, int32_t n_substeps) {
         }
         hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s->stream, a, s->bstart[c ^ 1], limit_slots);
         hipLaunchKernelGGL(k_scatter, dim3(s->n_tiles), dim3(kBlock), 0, s->stream, a, s->order[c],
-                           s->bstart[c], s->order[c ^ 1]);
+                           s->bstart[c], s->bstart[c ^ 1], s->order[c ^ 1]);
         HIPCHK(s, hipGetLastError());
         s->sbin = c;
         s->cur ^= 1;

@@ -18,16 +18,37 @@ __device__ __forceinline__ void tile_coords(const KArgs& a, int t, int tc[3]) {
     tc[2] = t / (a.NT[0] * a.NT[1]);
 }
 
+// Node sums in LDS are 64-bit fixed point with 2^-32 resolution: a contribution
+// x becomes round(x 2^32) through one FP64 fused multiply-add against the
+// constant 1.5 * 2^52, whose result holds the rounded integer in its low
+// mantissa bits; the constant's own bits are a multiple of 2^51 and drop out of
+// the low 51 bits of the sum, which are sign-extended at the flush (valid for
+// |sum| < 2^18).  Integer adds make the sums exact and independent of order,
+// and LDS integer atomics are several times faster than LDS float atomics.
+constexpr double kFixScale = 4294967296.0;          // 2^32
+constexpr double kFixMagic = 6755399441055744.0;    // 1.5 * 2^52
+
+__device__ __forceinline__ unsigned long long to_fixed(float x) {
+    return (unsigned long long)__double_as_longlong(fma((double)x, kFixScale, kFixMagic));
+}
+__device__ __forceinline__ float from_fixed(unsigned long long a) {
+    const long long v = ((long long)(a << 13)) >> 13;
+    return (float)((double)v * (1.0 / kFixScale));
+}
+
 // Particle-to-grid contribution of one particle (Eq. 1-4) into an LDS node
-// block whose first node is `org` and whose size is `fp`.  Masses are carried
-// as weights (every particle has the same m_p): node (W, P) with
-// W = sum w, P = sum w (v + B d), d = X_i - x_p in cell units and
-// B = dx C - (4 h / (rho dx)) tau, so that M_i = m_p W and MG_i = m_p P.
-__device__ __forceinline__ bool p2g_particle(float4* acc, const int org[3], const int fp[3],
-                                             const int cell[3], const float f[3],
-                                             const float v[3], const float C[9],
-                                             const float G[9], bool with_stress,
-                                             const KArgs& a) {
+// block whose first node is `org` and whose size is `fp` (4 fixed-point sums
+// per node).  Masses are carried as weights (every particle has the same m_p):
+// node (W, P) with W = sum w, P = sum w (v + B d), d = X_i - x_p in cell units
+// and B = dx C - (4 h / (rho dx)) tau, so that M_i = m_p W and MG_i = m_p P.
+// Returns 0, or DEV_CFL when the stencil leaves the block, or DEV_NONFINITE when
+// the particle's terms are not finite or too large for the fixed-point range
+// (the particle then contributes nothing).
+__device__ __forceinline__ int p2g_particle(unsigned long long* acc, const int org[3], const int fp[3],
+                                            const int cell[3], const float f[3],
+                                            const float v[3], const float C[9],
+                                            const float G[9], bool with_stress,
+                                            const KArgs& a) {
     int base[3];
     float fx[3], w[3][3];
 #pragma unroll
@@ -36,7 +57,7 @@ __device__ __forceinline__ bool p2g_particle(float4* acc, const int org[3], cons
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
         l[q] = base[q] - org[q];
-        if (l[q] < 0 || l[q] + 2 >= fp[q]) return false;
+        if (l[q] < 0 || l[q] + 2 >= fp[q]) return DEV_CFL;
     }
     float B[9];
     if (with_stress) {
@@ -48,6 +69,14 @@ __device__ __forceinline__ bool p2g_particle(float4* acc, const int org[3], cons
 #pragma unroll
         for (int k = 0; k < 9; ++k) B[k] = a.dx * C[k];
     }
+    // |w (v + B d)| <= |v| + 4.5 max|B| per node; the node sums stay below the
+    // 2^18 fixed-point range while this bound is below 4096 (NaN fails the test)
+    // (fmaxf drops NaN operands, so finiteness is tested on a plain sum)
+    float mag = fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fabsf(v[2]));
+    float bm = 0.f, sum = v[0] + v[1] + v[2];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) { bm = fmaxf(bm, fabsf(B[k])); sum += B[k]; }
+    if (!isfinite(sum) || !(mag + 4.5f * bm < 4096.0f)) return DEV_NONFINITE;
 #pragma unroll
     for (int cz = 0; cz < 3; ++cz) {
         const float dz = (float)cz - fx[2];
@@ -63,15 +92,22 @@ __device__ __forceinline__ bool p2g_particle(float4* acc, const int org[3], cons
                 const float px = v[0] + (B[0] * dxx + B[1] * dy + B[2] * dz);
                 const float py = v[1] + (B[3] * dxx + B[4] * dy + B[5] * dz);
                 const float pz = v[2] + (B[6] * dxx + B[7] * dy + B[8] * dz);
-                float* nd = reinterpret_cast<float*>(acc + row + cx);
-                atomicAdd(nd + 0, wt);
-                atomicAdd(nd + 1, wt * px);
-                atomicAdd(nd + 2, wt * py);
-                atomicAdd(nd + 3, wt * pz);
+                unsigned long long* nd = acc + 4 * (row + cx);
+                atomicAdd(nd + 0, to_fixed(wt));
+                atomicAdd(nd + 1, to_fixed(wt * px));
+                atomicAdd(nd + 2, to_fixed(wt * py));
+                atomicAdd(nd + 3, to_fixed(wt * pz));
             }
         }
     }
-    return true;
+    return 0;
+}
+
+// Write a tile's fixed-point node sums to its scratch record as floats.
+__device__ __forceinline__ void flush_tile(const unsigned long long* acc, float4* dst, int vol) {
+    for (int k = threadIdx.x; k < vol; k += kBlock)
+        dst[k] = make_float4(from_fixed(acc[4 * k]), from_fixed(acc[4 * k + 1]),
+                             from_fixed(acc[4 * k + 2]), from_fixed(acc[4 * k + 3]));
 }
 
 __device__ __forceinline__ void load_particle(const KArgs& a, long long id, int cell[3],
@@ -92,7 +128,7 @@ __global__ void k_fill(float* p, long long n, float val) {
 __global__ __launch_bounds__(kBlock) void k_p2g(KArgs a, const uint32_t* __restrict__ order,
                                                 const uint32_t* __restrict__ bstart) {
     extern __shared__ float4 lds[];
-    float4* acc = lds;
+    unsigned long long* acc = reinterpret_cast<unsigned long long*>(lds);
     const int t = blockIdx.x;
     const uint32_t s0 = bstart[t], cnt = bstart[t + 1] - s0;
     if (cnt == 0) return;
@@ -100,7 +136,7 @@ __global__ __launch_bounds__(kBlock) void k_p2g(KArgs a, const uint32_t* __restr
     tile_coords(a, t, tc);
     int org[3];
     for (int q = 0; q < 3; ++q) org[q] = tc[q] * a.T[q] - 2;
-    for (int k = threadIdx.x; k < a.FPvol; k += kBlock) acc[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int k = threadIdx.x; k < 4 * a.FPvol; k += kBlock) acc[k] = 0ull;
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < cnt; i += kBlock) {
         const long long id = order[s0 + i];
@@ -110,11 +146,11 @@ __global__ __launch_bounds__(kBlock) void k_p2g(KArgs a, const uint32_t* __restr
         for (int q = 0; q < 3; ++q) v[q] = a.soa[(size_t)(V0 + q) * a.n + id];
         for (int q = 0; q < 9; ++q) C[q] = a.soa[(size_t)(C0 + q) * a.n + id];
         for (int q = 0; q < 9; ++q) G[q] = a.soa[(size_t)(G0 + q) * a.n + id];
-        if (!p2g_particle(acc, org, a.FP, cell, f, v, C, G, true, a)) atomicOr(&a.st->error, DEV_CFL);
+        const int pe = p2g_particle(acc, org, a.FP, cell, f, v, C, G, true, a);
+        if (pe) atomicOr(&a.st->error, pe);
     }
     __syncthreads();
-    float4* dst = a.scratch + (size_t)t * a.FPvol;
-    for (int k = threadIdx.x; k < a.FPvol; k += kBlock) dst[k] = acc[k];
+    flush_tile(acc, a.scratch + (size_t)t * a.FPvol, a.FPvol);
 }
 
 // Node kernel (EXTRA: passes after the first of a step, which run only while
@@ -188,8 +224,8 @@ __global__ __launch_bounds__(kBlock) void k_g2p2g(KArgs a, const uint32_t* __res
         return;
     }
     extern __shared__ float4 lds[];
-    float4* acc = lds;                       // FPvol
-    float4* gv = lds + a.FPvol;              // FGvol
+    unsigned long long* acc = reinterpret_cast<unsigned long long*>(lds);   // 4 * FPvol
+    float4* gv = lds + 2 * a.FPvol;                                         // FGvol
     float* ve_part = reinterpret_cast<float*>(gv + a.FGvol);   // 27 * 3
     int* wc = reinterpret_cast<int*>(ve_part + 81);            // kWaves * 27
     int* running = wc + kWaves * kDirs;                        // 27
@@ -273,7 +309,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p2g(KArgs a, const uint32_t* __res
             V = a.gridV[((long long)gz * a.nn[1] + gy) * a.nn[0] + gx];
         gv[kk] = V;
     }
-    for (int kk = tid; kk < a.FPvol; kk += kBlock) acc[kk] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int kk = tid; kk < 4 * a.FPvol; kk += kBlock) acc[kk] = 0ull;
     __syncthreads();
 
     const bool with_stress = fin || a.stress_each_pass;
@@ -402,7 +438,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p2g(KArgs a, const uint32_t* __res
                 for (int q = 0; q < 9; ++q) a.soa[(size_t)(C0 + q) * a.n + id] = C[q];
             }
             // ---- transfer to the grid of the next exchange
-            if (!p2g_particle(acc, orgP, a.FP, cell, f, v, C, G, with_stress, a)) err |= DEV_CFL;
+            err |= p2g_particle(acc, orgP, a.FP, cell, f, v, C, G, with_stress, a);
         }
         if (fin) {
             // deterministic rank of this particle among the block's particles that
@@ -434,14 +470,27 @@ __global__ __launch_bounds__(kBlock) void k_g2p2g(KArgs a, const uint32_t* __res
     }
     if (err) atomicOr(&a.st->error, err);
     __syncthreads();
-    float4* dst = a.scratch + (size_t)t * a.FPvol;
-    for (int kk = tid; kk < a.FPvol; kk += kBlock) dst[kk] = acc[kk];
-    if (fin && tid < kDirs) a.dircount[(size_t)t * kDirs + tid] = running[tid];
+    flush_tile(acc, a.scratch + (size_t)t * a.FPvol, a.FPvol);
+    if (fin && tid < kDirs) {
+        const uint32_t c = running[tid];
+        a.dircount[(size_t)t * kDirs + tid] = c;
+        if (c) {
+            int dt[3] = {tid % 3 - 1, (tid / 3) % 3 - 1, tid / 9 - 1};
+            int u[3];
+            bool ok = true;
+            for (int q = 0; q < 3; ++q) {
+                u[q] = tc[q] + dt[q];
+                ok = ok && u[q] >= 0 && u[q] < a.NT[q];
+            }
+            if (ok) atomicAdd(&a.newcnt[tile_linear(a, u)], c);
+            else atomicOr(&a.st->error, DEV_CFL);
+        }
+    }
 }
 
-// Counting sort, scan part: new tile sizes from the per-(tile, direction)
-// counts, their exclusive prefix sum, and the destination offset of every
-// (source tile, direction) run.  One block; resets the per-step loop flags.
+// Counting sort, scan part: exclusive prefix sum of the next step's tile sizes
+// (accumulated by the fused kernel), one block; clears the counts and the
+// per-step loop flags for the next step.
 __global__ __launch_bounds__(1024) void k_scan(KArgs a, uint32_t* __restrict__ bstart_next,
                                                int limit_slots) {
     __shared__ uint32_t part[1024];
@@ -453,19 +502,9 @@ __global__ __launch_bounds__(1024) void k_scan(KArgs a, uint32_t* __restrict__ b
     for (int t0 = 0; t0 < a.n_tiles; t0 += 1024) {
         const int u = t0 + tid;
         uint32_t cnt = 0;
-        int tc[3];
         if (u < a.n_tiles) {
-            tile_coords(a, u, tc);
-            for (int d = 0; d < kDirs; ++d) {
-                const int dd[3] = {d % 3 - 1, (d / 3) % 3 - 1, d / 9 - 1};
-                int sc[3];
-                bool ok = true;
-                for (int q = 0; q < 3; ++q) {
-                    sc[q] = tc[q] - dd[q];
-                    ok = ok && sc[q] >= 0 && sc[q] < a.NT[q];
-                }
-                if (ok) cnt += a.dircount[(size_t)tile_linear(a, sc) * kDirs + d];
-            }
+            cnt = a.newcnt[u];
+            a.newcnt[u] = 0;
         }
         part[tid] = cnt;
         __syncthreads();
@@ -475,25 +514,7 @@ __global__ __launch_bounds__(1024) void k_scan(KArgs a, uint32_t* __restrict__ b
             part[tid] += x;
             __syncthreads();
         }
-        const uint32_t excl = carry + part[tid] - cnt;
-        if (u < a.n_tiles) {
-            bstart_next[u] = excl;
-            uint32_t run = excl;
-            for (int d = 0; d < kDirs; ++d) {
-                const int dd[3] = {d % 3 - 1, (d / 3) % 3 - 1, d / 9 - 1};
-                int sc[3];
-                bool ok = true;
-                for (int q = 0; q < 3; ++q) {
-                    sc[q] = tc[q] - dd[q];
-                    ok = ok && sc[q] >= 0 && sc[q] < a.NT[q];
-                }
-                if (ok) {
-                    const size_t src = (size_t)tile_linear(a, sc) * kDirs + d;
-                    a.diroff[src] = run;
-                    run += a.dircount[src];
-                }
-            }
-        }
+        if (u < a.n_tiles) bstart_next[u] = carry + part[tid] - cnt;
         __syncthreads();
         if (tid == 1023) carry += part[1023];
         __syncthreads();
@@ -501,16 +522,47 @@ __global__ __launch_bounds__(1024) void k_scan(KArgs a, uint32_t* __restrict__ b
     if (tid == 0) bstart_next[a.n_tiles] = carry;
 }
 
-// Counting sort, scatter part: every binned position moves its particle id to
-// the next order at offset(source tile, direction) + rank.
+// Counting sort, scatter part: the particles of tile t that move in direction
+// d go to next-order positions bstart_next[t + d] + (particles that entered
+// t + d from the directions before d, in a fixed order) + rank.
 __global__ __launch_bounds__(kBlock) void k_scatter(KArgs a, const uint32_t* __restrict__ order,
                                                     const uint32_t* __restrict__ bstart,
+                                                    const uint32_t* __restrict__ bstart_next,
                                                     uint32_t* __restrict__ order_next) {
+    __shared__ uint32_t off[kDirs];
     const int t = blockIdx.x;
     const uint32_t s0 = bstart[t], cnt = bstart[t + 1] - s0;
-    for (uint32_t i = threadIdx.x; i < cnt; i += kBlock) {
+    if (cnt == 0) return;
+    const int tid = threadIdx.x;
+    if (tid < kDirs) {
+        int tc[3], u[3];
+        tile_coords(a, t, tc);
+        const int dd[3] = {tid % 3 - 1, (tid / 3) % 3 - 1, tid / 9 - 1};
+        bool ok = true;
+        for (int q = 0; q < 3; ++q) {
+            u[q] = tc[q] + dd[q];
+            ok = ok && u[q] >= 0 && u[q] < a.NT[q];
+        }
+        uint32_t o = 0;
+        if (ok) {
+            o = bstart_next[tile_linear(a, u)];
+            for (int d2 = 0; d2 < tid; ++d2) {
+                const int e2[3] = {d2 % 3 - 1, (d2 / 3) % 3 - 1, d2 / 9 - 1};
+                int sc[3];
+                bool ok2 = true;
+                for (int q = 0; q < 3; ++q) {
+                    sc[q] = u[q] - e2[q];
+                    ok2 = ok2 && sc[q] >= 0 && sc[q] < a.NT[q];
+                }
+                if (ok2) o += a.dircount[(size_t)tile_linear(a, sc) * kDirs + d2];
+            }
+        }
+        off[tid] = o;
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < cnt; i += kBlock) {
         const uint32_t dr = a.dirrank[s0 + i];
-        const uint32_t dst = a.diroff[(size_t)t * kDirs + (dr & 31u)] + (dr >> 5);
+        const uint32_t dst = off[dr & 31u] + (dr >> 5);
         if (dst < (uint32_t)a.n) order_next[dst] = order[s0 + i];
         else atomicOr(&a.st->error, DEV_CFL);
     }
