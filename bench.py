@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=4, help="oracle executed steps timed")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--tile", default=None, help="tile cells tx,ty,tz[,threads] of the binned order")
     return ap.parse_args()
 
 
@@ -121,12 +122,16 @@ def main():
     # warm-up on a throw-away sensor (allocation, code load, caches)
     if args.warmup:
         w = impm.Sim(p)
+        if args.tile:
+            w.sim_set_tile(*[int(v) for v in args.tile.split(",")])
         run_frames(w, segs, 0, args.warmup, hm)
         w.sim_synchronize()
         w.close()
         del w
 
     sim = impm.Sim(p)
+    if args.tile:
+        sim.sim_set_tile(*[int(v) for v in args.tile.split(",")])
     sim.sim_profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -164,7 +169,7 @@ def main():
         "config": {"workload": "IMPM sensor 128x128x32 cells dx 0.25 mm, 4194304 particles, capsule "
                                "press 1.5 mm then slip 2 mm + rotate 30 deg, 256x256 height map "
                                "every 50 substeps",
-                   "particles": n, "subcycle": SUBCYCLE, "executed_steps": steps_exec,
+                   "particles": n, "subcycle": SUBCYCLE, "tile": args.tile or "8,4,4", "executed_steps": steps_exec,
                    "passes": st["passes"], "limit_hits": st["limit_hits"],
                    "particle_substeps_per_s": n * args.steps / wall,
                    "particle_passes_per_s": n * st["passes"] / wall},

@@ -154,9 +154,11 @@ int sim_read_grid(sim_t* s, float* M, float* MG, float* V);
  * exchanges each (parity runs near the relative-rest threshold). */
 int sim_debug_force_passes(sim_t* s, const int32_t* passes, int32_t n);
 
-/* Tile shape (cells per axis) of the binned particle order; call before the
- * first sim_step or after sim_write_particles.  Default 8 x 8 x 4. */
+/* Tile shape (cells per axis) of the binned particle order and the threads per
+ * block of the tile kernels (sim_set_tile: 256).  Only the shapes compiled into
+ * the library are accepted (SIM_EINVAL lists them).  Default 8 x 4 x 4 / 256. */
 int sim_set_tile(sim_t* s, int32_t tx, int32_t ty, int32_t tz);
+int sim_set_tile_threads(sim_t* s, int32_t tx, int32_t ty, int32_t tz, int32_t threads);
 
 /* Time every first-pass fused exchange kernel (grid-to-particle, commit,
  * particle-to-grid) with HIP events on the handle's stream (on != 0).

@@ -52,9 +52,6 @@ struct KArgs {
     int T[3];         // tile size in cells
     int NT[3];        // tiles per axis
     int n_tiles;
-    int FP[3];        // P2G footprint (nodes) of a tile: T + 5, origin tile_origin - 2 (LDS: 32 B/node)
-    int FG[3];        // G2P footprint (nodes) of a tile: T + 3, origin tile_origin - 1
-    int FPvol, FGvol;
     int pad_l, pad_b, band;
     int mode, bottom_rule, rest_limit, stress_each_pass;
     int shape;
@@ -86,6 +83,21 @@ struct SurfArgs {
     const float* rest_r;         // 3 per surface particle: in-cell rest offsets
     float4* acc;                 // H*W (w, w ux, w uy, w uz)
 };
+
+// Launchers of the tile kernels for one compiled tile shape.
+struct TileOps {
+    int T[3];
+    int threads;               // threads per block of the particle kernels
+    int pvol;                  // nodes of a tile's particle-to-grid block (scratch record)
+    size_t lds_g2p2g;
+    void (*p2g)(const KArgs& a, const uint32_t* order, const uint32_t* bstart, hipStream_t st);
+    void (*grid)(const KArgs& a, const uint32_t* bstart, int step, int pass, bool extra, int blocks,
+                 hipStream_t st);
+    void (*g2p2g)(const KArgs& a, const uint32_t* order, const uint32_t* bstart, int step,
+                  long long gstep, int pass, int store_vc, bool extra, hipStream_t st);
+};
+extern const TileOps kTileOps[];
+extern const int kNumTileOps;
 
 __host__ __device__ __forceinline__ void unpack_cell(uint32_t c, int o[3]) {
     o[0] = c & 1023; o[1] = (c >> 10) & 1023; o[2] = (c >> 20) & 1023;
@@ -121,10 +133,15 @@ __device__ __forceinline__ float det_minus_one(const float Y[9]) {
     return tr + m2 + d3;
 }
 
+// Each Newton step squares the error, so once an update is below 1e-4 of the
+// size of G the next iterate is accurate to FP32 precision relative to F - R;
+// the loop stops after that update (at most 10 steps).
 __device__ __forceinline__ void polar_rotation_minus_identity(const float G[9], float Q[9]) {
+    float gs = 0.0f;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) Q[k] = G[k];
-    for (int it = 0; it < 12; ++it) {
+    for (int k = 0; k < 9; ++k) { Q[k] = G[k]; gs = fmaxf(gs, fabsf(G[k])); }
+    const float tol = 1e-4f * gs;
+    for (int it = 0; it < 10; ++it) {
         const float tr = Q[0] + Q[4] + Q[8];
         float cof[9];
         cof[0] = Q[4] * Q[8] - Q[5] * Q[7];
@@ -143,15 +160,14 @@ __device__ __forceinline__ void polar_rotation_minus_identity(const float G[9], 
         K[0] = tr - Q[0] + cof[0] - d; K[1] = -Q[3] + cof[1];      K[2] = -Q[6] + cof[2];
         K[3] = -Q[1] + cof[3];      K[4] = tr - Q[4] + cof[4] - d; K[5] = -Q[7] + cof[5];
         K[6] = -Q[2] + cof[6];      K[7] = -Q[5] + cof[7];      K[8] = tr - Q[8] + cof[8] - d;
-        float diff = 0.0f, mag = 0.0f;
+        float diff = 0.0f;
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
             const float nq = 0.5f * (Q[k] + K[k] * inv);
             diff = fmaxf(diff, fabsf(nq - Q[k]));
-            mag = fmaxf(mag, fabsf(nq));
             Q[k] = nq;
         }
-        if (diff <= 1e-7f * fmaxf(mag, 1e-30f) || diff < 1e-30f) break;
+        if (diff <= tol) break;
     }
 }
 

@@ -16,12 +16,6 @@
 
 namespace impm {
 __global__ void k_fill(float* p, long long n, float val);
-__global__ void k_p2g(KArgs a, const uint32_t* order, const uint32_t* bstart);
-template <bool EXTRA>
-__global__ void k_grid(KArgs a, const uint32_t* bstart, int step, int pass);
-template <bool EXTRA>
-__global__ void k_g2p2g(KArgs a, const uint32_t* order, const uint32_t* bstart, int step,
-                        long long gstep, int pass, int store_vc);
 __global__ void k_scan(KArgs a, uint32_t* bstart_next, int limit_slots);
 __global__ void k_scatter(KArgs a, const uint32_t* order, const uint32_t* bstart,
                           const uint32_t* bstart_next, uint32_t* order_next);
@@ -41,8 +35,9 @@ struct sim_s {
     int nn[3] = {0, 0, 0};
     long long n_nodes = 0;
     double mu = 0, lam = 0, Vp = 0, mp = 0;
-    // tiles
-    int T[3] = {8, 8, 4};
+    // tiles (an entry of the compiled tile-shape table)
+    int tile_idx = 3;            // 8 x 4 x 4 cells, 256 threads
+    int T[3] = {8, 4, 4};
     int NT[3] = {0, 0, 0};
     int n_tiles = 0;
     // device buffers
@@ -214,12 +209,8 @@ static KArgs kargs(const sim_t* s) {
         a.nn[q] = s->nn[q];
         a.T[q] = s->T[q];
         a.NT[q] = s->NT[q];
-        a.FP[q] = s->T[q] + 5;
-        a.FG[q] = s->T[q] + 3;
     }
     a.n_tiles = s->n_tiles;
-    a.FPvol = a.FP[0] * a.FP[1] * a.FP[2];
-    a.FGvol = a.FG[0] * a.FG[1] * a.FG[2];
     a.pad_l = P.pad_lateral;
     a.pad_b = P.pad_bottom;
     a.band = P.band;
@@ -261,18 +252,15 @@ static KArgs kargs(const sim_t* s) {
     return a;
 }
 
-static size_t g2p2g_lds(const KArgs& a) {
-    return (size_t)(2 * a.FPvol + a.FGvol) * sizeof(float4) + 81 * sizeof(float) +
-           (kWaves * kDirs + kDirs + 4) * sizeof(int);
-}
-
 // Host-side counting sort of the particles by tile (stable in id order).
-static int rebin_host(sim_t* s, const std::vector<uint32_t>& cells) {
+static int rebin_host(sim_t* s, const std::vector<uint32_t>& cells, const std::vector<float>& offs) {
     std::vector<uint32_t> cnt(s->n_tiles + 1, 0), tile(s->n);
     for (long long id = 0; id < s->n; ++id) {
+        // tile of the stencil base node floor(x - 1/2)
         const uint32_t c = cells[id];
-        const int cx = c & 1023, cy = (c >> 10) & 1023, cz = (c >> 20) & 1023;
-        const int t = ((cz / s->T[2]) * s->NT[1] + cy / s->T[1]) * s->NT[0] + cx / s->T[0];
+        int b[3] = {(int)(c & 1023) - 1, (int)((c >> 10) & 1023) - 1, (int)((c >> 20) & 1023) - 1};
+        for (int q = 0; q < 3; ++q) b[q] += offs[(size_t)q * s->n + id] >= 0.5f ? 1 : 0;
+        const int t = ((b[2] / s->T[2]) * s->NT[1] + b[1] / s->T[1]) * s->NT[0] + b[0] / s->T[0];
         tile[id] = t;
         cnt[t + 1]++;
     }
@@ -299,8 +287,7 @@ static int set_xe_snapshot(sim_t* s, uint32_t cell, const float f[3]) {
 static int alloc_tiles(sim_t* s) {
     for (int q = 0; q < 3; ++q) s->NT[q] = (s->nn[q] - 1 + s->T[q] - 1) / s->T[q];
     s->n_tiles = s->NT[0] * s->NT[1] * s->NT[2];
-    const size_t fpvol = (size_t)(s->T[0] + 5) * (s->T[1] + 5) * (s->T[2] + 5);
-    const size_t need = fpvol * s->n_tiles;
+    const size_t need = (size_t)kTileOps[s->tile_idx].pvol * s->n_tiles;
     for (int k = 0; k < 2; ++k) {
         if (s->bstart[k]) (void)hipFree(s->bstart[k]);
         s->bstart[k] = nullptr;
@@ -322,18 +309,22 @@ static int alloc_tiles(sim_t* s) {
     return SIM_OK;
 }
 
-static int read_cells(sim_t* s, std::vector<uint32_t>& cells) {
+static int read_cells(sim_t* s, std::vector<uint32_t>& cells, std::vector<float>& offs) {
     cells.resize(s->n);
+    offs.resize((size_t)3 * s->n);
     HIPCHK(s, hipMemcpyAsync(cells.data(), s->cell, s->n * 4, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipMemcpyAsync(offs.data(), s->soa + (size_t)F0 * s->n, (size_t)3 * s->n * 4,
+                             hipMemcpyDeviceToHost, s->stream));
     HIPCHK(s, hipStreamSynchronize(s->stream));
     return SIM_OK;
 }
 
 static int refresh_binning(sim_t* s) {
     std::vector<uint32_t> cells;
-    int rc = read_cells(s, cells);
+    std::vector<float> offs;
+    int rc = read_cells(s, cells, offs);
     if (rc) return rc;
-    rc = rebin_host(s, cells);
+    rc = rebin_host(s, cells, offs);
     if (rc) return rc;
     uint32_t ce;
     float fe[3];
@@ -518,7 +509,10 @@ int sim_create(const sim_params* p, void* hip_stream, sim_t** out) {
     if (hipMalloc(&s->surf_rest, srest.size() * sizeof(float)) != hipSuccess) return bail(SIM_ENOMEM);
     if (hipMemcpy(s->surf_rest, srest.data(), srest.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
         return bail(SIM_EHIP);
-    if (rebin_host(s, cells) != SIM_OK) return bail(SIM_EHIP);
+    {
+        std::vector<float> offs(host.begin() + (size_t)F0 * n, host.begin() + (size_t)(F0 + 3) * n);
+        if (rebin_host(s, cells, offs) != SIM_OK) return bail(SIM_EHIP);
+    }
     const float fe[3] = {host[(size_t)F0 * n + s->e], host[(size_t)(F0 + 1) * n + s->e],
                          host[(size_t)(F0 + 2) * n + s->e]};
     if (set_xe_snapshot(s, cells[s->e], fe) != SIM_OK) return bail(SIM_EHIP);
@@ -555,14 +549,23 @@ int sim_set_indenter_pose(sim_t* s, const double pos[3], const double quat_wxyz[
 }
 
 int sim_set_tile(sim_t* s, int32_t tx, int32_t ty, int32_t tz) {
+    return sim_set_tile_threads(s, tx, ty, tz, 256);
+}
+
+int sim_set_tile_threads(sim_t* s, int32_t tx, int32_t ty, int32_t tz, int32_t threads) {
     if (!s) return SIM_EINVAL;
-    if (tx < 2 || ty < 2 || tz < 2 || tx > 32 || ty > 32 || tz > 32)
-        return fail(s, SIM_EINVAL, "tile sizes must be in [2, 32]");
-    const size_t lds = (size_t)(2 * (tx + 5) * (ty + 5) * (tz + 5) + (tx + 3) * (ty + 3) * (tz + 3)) *
-                       sizeof(float4) + 1024;
-    if (lds > 160 * 1024) return fail(s, SIM_EINVAL, "tile needs more LDS than a workgroup has");
+    int idx = -1;
+    std::string avail;
+    for (int k = 0; k < kNumTileOps; ++k) {
+        const int* T = kTileOps[k].T;
+        if (T[0] == tx && T[1] == ty && T[2] == tz && kTileOps[k].threads == threads) idx = k;
+        avail += " " + std::to_string(T[0]) + "x" + std::to_string(T[1]) + "x" + std::to_string(T[2]) + "/" +
+                 std::to_string(kTileOps[k].threads);
+    }
+    if (idx < 0) return fail(s, SIM_EINVAL, "tile shape not compiled in; available:" + avail);
     HIPCHK(s, hipStreamSynchronize(s->stream));
-    s->T[0] = tx; s->T[1] = ty; s->T[2] = tz;
+    s->tile_idx = idx;
+    for (int q = 0; q < 3; ++q) s->T[q] = kTileOps[idx].T[q];
     int rc = alloc_tiles(s);
     if (rc) return rc;
     return refresh_binning(s);
@@ -604,12 +607,10 @@ int sim_step(sim_t* s, int32_t n_substeps) {
     HIPCHK(s, hipMemcpyAsync(s->poses, poses, N * sizeof(StepPose), hipMemcpyHostToDevice, s->stream));
     HIPCHK(s, hipEventRecord(s->stage_ev[b], s->stream));
     KArgs a = kargs(s);
-    const size_t lds_g = g2p2g_lds(a);
-    const size_t lds_p = (size_t)a.FPvol * 2 * sizeof(float4);
+    const TileOps& ops = kTileOps[s->tile_idx];
     const int node_blocks = (int)((s->n_nodes + kBlock - 1) / kBlock);
     if (!s->pending) {
-        hipLaunchKernelGGL(k_p2g, dim3(s->n_tiles), dim3(kBlock), lds_p, s->stream, a,
-                           s->order[s->cur], s->bstart[s->cur]);
+        ops.p2g(a, s->order[s->cur], s->bstart[s->cur], s->stream);
         HIPCHK(s, hipGetLastError());
         s->sbin = s->cur;
     }
@@ -618,8 +619,7 @@ int sim_step(sim_t* s, int32_t n_substeps) {
         const int c = s->cur;
         const int store = j == N - 1 ? 1 : 0;
         // the partials were written under the binning of the pass that made them
-        hipLaunchKernelGGL(k_grid<false>, dim3(node_blocks), dim3(kBlock), 0, s->stream, a,
-                           s->bstart[s->sbin], (int)j, 0);
+        ops.grid(a, s->bstart[s->sbin], (int)j, 0, false, node_blocks, s->stream);
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (s->prof) {
             while (s->ev_pool.size() < s->ev_used + 2) {
@@ -631,14 +631,11 @@ int sim_step(sim_t* s, int32_t n_substeps) {
             e1 = s->ev_pool[s->ev_used++];
             HIPCHK(s, hipEventRecord(e0, s->stream));
         }
-        hipLaunchKernelGGL(k_g2p2g<false>, dim3(s->n_tiles), dim3(kBlock), lds_g, s->stream, a,
-                           s->order[c], s->bstart[c], (int)j, s->gstep, 0, store);
+        ops.g2p2g(a, s->order[c], s->bstart[c], (int)j, s->gstep, 0, store, false, s->stream);
         if (s->prof) HIPCHK(s, hipEventRecord(e1, s->stream));
         for (int pass = 1; pass < npass[j]; ++pass) {
-            hipLaunchKernelGGL(k_grid<true>, dim3(node_blocks), dim3(kBlock), 0, s->stream, a,
-                               s->bstart[c], (int)j, pass);
-            hipLaunchKernelGGL(k_g2p2g<true>, dim3(s->n_tiles), dim3(kBlock), lds_g, s->stream, a,
-                               s->order[c], s->bstart[c], (int)j, s->gstep, pass, store);
+            ops.grid(a, s->bstart[c], (int)j, pass, true, node_blocks, s->stream);
+            ops.g2p2g(a, s->order[c], s->bstart[c], (int)j, s->gstep, pass, store, true, s->stream);
         }
         hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s->stream, a, s->bstart[c ^ 1], limit_slots);
         hipLaunchKernelGGL(k_scatter, dim3(s->n_tiles), dim3(kBlock), 0, s->stream, a, s->order[c],

@@ -18,47 +18,71 @@ __device__ __forceinline__ void tile_coords(const KArgs& a, int t, int tc[3]) {
     tc[2] = t / (a.NT[0] * a.NT[1]);
 }
 
-// Node sums in LDS are 64-bit fixed point with 2^-32 resolution: a contribution
-// x becomes round(x 2^32) through one FP64 fused multiply-add against the
-// constant 1.5 * 2^52, whose result holds the rounded integer in its low
-// mantissa bits; the constant's own bits are a multiple of 2^51 and drop out of
-// the low 51 bits of the sum, which are sign-extended at the flush (valid for
-// |sum| < 2^18).  Integer adds make the sums exact and independent of order,
-// and LDS integer atomics are several times faster than LDS float atomics.
-constexpr double kFixScale = 4294967296.0;          // 2^32
+// Node sums in LDS are 64-bit fixed point with 2^-32 resolution.  A contribution
+// y (already scaled by 2^32, which is exact) becomes round(y) through one FP64
+// add of the constant 1.5 * 2^52: the sum holds the rounded integer in its low
+// mantissa bits, and the constant's own bits are a multiple of 2^51, so they drop
+// out of the low 51 bits of the accumulated sum, which are sign-extended at the
+// flush (valid for |sum| < 2^18).  Integer adds make the node sums exact and
+// independent of order, and LDS integer atomics are several times faster than
+// LDS float atomics on this chip.
+constexpr float kFixScaleF = 4294967296.0f;         // 2^32
+constexpr double kFixScale = 4294967296.0;
 constexpr double kFixMagic = 6755399441055744.0;    // 1.5 * 2^52
 
-__device__ __forceinline__ unsigned long long to_fixed(float x) {
-    return (unsigned long long)__double_as_longlong(fma((double)x, kFixScale, kFixMagic));
+__device__ __forceinline__ unsigned long long to_fixed_scaled(float y, double magic) {
+    return (unsigned long long)__double_as_longlong((double)y + magic);
 }
 __device__ __forceinline__ float from_fixed(unsigned long long a) {
     const long long v = ((long long)(a << 13)) >> 13;
     return (float)((double)v * (1.0 / kFixScale));
 }
 
-// Particle-to-grid contribution of one particle (Eq. 1-4) into an LDS node
-// block whose first node is `org` and whose size is `fp` (4 fixed-point sums
-// per node).  Masses are carried as weights (every particle has the same m_p):
-// node (W, P) with W = sum w, P = sum w (v + B d), d = X_i - x_p in cell units
-// and B = dx C - (4 h / (rho dx)) tau, so that M_i = m_p W and MG_i = m_p P.
-// Returns 0, or DEV_CFL when the stencil leaves the block, or DEV_NONFINITE when
-// the particle's terms are not finite or too large for the fixed-point range
-// (the particle then contributes nothing).
-__device__ __forceinline__ int p2g_particle(unsigned long long* acc, const int org[3], const int fp[3],
-                                            const int cell[3], const float f[3],
-                                            const float v[3], const float C[9],
-                                            const float G[9], bool with_stress,
-                                            const KArgs& a) {
+// Compile-time tile geometry.  A tile holds the particles whose stencil base
+// node floor(x - 1/2) lies in its TX x TY x TZ block starting at `origin`: its
+// grid-to-particle block covers nodes [origin, origin + T + 1] per axis, and
+// its particle-to-grid block [origin - 1, origin + T + 2] (a particle may move
+// its base by one node in the step before it is re-binned).  NB threads per
+// block.
+//
+// The LDS planes of the particle-to-grid block use padded pitches: an odd row
+// pitch and a plane pitch of 9 mod 16 (in 64-bit words), so that the nodes one
+// atomic instruction of a wave touches (a row of cells, two y and two z bases)
+// spread over the 32 banks.
+template <int TX, int TY, int TZ, int NB>
+struct Tile {
+    static constexpr int T0 = TX, T1 = TY, T2 = TZ, NT = NB;
+    static constexpr int PX = TX + 4, PY = TY + 4, PZ = TZ + 4, PVOL = PX * PY * PZ;
+    static constexpr int SY = PX | 1;
+    static constexpr int SZ = SY * PY + ((9 - (SY * PY) % 16) + 16) % 16;
+    static constexpr int AVOL = SZ * PZ;          // words per LDS plane (>= PVOL)
+    static constexpr int GX = TX + 2, GY = TY + 2, GZ = TZ + 2, GVOL = GX * GY * GZ;
+    static constexpr size_t LDS_P2G = (size_t)4 * AVOL * 8;
+    static constexpr int NW = NB / 64;
+    static constexpr size_t LDS_G2P2G = LDS_P2G + (size_t)GVOL * 16 + 81 * 4 + (NW * kDirs + kDirs + 4) * 4;
+};
+
+// Particle-to-grid contribution of one particle (Eq. 1-4) into the LDS node
+// block `acc` whose first node is `org`: four planes (W, Px, Py, Pz) of PVOL
+// fixed-point sums; the planar layout puts neighbouring nodes on different LDS
+// banks.  Masses are carried as weights (every particle has the same m_p): node
+// (W, P) with W = sum w, P = sum w (v + B d), d = X_i - x_p in cell units and
+// B = dx C - (4 h / (rho dx)) tau, so that M_i = m_p W and MG_i = m_p P.  The
+// velocity term is separable: v + B d = (v + B_.2 dz) + B_.1 dy + B_.0 dx.
+// Returns 0, or DEV_CFL when the stencil leaves the block, or DEV_NONFINITE
+// when the particle's terms are not finite or too large for the fixed-point
+// range (the particle then contributes nothing).
+template <class TL>
+__device__ __forceinline__ int p2g_particle(unsigned long long* acc, const int org[3], const int cell[3],
+                                            const float f[3], const float v[3], const float C[9],
+                                            const float G[9], bool with_stress, const KArgs& a) {
     int base[3];
     float fx[3], w[3][3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) bspline_axis(cell[q], f[q], base[q], fx[q], w[q]);
-    int l[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        l[q] = base[q] - org[q];
-        if (l[q] < 0 || l[q] + 2 >= fp[q]) return DEV_CFL;
-    }
+    const int l0 = base[0] - org[0], l1 = base[1] - org[1], l2 = base[2] - org[2];
+    if (l0 < 0 || l0 + 2 >= TL::PX || l1 < 0 || l1 + 2 >= TL::PY || l2 < 0 || l2 + 2 >= TL::PZ)
+        return DEV_CFL;
     float B[9];
     if (with_stress) {
         float tau[9];
@@ -70,33 +94,42 @@ __device__ __forceinline__ int p2g_particle(unsigned long long* acc, const int o
         for (int k = 0; k < 9; ++k) B[k] = a.dx * C[k];
     }
     // |w (v + B d)| <= |v| + 4.5 max|B| per node; the node sums stay below the
-    // 2^18 fixed-point range while this bound is below 4096 (NaN fails the test)
-    // (fmaxf drops NaN operands, so finiteness is tested on a plain sum)
+    // fixed-point range while this bound is below 4096 m/s.  fmaxf drops NaN
+    // operands, so finiteness is tested on a plain sum.
     float mag = fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fabsf(v[2]));
     float bm = 0.f, sum = v[0] + v[1] + v[2];
 #pragma unroll
     for (int k = 0; k < 9; ++k) { bm = fmaxf(bm, fabsf(B[k])); sum += B[k]; }
     if (!isfinite(sum) || !(mag + 4.5f * bm < 4096.0f)) return DEV_NONFINITE;
+
+    float ax[3][3], by[3][3], cz[3][3], wx[3];
 #pragma unroll
-    for (int cz = 0; cz < 3; ++cz) {
-        const float dz = (float)cz - fx[2];
+    for (int c = 0; c < 3; ++c) {
+        const float dxa = (float)c - fx[0], dyb = (float)c - fx[1], dzc = (float)c - fx[2];
 #pragma unroll
-        for (int cy = 0; cy < 3; ++cy) {
-            const float dy = (float)cy - fx[1];
-            const float wyz = w[1][cy] * w[2][cz];
-            const int row = ((l[2] + cz) * fp[1] + (l[1] + cy)) * fp[0] + l[0];
+        for (int r = 0; r < 3; ++r) {
+            ax[c][r] = B[3 * r] * dxa;
+            by[c][r] = B[3 * r + 1] * dyb;
+            cz[c][r] = v[r] + B[3 * r + 2] * dzc;
+        }
+        wx[c] = w[0][c] * kFixScaleF;
+    }
+    const double magic = kFixMagic;
+    unsigned long long* row0 = acc + l2 * TL::SZ + l1 * TL::SY + l0;
 #pragma unroll
-            for (int cx = 0; cx < 3; ++cx) {
-                const float dxx = (float)cx - fx[0];
-                const float wt = w[0][cx] * wyz;
-                const float px = v[0] + (B[0] * dxx + B[1] * dy + B[2] * dz);
-                const float py = v[1] + (B[3] * dxx + B[4] * dy + B[5] * dz);
-                const float pz = v[2] + (B[6] * dxx + B[7] * dy + B[8] * dz);
-                unsigned long long* nd = acc + 4 * (row + cx);
-                atomicAdd(nd + 0, to_fixed(wt));
-                atomicAdd(nd + 1, to_fixed(wt * px));
-                atomicAdd(nd + 2, to_fixed(wt * py));
-                atomicAdd(nd + 3, to_fixed(wt * pz));
+    for (int c = 0; c < 3; ++c) {
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const float wbc = w[1][b] * w[2][c];
+            const float sy0 = by[b][0] + cz[c][0], sy1 = by[b][1] + cz[c][1], sy2 = by[b][2] + cz[c][2];
+            unsigned long long* nd = row0 + c * TL::SZ + b * TL::SY;
+#pragma unroll
+            for (int aa = 0; aa < 3; ++aa) {
+                const float wt = wx[aa] * wbc;
+                atomicAdd(nd + aa, to_fixed_scaled(wt, magic));
+                atomicAdd(nd + aa + TL::AVOL, to_fixed_scaled(wt * (ax[aa][0] + sy0), magic));
+                atomicAdd(nd + aa + 2 * TL::AVOL, to_fixed_scaled(wt * (ax[aa][1] + sy1), magic));
+                atomicAdd(nd + aa + 3 * TL::AVOL, to_fixed_scaled(wt * (ax[aa][2] + sy2), magic));
             }
         }
     }
@@ -104,10 +137,14 @@ __device__ __forceinline__ int p2g_particle(unsigned long long* acc, const int o
 }
 
 // Write a tile's fixed-point node sums to its scratch record as floats.
-__device__ __forceinline__ void flush_tile(const unsigned long long* acc, float4* dst, int vol) {
-    for (int k = threadIdx.x; k < vol; k += kBlock)
-        dst[k] = make_float4(from_fixed(acc[4 * k]), from_fixed(acc[4 * k + 1]),
-                             from_fixed(acc[4 * k + 2]), from_fixed(acc[4 * k + 3]));
+template <class TL>
+__device__ __forceinline__ void flush_tile(const unsigned long long* acc, float4* dst) {
+    for (int k = threadIdx.x; k < TL::PVOL; k += TL::NT) {
+        const int x = k % TL::PX, y = (k / TL::PX) % TL::PY, z = k / (TL::PX * TL::PY);
+        const int o = z * TL::SZ + y * TL::SY + x;
+        dst[k] = make_float4(from_fixed(acc[o]), from_fixed(acc[TL::AVOL + o]),
+                             from_fixed(acc[2 * TL::AVOL + o]), from_fixed(acc[3 * TL::AVOL + o]));
+    }
 }
 
 __device__ __forceinline__ void load_particle(const KArgs& a, long long id, int cell[3],
@@ -125,20 +162,21 @@ __global__ void k_fill(float* p, long long n, float val) {
 
 // Stand-alone particle-to-grid of the first exchange of a step (after creation or
 // an external state write): one block per tile, partials to the tile's scratch.
-__global__ __launch_bounds__(kBlock) void k_p2g(KArgs a, const uint32_t* __restrict__ order,
+template <class TL>
+__global__ __launch_bounds__(TL::NT) void k_p2g(KArgs a, const uint32_t* __restrict__ order,
                                                 const uint32_t* __restrict__ bstart) {
-    extern __shared__ float4 lds[];
-    unsigned long long* acc = reinterpret_cast<unsigned long long*>(lds);
+    extern __shared__ unsigned long long lds_u64[];
+    unsigned long long* acc = lds_u64;
     const int t = blockIdx.x;
     const uint32_t s0 = bstart[t], cnt = bstart[t + 1] - s0;
     if (cnt == 0) return;
     int tc[3];
     tile_coords(a, t, tc);
-    int org[3];
-    for (int q = 0; q < 3; ++q) org[q] = tc[q] * a.T[q] - 2;
-    for (int k = threadIdx.x; k < 4 * a.FPvol; k += kBlock) acc[k] = 0ull;
+    const int org[3] = {tc[0] * TL::T0 - 1, tc[1] * TL::T1 - 1, tc[2] * TL::T2 - 1};
+    for (int k = threadIdx.x; k < 4 * TL::AVOL; k += TL::NT) acc[k] = 0ull;
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < cnt; i += kBlock) {
+    int err = 0;
+    for (uint32_t i = threadIdx.x; i < cnt; i += TL::NT) {
         const long long id = order[s0 + i];
         int cell[3];
         float f[3], v[3], C[9], G[9];
@@ -146,18 +184,19 @@ __global__ __launch_bounds__(kBlock) void k_p2g(KArgs a, const uint32_t* __restr
         for (int q = 0; q < 3; ++q) v[q] = a.soa[(size_t)(V0 + q) * a.n + id];
         for (int q = 0; q < 9; ++q) C[q] = a.soa[(size_t)(C0 + q) * a.n + id];
         for (int q = 0; q < 9; ++q) G[q] = a.soa[(size_t)(G0 + q) * a.n + id];
-        const int pe = p2g_particle(acc, org, a.FP, cell, f, v, C, G, true, a);
-        if (pe) atomicOr(&a.st->error, pe);
+        err |= p2g_particle<TL>(acc, org, cell, f, v, C, G, true, a);
     }
+    if (err) atomicOr(&a.st->error, err);
     __syncthreads();
-    flush_tile(acc, a.scratch + (size_t)t * a.FPvol, a.FPvol);
+    flush_tile<TL>(acc, a.scratch + (size_t)t * TL::PVOL);
 }
 
-// Node kernel (EXTRA: passes after the first of a step, which run only while
-// the relative-rest test fails): sum the partials of the tiles whose P2G footprint covers the node
+// Node kernel: sum the partials of the tiles whose P2G block covers the node
 // (fixed order), V = MG / M (Eq. 5), nodes inside the indenter take its rigid
 // velocity (relative rest with the object), boundary nodes get zero velocity.
-template <bool EXTRA>
+// EXTRA: the same for the passes after the first of a step, which run only while
+// the relative-rest test fails.
+template <class TL, bool EXTRA>
 __global__ __launch_bounds__(kBlock) void k_grid(KArgs a, const uint32_t* __restrict__ bstart,
                                                  int step, int pass) {
     if (a.st->finished[pass]) return;
@@ -168,12 +207,13 @@ __global__ __launch_bounds__(kBlock) void k_grid(KArgs a, const uint32_t* __rest
     const int j = (int)((nid / a.nn[0]) % a.nn[1]);
     const int k = (int)(nid / ((long long)a.nn[0] * a.nn[1]));
     const int nd[3] = {i, j, k};
+    const int T[3] = {TL::T0, TL::T1, TL::T2};
     int lo[3], hi[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-        const int m = nd[q] - a.T[q] - 2;
-        lo[q] = m <= 0 ? 0 : (m + a.T[q] - 1) / a.T[q];
-        hi[q] = min((nd[q] + 2) / a.T[q], a.NT[q] - 1);
+        const int m = nd[q] - T[q] - 2;
+        lo[q] = m <= 0 ? 0 : (m + T[q] - 1) / T[q];
+        hi[q] = min((nd[q] + 1) / T[q], a.NT[q] - 1);
     }
     float W = 0.f, P0 = 0.f, P1 = 0.f, P2 = 0.f;
     for (int tz = lo[2]; tz <= hi[2]; ++tz)
@@ -181,9 +221,8 @@ __global__ __launch_bounds__(kBlock) void k_grid(KArgs a, const uint32_t* __rest
             for (int tx = lo[0]; tx <= hi[0]; ++tx) {
                 const int t = (tz * a.NT[1] + ty) * a.NT[0] + tx;
                 if (bstart[t + 1] == bstart[t]) continue;
-                const int l0 = i - (tx * a.T[0] - 2), l1 = j - (ty * a.T[1] - 2),
-                          l2 = k - (tz * a.T[2] - 2);
-                const float4 c = a.scratch[(size_t)t * a.FPvol + (l2 * a.FP[1] + l1) * a.FP[0] + l0];
+                const int l0 = i - (tx * TL::T0 - 1), l1 = j - (ty * TL::T1 - 1), l2 = k - (tz * TL::T2 - 1);
+                const float4 c = a.scratch[(size_t)t * TL::PVOL + (l2 * TL::PY + l1) * TL::PX + l0];
                 W += c.x; P0 += c.y; P1 += c.z; P2 += c.w;
             }
     float V[3] = {0.f, 0.f, 0.f};
@@ -213,8 +252,9 @@ __global__ __launch_bounds__(kBlock) void k_grid(KArgs a, const uint32_t* __rest
 //  3. If the step ends here: commit F and x (Eq. 8-9), bin the particle for the
 //     next step, and transfer it to the grid of the next step's first pass;
 //     otherwise transfer it (same x and F, new v and C) to the next pass's grid.
-template <bool EXTRA>
-__global__ __launch_bounds__(kBlock) void k_g2p2g(KArgs a, const uint32_t* __restrict__ order,
+// EXTRA marks the launches for passes after the first of a step.
+template <class TL, bool EXTRA>
+__global__ __launch_bounds__(TL::NT) void k_g2p2g(KArgs a, const uint32_t* __restrict__ order,
                                                   const uint32_t* __restrict__ bstart, int step,
                                                   long long gstep, int pass, int store_vc) {
     if (a.st->finished[pass]) {
@@ -223,13 +263,13 @@ __global__ __launch_bounds__(kBlock) void k_g2p2g(KArgs a, const uint32_t* __res
         if (blockIdx.x == 0 && threadIdx.x == 0) a.st->finished[pass + 1] = 1;
         return;
     }
-    extern __shared__ float4 lds[];
-    unsigned long long* acc = reinterpret_cast<unsigned long long*>(lds);   // 4 * FPvol
-    float4* gv = lds + 2 * a.FPvol;                                         // FGvol
-    float* ve_part = reinterpret_cast<float*>(gv + a.FGvol);   // 27 * 3
-    int* wc = reinterpret_cast<int*>(ve_part + 81);            // kWaves * 27
-    int* running = wc + kWaves * kDirs;                        // 27
-    int* sh = running + kDirs;                                 // [0] = final
+    extern __shared__ unsigned long long lds_u64[];
+    unsigned long long* acc = lds_u64;                                   // 4 * PVOL
+    float4* gv = reinterpret_cast<float4*>(lds_u64 + 4 * TL::AVOL);      // GVOL
+    float* ve_part = reinterpret_cast<float*>(gv + TL::GVOL);            // 27 * 3
+    int* wc = reinterpret_cast<int*>(ve_part + 81);                      // NW * 27 wave counts
+    int* running = wc + TL::NW * kDirs;                                  // 27 per-direction counts
+    int* sh = running + kDirs;                                           // [0] = final
 
     const int tid = threadIdx.x;
     const int t = blockIdx.x;
@@ -253,7 +293,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p2g(KArgs a, const uint32_t* __res
         ve_part[3 * tid + 2] = wt * V.z;
     }
     if (tid < kDirs) running[tid] = 0;
-    if (tid < kWaves * kDirs) wc[tid] = 0;
+    if (tid < TL::NW * kDirs) wc[tid] = 0;
     __syncthreads();
     if (tid == 0) {
         float ve0 = 0.f, ve1 = 0.f;
@@ -295,27 +335,24 @@ __global__ __launch_bounds__(kBlock) void k_g2p2g(KArgs a, const uint32_t* __res
     }
     int tc[3];
     tile_coords(a, t, tc);
-    int orgP[3], orgG[3];
-    for (int q = 0; q < 3; ++q) {
-        orgP[q] = tc[q] * a.T[q] - 2;
-        orgG[q] = tc[q] * a.T[q] - 1;
-    }
-    // ---- stage the grid velocities of the tile's G2P footprint, clear the P2G block
-    for (int kk = tid; kk < a.FGvol; kk += kBlock) {
-        const int lx = kk % a.FG[0], ly = (kk / a.FG[0]) % a.FG[1], lz = kk / (a.FG[0] * a.FG[1]);
+    const int orgP[3] = {tc[0] * TL::T0 - 1, tc[1] * TL::T1 - 1, tc[2] * TL::T2 - 1};
+    const int orgG[3] = {tc[0] * TL::T0, tc[1] * TL::T1, tc[2] * TL::T2};
+    // ---- stage the grid velocities of the tile's G2P block, clear the P2G block
+    for (int kk = tid; kk < TL::GVOL; kk += TL::NT) {
+        const int lx = kk % TL::GX, ly = (kk / TL::GX) % TL::GY, lz = kk / (TL::GX * TL::GY);
         const int gx = orgG[0] + lx, gy = orgG[1] + ly, gz = orgG[2] + lz;
         float4 V = make_float4(0.f, 0.f, 0.f, 0.f);
         if (gx >= 0 && gy >= 0 && gz >= 0 && gx < a.nn[0] && gy < a.nn[1] && gz < a.nn[2])
             V = a.gridV[((long long)gz * a.nn[1] + gy) * a.nn[0] + gx];
         gv[kk] = V;
     }
-    for (int kk = tid; kk < 4 * a.FPvol; kk += kBlock) acc[kk] = 0ull;
+    for (int kk = tid; kk < 4 * TL::AVOL; kk += TL::NT) acc[kk] = 0ull;
     __syncthreads();
 
     const bool with_stress = fin || a.stress_each_pass;
     const int lane = tid & 63, wid = tid >> 6;
     int err = 0;
-    for (uint32_t i0 = 0; i0 < cnt; i0 += kBlock) {
+    for (uint32_t i0 = 0; i0 < cnt; i0 += TL::NT) {
         const uint32_t i = i0 + tid;
         int dir = -1;
         if (i < cnt) {
@@ -323,53 +360,49 @@ __global__ __launch_bounds__(kBlock) void k_g2p2g(KArgs a, const uint32_t* __res
             int cell[3];
             float f[3];
             load_particle(a, id, cell, f);
-            // ---- 2. grid-to-particle (Eq. 6-7)
+            // ---- 2. grid-to-particle (Eq. 6-7), separably: column sums S_a,
+            // T_b, U_c of the weighted grid velocities along each axis give
+            // v = sum_a w_a S_a and C_.0 = (4/dx) sum_a w_a (a - fx) (S_a - v)
+            // (the v term vanishes in exact arithmetic and removes cancellation)
             int base[3];
             float fx[3], w[3][3];
             for (int q = 0; q < 3; ++q) bspline_axis(cell[q], f[q], base[q], fx[q], w[q]);
-            int l[3];
-            bool ok = true;
-            for (int q = 0; q < 3; ++q) {
-                l[q] = base[q] - orgG[q];
-                ok = ok && l[q] >= 0 && l[q] + 2 < a.FG[q];
-            }
+            const int l0 = base[0] - orgG[0], l1 = base[1] - orgG[1], l2 = base[2] - orgG[2];
             float v[3] = {0.f, 0.f, 0.f}, C[9];
             for (int q = 0; q < 9; ++q) C[q] = 0.f;
-            if (ok) {
+            if (l0 >= 0 && l0 + 2 < TL::GX && l1 >= 0 && l1 + 2 < TL::GY && l2 >= 0 && l2 + 2 < TL::GZ) {
+                float S[3][3], Tb[3][3], U[3][3];
+#pragma unroll
+                for (int q = 0; q < 3; ++q)
+#pragma unroll
+                    for (int r = 0; r < 3; ++r) { S[q][r] = 0.f; Tb[q][r] = 0.f; U[q][r] = 0.f; }
+                const float4* g0 = gv + (l2 * TL::GY + l1) * TL::GX + l0;
 #pragma unroll
                 for (int cz = 0; cz < 3; ++cz)
 #pragma unroll
                     for (int cy = 0; cy < 3; ++cy) {
-                        const float wyz = w[1][cy] * w[2][cz];
-                        const int row = ((l[2] + cz) * a.FG[1] + (l[1] + cy)) * a.FG[0] + l[0];
+                        const float wbc = w[1][cy] * w[2][cz];
 #pragma unroll
                         for (int cx = 0; cx < 3; ++cx) {
-                            const float4 V = gv[row + cx];
-                            const float wt = w[0][cx] * wyz;
-                            v[0] += wt * V.x; v[1] += wt * V.y; v[2] += wt * V.z;
+                            const float4 V = g0[(cz * TL::GY + cy) * TL::GX + cx];
+                            const float wac = w[0][cx] * w[2][cz], wab = w[0][cx] * w[1][cy];
+                            S[cx][0] += wbc * V.x; S[cx][1] += wbc * V.y; S[cx][2] += wbc * V.z;
+                            Tb[cy][0] += wac * V.x; Tb[cy][1] += wac * V.y; Tb[cy][2] += wac * V.z;
+                            U[cz][0] += wab * V.x; U[cz][1] += wab * V.y; U[cz][2] += wab * V.z;
                         }
                     }
-                // C = (4/dx^2) sum w V d^T, evaluated as (4/dx) sum w (V - v) d^T in
-                // cell units (equal because sum w d = 0; less cancellation)
 #pragma unroll
-                for (int cz = 0; cz < 3; ++cz) {
-                    const float dz = (float)cz - fx[2];
+                for (int r = 0; r < 3; ++r) v[r] = w[0][0] * S[0][r] + w[0][1] * S[1][r] + w[0][2] * S[2][r];
 #pragma unroll
-                    for (int cy = 0; cy < 3; ++cy) {
-                        const float dy = (float)cy - fx[1];
-                        const float wyz = w[1][cy] * w[2][cz];
-                        const int row = ((l[2] + cz) * a.FG[1] + (l[1] + cy)) * a.FG[0] + l[0];
+                for (int q = 0; q < 3; ++q) {
+                    const float ea = w[0][q] * ((float)q - fx[0]);
+                    const float eb = w[1][q] * ((float)q - fx[1]);
+                    const float ec = w[2][q] * ((float)q - fx[2]);
 #pragma unroll
-                        for (int cx = 0; cx < 3; ++cx) {
-                            const float dxx = (float)cx - fx[0];
-                            const float4 V = gv[row + cx];
-                            const float wt = w[0][cx] * wyz;
-                            const float u0 = wt * (V.x - v[0]), u1 = wt * (V.y - v[1]),
-                                        u2 = wt * (V.z - v[2]);
-                            C[0] += u0 * dxx; C[1] += u0 * dy; C[2] += u0 * dz;
-                            C[3] += u1 * dxx; C[4] += u1 * dy; C[5] += u1 * dz;
-                            C[6] += u2 * dxx; C[7] += u2 * dy; C[8] += u2 * dz;
-                        }
+                    for (int r = 0; r < 3; ++r) {
+                        C[3 * r + 0] += ea * (S[q][r] - v[r]);
+                        C[3 * r + 1] += eb * (Tb[q][r] - v[r]);
+                        C[3 * r + 2] += ec * (U[q][r] - v[r]);
                     }
                 }
 #pragma unroll
@@ -424,10 +457,12 @@ __global__ __launch_bounds__(kBlock) void k_g2p2g(KArgs a, const uint32_t* __res
                     a.st->xe_cell[par ^ 1] = pack_cell(cell);
                     for (int q = 0; q < 3; ++q) a.st->xe_f[par ^ 1][q] = f[q];
                 }
-                int nt[3];
+                // tile of the new stencil base floor(x - 1/2)
+                const int nt[3] = {(cell[0] - 1 + (f[0] >= 0.5f ? 1 : 0)) / TL::T0,
+                                   (cell[1] - 1 + (f[1] >= 0.5f ? 1 : 0)) / TL::T1,
+                                   (cell[2] - 1 + (f[2] >= 0.5f ? 1 : 0)) / TL::T2};
                 dir = 0;
                 for (int q = 2; q >= 0; --q) {
-                    nt[q] = cell[q] / a.T[q];
                     int dd = nt[q] - tc[q];
                     dd = dd < -1 ? -1 : (dd > 1 ? 1 : dd);
                     dir = dir * 3 + (dd + 1);
@@ -438,11 +473,13 @@ __global__ __launch_bounds__(kBlock) void k_g2p2g(KArgs a, const uint32_t* __res
                 for (int q = 0; q < 9; ++q) a.soa[(size_t)(C0 + q) * a.n + id] = C[q];
             }
             // ---- transfer to the grid of the next exchange
-            err |= p2g_particle(acc, orgP, a.FP, cell, f, v, C, G, with_stress, a);
+            err |= p2g_particle<TL>(acc, orgP, cell, f, v, C, G, with_stress, a);
         }
         if (fin) {
-            // deterministic rank of this particle among the block's particles that
-            // move to the same neighbour tile (binned order of the next step)
+            // stable rank of this particle among the tile's particles that move to
+            // the same neighbour tile (earlier positions first): the next binned
+            // order keeps each tile's particles in their previous order, so the
+            // loads of a wave stay on few cache lines
             int my_rank = 0;
             unsigned long long act = __ballot(dir >= 0);
             while (act) {
@@ -461,21 +498,21 @@ __global__ __launch_bounds__(kBlock) void k_g2p2g(KArgs a, const uint32_t* __res
             }
             __syncthreads();
             if (tid < kDirs) {
-                int s = 0;
-                for (int w2 = 0; w2 < kWaves; ++w2) { s += wc[w2 * kDirs + tid]; wc[w2 * kDirs + tid] = 0; }
-                running[tid] += s;
+                int sum = 0;
+                for (int w2 = 0; w2 < TL::NW; ++w2) { sum += wc[w2 * kDirs + tid]; wc[w2 * kDirs + tid] = 0; }
+                running[tid] += sum;
             }
             __syncthreads();
         }
     }
     if (err) atomicOr(&a.st->error, err);
     __syncthreads();
-    flush_tile(acc, a.scratch + (size_t)t * a.FPvol, a.FPvol);
+    flush_tile<TL>(acc, a.scratch + (size_t)t * TL::PVOL);
     if (fin && tid < kDirs) {
         const uint32_t c = running[tid];
         a.dircount[(size_t)t * kDirs + tid] = c;
         if (c) {
-            int dt[3] = {tid % 3 - 1, (tid / 3) % 3 - 1, tid / 9 - 1};
+            const int dt[3] = {tid % 3 - 1, (tid / 3) % 3 - 1, tid / 9 - 1};
             int u[3];
             bool ok = true;
             for (int q = 0; q < 3; ++q) {
@@ -546,16 +583,21 @@ __global__ __launch_bounds__(kBlock) void k_scatter(KArgs a, const uint32_t* __r
         uint32_t o = 0;
         if (ok) {
             o = bstart_next[tile_linear(a, u)];
-            for (int d2 = 0; d2 < tid; ++d2) {
+            // the 26 candidate loads are independent: issue them all, then sum
+            uint32_t cnts[kDirs];
+#pragma unroll
+            for (int d2 = 0; d2 < kDirs; ++d2) {
                 const int e2[3] = {d2 % 3 - 1, (d2 / 3) % 3 - 1, d2 / 9 - 1};
                 int sc[3];
-                bool ok2 = true;
+                bool ok2 = d2 < tid;
                 for (int q = 0; q < 3; ++q) {
                     sc[q] = u[q] - e2[q];
                     ok2 = ok2 && sc[q] >= 0 && sc[q] < a.NT[q];
                 }
-                if (ok2) o += a.dircount[(size_t)tile_linear(a, sc) * kDirs + d2];
+                cnts[d2] = ok2 ? a.dircount[(size_t)tile_linear(a, sc) * kDirs + d2] : 0u;
             }
+#pragma unroll
+            for (int d2 = 0; d2 < kDirs; ++d2) o += cnts[d2];
         }
         off[tid] = o;
     }
@@ -631,11 +673,65 @@ __global__ void k_surface_finish(const float4* __restrict__ acc, int npix, float
     }
 }
 
-template __global__ void k_grid<false>(KArgs, const uint32_t*, int, int);
-template __global__ void k_grid<true>(KArgs, const uint32_t*, int, int);
-template __global__ void k_g2p2g<false>(KArgs, const uint32_t*, const uint32_t*, int, long long, int,
-                                        int);
-template __global__ void k_g2p2g<true>(KArgs, const uint32_t*, const uint32_t*, int, long long, int,
-                                       int);
+// Tile shapes compiled into the library (cells per axis): explicit kernel
+// instantiations, seen by both the device and the host compilation pass.
+#define IMPM_TILE_KERNELS(X, Y, Z, N)                                                                  \
+    template __global__ void k_p2g<Tile<X, Y, Z, N>>(KArgs, const uint32_t*, const uint32_t*);         \
+    template __global__ void k_grid<Tile<X, Y, Z, N>, false>(KArgs, const uint32_t*, int, int);        \
+    template __global__ void k_grid<Tile<X, Y, Z, N>, true>(KArgs, const uint32_t*, int, int);         \
+    template __global__ void k_g2p2g<Tile<X, Y, Z, N>, false>(KArgs, const uint32_t*, const uint32_t*, \
+                                                              int, long long, int, int);               \
+    template __global__ void k_g2p2g<Tile<X, Y, Z, N>, true>(KArgs, const uint32_t*, const uint32_t*,  \
+                                                             int, long long, int, int);
+IMPM_TILE_KERNELS(8, 8, 2, 256)
+IMPM_TILE_KERNELS(8, 8, 2, 512)
+IMPM_TILE_KERNELS(4, 8, 4, 256)
+IMPM_TILE_KERNELS(8, 4, 4, 256)
+IMPM_TILE_KERNELS(8, 8, 4, 256)
+IMPM_TILE_KERNELS(8, 8, 4, 512)
+IMPM_TILE_KERNELS(4, 4, 4, 256)
+IMPM_TILE_KERNELS(8, 4, 2, 256)
+IMPM_TILE_KERNELS(4, 4, 2, 256)
+IMPM_TILE_KERNELS(4, 8, 2, 256)
+IMPM_TILE_KERNELS(8, 8, 8, 512)
+#undef IMPM_TILE_KERNELS
+
+// Host launchers and the table of the compiled tile shapes (host pass only).
+#ifndef __HIP_DEVICE_COMPILE__
+template <int TX, int TY, int TZ, int NB>
+struct TileLaunch {
+    using TL = Tile<TX, TY, TZ, NB>;
+    static void p2g(const KArgs& a, const uint32_t* order, const uint32_t* bstart, hipStream_t st) {
+        hipLaunchKernelGGL(k_p2g<TL>, dim3(a.n_tiles), dim3(NB), TL::LDS_P2G, st, a, order, bstart);
+    }
+    static void grid(const KArgs& a, const uint32_t* bstart, int step, int pass, bool extra, int blocks,
+                     hipStream_t st) {
+        if (extra)
+            hipLaunchKernelGGL((k_grid<TL, true>), dim3(blocks), dim3(kBlock), 0, st, a, bstart, step, pass);
+        else
+            hipLaunchKernelGGL((k_grid<TL, false>), dim3(blocks), dim3(kBlock), 0, st, a, bstart, step, pass);
+    }
+    static void g2p2g(const KArgs& a, const uint32_t* order, const uint32_t* bstart, int step, long long gstep,
+                      int pass, int store_vc, bool extra, hipStream_t st) {
+        if (extra)
+            hipLaunchKernelGGL((k_g2p2g<TL, true>), dim3(a.n_tiles), dim3(NB), TL::LDS_G2P2G, st, a, order,
+                               bstart, step, gstep, pass, store_vc);
+        else
+            hipLaunchKernelGGL((k_g2p2g<TL, false>), dim3(a.n_tiles), dim3(NB), TL::LDS_G2P2G, st, a,
+                               order, bstart, step, gstep, pass, store_vc);
+    }
+    static constexpr TileOps ops() {
+        return TileOps{{TX, TY, TZ}, NB, TL::PVOL, TL::LDS_G2P2G, &p2g, &grid, &g2p2g};
+    }
+};
+
+const TileOps kTileOps[] = {
+    TileLaunch<8, 8, 2, 256>::ops(), TileLaunch<8, 8, 2, 512>::ops(), TileLaunch<4, 8, 4, 256>::ops(),
+    TileLaunch<8, 4, 4, 256>::ops(), TileLaunch<8, 8, 4, 256>::ops(), TileLaunch<8, 8, 4, 512>::ops(),
+    TileLaunch<4, 4, 4, 256>::ops(), TileLaunch<8, 4, 2, 256>::ops(), TileLaunch<4, 4, 2, 256>::ops(),
+    TileLaunch<4, 8, 2, 256>::ops(), TileLaunch<8, 8, 8, 512>::ops(),
+};
+const int kNumTileOps = sizeof(kTileOps) / sizeof(kTileOps[0]);
+#endif
 
 }  // namespace impm

@@ -53,7 +53,7 @@ EXPORTS = ("sim_params_default", "sim_create", "sim_destroy", "sim_set_indenter_
            "sim_synchronize", "sim_surface_heightmap", "sim_surface_displacement", "sim_get_stats",
            "sim_num_particles", "sim_grid_dims", "sim_read_particles", "sim_write_particles",
            "sim_read_rest", "sim_debug_keep_grid", "sim_read_grid", "sim_debug_force_passes",
-           "sim_set_tile", "sim_profile", "sim_profile_read", "sim_last_error")
+           "sim_set_tile", "sim_set_tile_threads", "sim_profile", "sim_profile_read", "sim_last_error")
 
 _lib = None
 
@@ -87,6 +87,7 @@ def lib():
     L.sim_read_grid.argtypes = [vp, fp, fp, fp]
     L.sim_debug_force_passes.argtypes = [vp, vp, i32]
     L.sim_set_tile.argtypes = [vp, i32, i32, i32]
+    L.sim_set_tile_threads.argtypes = [vp, i32, i32, i32, i32]
     L.sim_profile.argtypes = [vp, i32]
     L.sim_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     L.sim_last_error.argtypes = [vp]
@@ -235,8 +236,8 @@ class Sim:
         self._chk(lib().sim_profile_read(self.h, C.byref(ms), C.byref(k)))
         return ms.value, k.value
 
-    def sim_set_tile(self, tx, ty, tz):
-        self._chk(lib().sim_set_tile(self.h, tx, ty, tz))
+    def sim_set_tile(self, tx, ty, tz, threads=256):
+        self._chk(lib().sim_set_tile_threads(self.h, tx, ty, tz, threads))
 
 
 def sim_params_default() -> sim_params:

@@ -81,7 +81,7 @@ def test_initial_state_bitwise(gpu, ref):
 
 
 @pytest.mark.parametrize("cells,tile", [((12, 10, 5), (8, 8, 4)), ((13, 9, 6), (4, 4, 4)),
-                                         ((7, 11, 3), (5, 3, 2))])
+                                         ((7, 11, 3), (4, 4, 2)), ((17, 9, 5), (8, 8, 2))])
 def test_single_substep_from_random_state(gpu, ref, cells, tile):
     """One substep (sub-cycled twice) of a press from a random state, on grids
     that span several tiles with ragged edges."""
@@ -231,6 +231,8 @@ def test_bad_arguments_rejected(gpu):
         g.sim_step(0)
     with pytest.raises(gpu.SimError):
         g.sim_set_tile(1, 8, 8)
+    with pytest.raises(gpu.SimError):
+        g.sim_set_tile(5, 3, 2)        # not a compiled tile shape
 
 
 @pytest.mark.slow
