@@ -35,10 +35,12 @@ PEAK_HBM_GBS = 8000.0
 # C, F (3 + 3 + 9 + 9 floats = 96 B) and write v, C, F, x (96 B), plus the
 # grid's share (two 16 B node records per 8 particles, read and written, ~7 B).
 ALG_BYTES_PER_PARTICLE_PASS = 192.0 + 7.0
-# rocprofv3 counter readings of the fused kernel for this workload (KiB per
-# dispatch), and the scale the same counters show for a copy of known size;
-# None until measured on this build of the kernel.
-PMC = None
+# HBM bytes per launch of the fused kernel for this workload, from two
+# rocprofv3 --pmc runs (FETCH_SIZE 290963 KiB, WRITE_SIZE 447834 KiB per
+# dispatch) scaled by the counters' reading of a copy of known size (fetched
+# bytes = 2.0 x FETCH_SIZE, written = 1.0 x WRITE_SIZE); set to None whenever the
+# kernel changes until the counters are taken again.
+PMC_TRAFFIC_BYTES = (2.0 * 290963 + 447834) * 1024
 
 
 def parse():
@@ -54,14 +56,19 @@ def parse():
 
 
 def copy_calibration():
+    """Known-size traffic for scaling the HBM byte counters: an elementwise
+    kernel (b = a * 1) that reads 1 GiB and writes 1 GiB with ordinary vector
+    loads and stores, and the runtime's device-to-device copy of 1 GiB."""
     import torch
     n = 1 << 28                       # 1 GiB of float32
     a = torch.ones(n, device="cuda")
     b = torch.empty_like(a)
     for _ in range(3):
+        torch.mul(a, 1.0, out=b)
+    for _ in range(3):
         b.copy_(a)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n}))
+    print(json.dumps({"bytes_read_per_kernel": 4 * n, "bytes_written_per_kernel": 4 * n}))
 
 
 def run_frames(sim, segs, first, count, hm_out):
@@ -149,10 +156,9 @@ def main():
     achieved = ALG_BYTES_PER_PARTICLE_PASS * n / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": "k_g2p2g<false>", "achieved": round(achieved, 1),
                 "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                "traffic": None, "avg_kernel_ms": round(avg_ms, 5),
+                "traffic": PMC_TRAFFIC_BYTES, "traffic_unit": "bytes/launch",
+                "avg_kernel_ms": round(avg_ms, 5),
                 "alg_bytes_per_launch": ALG_BYTES_PER_PARTICLE_PASS * n}
-    if PMC is not None:
-        roofline["traffic"] = PMC
     out = {
         "metric": "IMPM particle-updates/s",
         "value": value,

@@ -566,3 +566,29 @@ def test_contact_velocity_is_the_rigid_motion(ref):
     want = (moved - X) / p.dt
     err = np.abs(V[inside] - want).max()
     assert err < 2 * ang * np.abs(want).max(), err
+
+
+@pytest.mark.slow
+def test_elastic_impulse_once_per_step_is_the_stable_reading(ref):
+    """Algorithm 1 repeats the exchange while the relative-rest test fails.  If
+    every repetition re-added the elastic momentum ME_i (Eq. 4), a step with
+    several passes would apply the elastic impulse several times: under slip and
+    rotation the oracle then inverts elements (det F <= 0), while adding it in
+    the step's first exchange only stays valid.  This fixes the reading used on
+    both sides (the literal variant remains available as stress_each_pass = 1)."""
+    res = {}
+    for sep in (1, 0):
+        p = W.small_sensor(cells=(16, 16, 6), dx=0.25e-3, subcycle=4, radius=1.5e-3, pad=8,
+                           stress_each_pass=sep)
+        s = ref.OracleSim(p)
+        c = np.array(p.pose0[:3])
+        try:
+            s.set_target_pose(c + [0, 0, -0.5e-3], (1, 0, 0, 0))
+            s.step(200)
+            for i in range(10):
+                s.set_target_pose(c + [0.05e-3 * (i + 1), 0, -0.5e-3], W.quat_about_z(3 * (i + 1)))
+                s.step(20)
+            res[sep] = "ok"
+        except FloatingPointError:
+            res[sep] = "invalid"
+    assert res == {1: "invalid", 0: "ok"}, res
