@@ -169,6 +169,35 @@ int sim_profile_read(sim_t* s, double* ms_total, int64_t* launches);
 
 const char* sim_last_error(const sim_t* s);
 
+/* ---- Batched sensors (many independent sensors advanced together).
+ * All sensors of a batch share dt, subcycle and rest_limit and are stepped
+ * together: one launch per kernel phase covers every sensor of a tile-shape
+ * group (the blocks of a launch map to (sensor, tile) through prefix sums), so
+ * a step of the whole batch costs a handful of launches. */
+typedef struct sim_batch_s sim_batch_t;
+
+/* params: n records; tiles: n x (tx, ty, tz, threads) or NULL for the default
+ * shape (for example from sim_autotune_tile).  hip_stream as for sim_create. */
+int sim_batch_create(const sim_params* params, int32_t n, const int32_t* tiles, void* hip_stream,
+                     sim_batch_t** out);
+void sim_batch_destroy(sim_batch_t* b);
+int sim_batch_size(const sim_batch_t* b, int32_t* n);
+/* Borrow sensor i (for sim_read_*, sim_get_stats, ...); owned by the batch. */
+int sim_batch_get(sim_batch_t* b, int32_t i, sim_t** out);
+/* pos: n x 3, quat_wxyz: n x 4; each sensor's target for the next sim_batch_step. */
+int sim_batch_set_indenter_poses(sim_batch_t* b, const double* pos, const double* quat_wxyz);
+int sim_batch_step(sim_batch_t* b, int32_t n_substeps);
+int sim_batch_synchronize(sim_batch_t* b);
+/* out: n x H x W (heightmaps) or n x H x W x 3 (displacements), host or device. */
+int sim_batch_heightmaps(sim_batch_t* b, float* out, int32_t W, int32_t H, int32_t out_on_device);
+int sim_batch_displacements(sim_batch_t* b, float* out, int32_t W, int32_t H, int32_t out_on_device);
+const char* sim_batch_last_error(const sim_batch_t* b);
+
+/* Time `steps` executed steps of a sensor with these parameters for every
+ * compiled tile shape and return the fastest (tx, ty, tz, threads) and its
+ * time per executed step in ms. */
+int sim_autotune_tile(const sim_params* p, int32_t steps, void* hip_stream, int32_t out[4], double* out_ms);
+
 #ifdef __cplusplus
 }
 #endif

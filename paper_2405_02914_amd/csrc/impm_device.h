@@ -68,6 +68,8 @@ struct KArgs {
     float4* gridV;             // n_nodes (Vx, Vy, Vz, W)
     float* dbgM;               // n_nodes or null
     float* dbgMG;              // 3 * n_nodes or null
+    uint32_t* order[2];        // binned particle order (ids), double-buffered
+    uint32_t* bstart[2];       // tile starts of each order (n_tiles + 1)
     uint32_t* dirrank;         // per binned position: rank << 5 | dir
     uint32_t* dircount;        // n_tiles * 27: particles of a tile moving in each direction
     uint32_t* newcnt;          // n_tiles: next step's tile sizes (accumulated)
@@ -81,8 +83,29 @@ struct SurfArgs {
     float dx;
     long long n;
     const float* rest_r;         // 3 per surface particle: in-cell rest offsets
-    float4* acc;                 // H*W (w, w ux, w uy, w uz)
+    unsigned long long* acc;     // H*W x 4 fixed-point sums (w, w ux, w uy, w uz), u in cells
 };
+
+// One launch processes the tiles (or node blocks) of one or several sensors:
+// args[s] is sensor s's record in device memory; tile_base and node_base are
+// prefix sums of the sensors' tile counts and node-block counts (null for a
+// single sensor).
+struct BatchMap {
+    const KArgs* args;
+    const int* tile_base;
+    const int* node_base;
+    int n;
+};
+
+__device__ __forceinline__ int batch_find(const int* base, int n, int g) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (base[mid] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
 
 // Launchers of the tile kernels for one compiled tile shape.
 struct TileOps {
@@ -90,11 +113,11 @@ struct TileOps {
     int threads;               // threads per block of the particle kernels
     int pvol;                  // nodes of a tile's particle-to-grid block (scratch record)
     size_t lds_g2p2g;
-    void (*p2g)(const KArgs& a, const uint32_t* order, const uint32_t* bstart, hipStream_t st);
-    void (*grid)(const KArgs& a, const uint32_t* bstart, int step, int pass, bool extra, int blocks,
+    void (*p2g)(const BatchMap& m, int tile_blocks, int cur, hipStream_t st);
+    void (*grid)(const BatchMap& m, int node_blocks, int sbin, int step, int pass, bool extra,
                  hipStream_t st);
-    void (*g2p2g)(const KArgs& a, const uint32_t* order, const uint32_t* bstart, int step,
-                  long long gstep, int pass, int store_vc, bool extra, hipStream_t st);
+    void (*g2p2g)(const BatchMap& m, int tile_blocks, int cur, int step, int par, int pass,
+                  int store_vc, bool extra, hipStream_t st);
 };
 extern const TileOps kTileOps[];
 extern const int kNumTileOps;

@@ -16,11 +16,11 @@
 
 namespace impm {
 __global__ void k_fill(float* p, long long n, float val);
-__global__ void k_scan(KArgs a, uint32_t* bstart_next, int limit_slots);
-__global__ void k_scatter(KArgs a, const uint32_t* order, const uint32_t* bstart,
-                          const uint32_t* bstart_next, uint32_t* order_next);
+__global__ void k_scan(BatchMap m, int next, int limit_slots);
+__global__ void k_scatter(BatchMap m, int cur);
 __global__ void k_surface_accum(KArgs a, SurfArgs s);
-__global__ void k_surface_finish(const float4* acc, int npix, float top, int mode, float* out);
+__global__ void k_surface_finish(const unsigned long long* acc, int npix, float top, float dx, int mode,
+                                 float* out);
 }  // namespace impm
 
 using namespace impm;
@@ -56,11 +56,14 @@ struct sim_s {
     float* dbgM = nullptr;
     float* dbgMG = nullptr;
     DevState* st = nullptr;
+    KArgs* d_args = nullptr;     // device copy of the kernel record (single-sensor launches)
+    KArgs h_args;
+    bool args_valid = false;
     StepPose* poses = nullptr;
     long long pose_cap = 0;
     float* surf_rest = nullptr;
     long long n_surf = 0;
-    float4* surf_acc = nullptr;
+    unsigned long long* surf_acc = nullptr;   // 4 per pixel
     long long surf_cap = 0;
     float* out_tmp = nullptr;
     long long out_cap = 0;
@@ -244,6 +247,10 @@ static KArgs kargs(const sim_t* s) {
     a.gridV = s->gridV;
     a.dbgM = s->keep_grid ? s->dbgM : nullptr;
     a.dbgMG = s->keep_grid ? s->dbgMG : nullptr;
+    for (int k = 0; k < 2; ++k) {
+        a.order[k] = s->order[k];
+        a.bstart[k] = s->bstart[k];
+    }
     a.dirrank = s->dirrank;
     a.dircount = s->dircount;
     a.newcnt = s->newcnt;
@@ -347,6 +354,98 @@ static int check_device_error(sim_t* s) {
         return fail(s, SIM_ENUMERIC, buf);
     }
     return SIM_OK;
+}
+
+// Device copy of the handle's kernel record, refreshed when the record changes
+// (buffers reallocated, grid keeping toggled).
+static int sync_args(sim_t* s) {
+    if (!s->d_args) HIPCHK(s, hipMalloc(&s->d_args, sizeof(KArgs)));
+    const KArgs a = kargs(s);
+    if (!s->args_valid || std::memcmp(&a, &s->h_args, sizeof(KArgs)) != 0) {
+        HIPCHK(s, hipStreamSynchronize(s->stream));
+        HIPCHK(s, hipMemcpy(s->d_args, &a, sizeof(KArgs), hipMemcpyHostToDevice));
+        s->h_args = a;
+        s->args_valid = true;
+    }
+    return SIM_OK;
+}
+
+// Pose table of the next n_substeps (host FP64, staged through pinned memory and
+// uploaded on the handle's stream) and the number of exchange passes to launch
+// per executed step: 1 for a pure press or PLAIN mode, the forced count when a
+// schedule is replayed, LIMIT otherwise (later passes exit when the step has
+// converged).
+static int prepare_step(sim_t* s, int32_t n_substeps, std::vector<int>& npass) {
+    const sim_params& P = s->P;
+    const long long N = (long long)n_substeps * P.subcycle;
+    const double h = P.dt / (double)P.subcycle;
+    if (N > s->pose_cap) {
+        HIPCHK(s, hipStreamSynchronize(s->stream));
+        if (s->poses) (void)hipFree(s->poses);
+        s->poses = nullptr;
+        HIPCHK(s, hipMalloc(&s->poses, N * sizeof(StepPose)));
+        s->pose_cap = N;
+    }
+    const int b = s->stage_next;
+    s->stage_next ^= 1;
+    if (!s->stage_ev[b]) HIPCHK(s, hipEventCreateWithFlags(&s->stage_ev[b], hipEventDisableTiming));
+    HIPCHK(s, hipEventSynchronize(s->stage_ev[b]));   // the copy that last read this buffer
+    if (N > s->stage_cap[b]) {
+        if (s->stage[b]) (void)hipHostFree(s->stage[b]);
+        s->stage[b] = nullptr;
+        HIPCHK(s, hipHostMalloc(&s->stage[b], N * sizeof(StepPose), hipHostMallocDefault));
+        s->stage_cap[b] = N;
+    }
+    StepPose* poses = s->stage[b];
+    npass.assign(N, 1);
+    for (long long j = 0; j < N; ++j) {
+        StepPose& sp = poses[j];
+        make_pose(s, j, N, h, &sp);
+        if (s->forced_pos < s->forced.size()) sp.forced = s->forced[s->forced_pos++];
+        if (sp.forced > 0) npass[j] = sp.forced;
+        else if (P.mode == SIM_MODE_PLAIN || sp.gnorm <= 1e-9) npass[j] = 1;
+        else npass[j] = P.rest_limit;
+    }
+    HIPCHK(s, hipMemcpyAsync(s->poses, poses, N * sizeof(StepPose), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipEventRecord(s->stage_ev[b], s->stream));
+    return sync_args(s);
+}
+
+// One group of sensors that share a tile shape, launched together.
+struct LaunchSet {
+    const TileOps* ops;
+    BatchMap m;
+    int tile_blocks, node_blocks, n;
+    int limit_slots;
+    hipStream_t st;
+};
+
+// The kernels of one executed step: node kernel and fused exchange of the first
+// pass, the extra passes, then the counting sort of the next binned order.
+static void launch_step(const LaunchSet& L, int j, int npass, int cur, int sbin, int par, int store,
+                        hipEvent_t e0, hipEvent_t e1) {
+    L.ops->grid(L.m, L.node_blocks, sbin, j, 0, false, L.st);
+    if (e0) (void)hipEventRecord(e0, L.st);
+    L.ops->g2p2g(L.m, L.tile_blocks, cur, j, par, 0, store, false, L.st);
+    if (e1) (void)hipEventRecord(e1, L.st);
+    for (int pass = 1; pass < npass; ++pass) {
+        L.ops->grid(L.m, L.node_blocks, cur, j, pass, true, L.st);
+        L.ops->g2p2g(L.m, L.tile_blocks, cur, j, par, pass, store, true, L.st);
+    }
+    hipLaunchKernelGGL(k_scan, dim3(L.n), dim3(1024), 0, L.st, L.m, cur ^ 1, L.limit_slots);
+    hipLaunchKernelGGL(k_scatter, dim3(L.tile_blocks), dim3(kBlock), 0, L.st, L.m, cur);
+}
+
+static void finish_call(sim_t* s, int32_t n_substeps, long long N) {
+    s->pending = true;
+    std::memcpy(s->pos, s->tpos, sizeof(s->pos));
+    std::memcpy(s->quat, s->tquat, sizeof(s->quat));
+    s->substeps += n_substeps;
+    for (long long j = 0; j < N; ++j) {
+        s->sbin = s->cur;
+        s->cur ^= 1;
+        s->gstep += 1;
+    }
 }
 
 // ------------------------------------------------------------------ C ABI
@@ -525,7 +624,7 @@ void sim_destroy(sim_t* s) {
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     void* bufs[] = {s->soa, s->cell, s->flags, s->order[0], s->order[1], s->bstart[0], s->bstart[1],
                     s->dirrank, s->dircount, s->newcnt, s->scratch, s->gridV, s->dbgM, s->dbgMG,
-                    s->st, s->poses, s->surf_rest, s->surf_acc, s->out_tmp};
+                    s->st, s->poses, s->surf_rest, s->surf_acc, s->out_tmp, s->d_args};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     for (int k = 0; k < 2; ++k) {
@@ -574,52 +673,26 @@ int sim_set_tile_threads(sim_t* s, int32_t tx, int32_t ty, int32_t tz, int32_t t
 int sim_step(sim_t* s, int32_t n_substeps) {
     if (!s) return SIM_EINVAL;
     if (n_substeps < 1) return fail(s, SIM_EINVAL, "n_substeps must be >= 1");
-    const sim_params& P = s->P;
-    const long long N = (long long)n_substeps * P.subcycle;
-    const double h = P.dt / (double)P.subcycle;
-    if (N > s->pose_cap) {
-        HIPCHK(s, hipStreamSynchronize(s->stream));
-        if (s->poses) (void)hipFree(s->poses);
-        s->poses = nullptr;
-        HIPCHK(s, hipMalloc(&s->poses, N * sizeof(StepPose)));
-        s->pose_cap = N;
-    }
-    const int b = s->stage_next;
-    s->stage_next ^= 1;
-    if (!s->stage_ev[b]) HIPCHK(s, hipEventCreateWithFlags(&s->stage_ev[b], hipEventDisableTiming));
-    HIPCHK(s, hipEventSynchronize(s->stage_ev[b]));   // the copy that last read this buffer
-    if (N > s->stage_cap[b]) {
-        if (s->stage[b]) (void)hipHostFree(s->stage[b]);
-        s->stage[b] = nullptr;
-        HIPCHK(s, hipHostMalloc(&s->stage[b], N * sizeof(StepPose), hipHostMallocDefault));
-        s->stage_cap[b] = N;
-    }
-    StepPose* poses = s->stage[b];
-    std::vector<int> npass(N);
-    for (long long j = 0; j < N; ++j) {
-        StepPose& sp = poses[j];
-        make_pose(s, j, N, h, &sp);
-        if (s->forced_pos < s->forced.size()) sp.forced = s->forced[s->forced_pos++];
-        if (sp.forced > 0) npass[j] = sp.forced;
-        else if (P.mode == SIM_MODE_PLAIN || sp.gnorm <= 1e-9) npass[j] = 1;
-        else npass[j] = P.rest_limit;
-    }
-    HIPCHK(s, hipMemcpyAsync(s->poses, poses, N * sizeof(StepPose), hipMemcpyHostToDevice, s->stream));
-    HIPCHK(s, hipEventRecord(s->stage_ev[b], s->stream));
-    KArgs a = kargs(s);
-    const TileOps& ops = kTileOps[s->tile_idx];
-    const int node_blocks = (int)((s->n_nodes + kBlock - 1) / kBlock);
+    std::vector<int> npass;
+    int rc = prepare_step(s, n_substeps, npass);
+    if (rc) return rc;
+    const long long N = (long long)npass.size();
+    LaunchSet L;
+    L.ops = &kTileOps[s->tile_idx];
+    L.m = BatchMap{s->d_args, nullptr, nullptr, 1};
+    L.tile_blocks = s->n_tiles;
+    L.node_blocks = (int)((s->n_nodes + kBlock - 1) / kBlock);
+    L.n = 1;
+    L.limit_slots = std::min(34, s->P.rest_limit + 2);
+    L.st = s->stream;
     if (!s->pending) {
-        ops.p2g(a, s->order[s->cur], s->bstart[s->cur], s->stream);
+        L.ops->p2g(L.m, L.tile_blocks, s->cur, s->stream);
         HIPCHK(s, hipGetLastError());
         s->sbin = s->cur;
     }
-    const int limit_slots = std::min(34, P.rest_limit + 2);
+    int cur = s->cur, sbin = s->sbin;
+    long long g = s->gstep;
     for (long long j = 0; j < N; ++j) {
-        const int c = s->cur;
-        const int store = j == N - 1 ? 1 : 0;
-        // the partials were written under the binning of the pass that made them
-        ops.grid(a, s->bstart[s->sbin], (int)j, 0, false, node_blocks, s->stream);
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (s->prof) {
             while (s->ev_pool.size() < s->ev_used + 2) {
@@ -629,26 +702,14 @@ int sim_step(sim_t* s, int32_t n_substeps) {
             }
             e0 = s->ev_pool[s->ev_used++];
             e1 = s->ev_pool[s->ev_used++];
-            HIPCHK(s, hipEventRecord(e0, s->stream));
         }
-        ops.g2p2g(a, s->order[c], s->bstart[c], (int)j, s->gstep, 0, store, false, s->stream);
-        if (s->prof) HIPCHK(s, hipEventRecord(e1, s->stream));
-        for (int pass = 1; pass < npass[j]; ++pass) {
-            ops.grid(a, s->bstart[c], (int)j, pass, true, node_blocks, s->stream);
-            ops.g2p2g(a, s->order[c], s->bstart[c], (int)j, s->gstep, pass, store, true, s->stream);
-        }
-        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s->stream, a, s->bstart[c ^ 1], limit_slots);
-        hipLaunchKernelGGL(k_scatter, dim3(s->n_tiles), dim3(kBlock), 0, s->stream, a, s->order[c],
-                           s->bstart[c], s->bstart[c ^ 1], s->order[c ^ 1]);
+        launch_step(L, (int)j, npass[j], cur, sbin, (int)(g & 1), j == N - 1 ? 1 : 0, e0, e1);
         HIPCHK(s, hipGetLastError());
-        s->sbin = c;
-        s->cur ^= 1;
-        s->gstep += 1;
+        sbin = cur;
+        cur ^= 1;
+        g += 1;
     }
-    s->pending = true;
-    std::memcpy(s->pos, s->tpos, sizeof(s->pos));
-    std::memcpy(s->quat, s->tquat, sizeof(s->quat));
-    s->substeps += n_substeps;
+    finish_call(s, n_substeps, N);
     return SIM_OK;
 }
 
@@ -664,7 +725,7 @@ static int surface_raster(sim_t* s, float* out, int W, int H, int on_device, int
     if (npix > s->surf_cap) {
         if (s->surf_acc) (void)hipFree(s->surf_acc);
         s->surf_acc = nullptr;
-        HIPCHK(s, hipMalloc(&s->surf_acc, npix * sizeof(float4)));
+        HIPCHK(s, hipMalloc(&s->surf_acc, npix * 4 * sizeof(unsigned long long)));
         s->surf_cap = npix;
     }
     const long long nout = npix * (mode == 0 ? 1 : 3);
@@ -688,11 +749,11 @@ static int surface_raster(sim_t* s, float* out, int W, int H, int on_device, int
     sa.n = s->n;
     sa.rest_r = s->surf_rest;
     sa.acc = s->surf_acc;
-    hipLaunchKernelGGL(k_fill, dim3(std::min<long long>((npix * 4 + 255) / 256, 4096)), dim3(256), 0, s->stream,
-                       reinterpret_cast<float*>(s->surf_acc), npix * 4, 0.0f);
+    hipLaunchKernelGGL(k_fill, dim3(std::min<long long>((npix * 8 + 255) / 256, 4096)), dim3(256), 0, s->stream,
+                       reinterpret_cast<float*>(s->surf_acc), npix * 8, 0.0f);
     hipLaunchKernelGGL(k_surface_accum, dim3((unsigned)((s->n + 255) / 256)), dim3(256), 0, s->stream, a, sa);
     hipLaunchKernelGGL(k_surface_finish, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, s->stream,
-                       s->surf_acc, (int)npix, (float)(s->P.cells[2] * s->P.dx), mode, dst);
+                       s->surf_acc, (int)npix, (float)(s->P.cells[2] * s->P.dx), (float)s->P.dx, mode, dst);
     HIPCHK(s, hipGetLastError());
     if (!on_device) {
         HIPCHK(s, hipMemcpyAsync(out, dst, nout * sizeof(float), hipMemcpyDeviceToHost, s->stream));
@@ -890,5 +951,297 @@ int sim_profile_read(sim_t* s, double* ms_total, int64_t* launches) {
 }
 
 const char* sim_last_error(const sim_t* s) { return s ? s->err.c_str() : "null handle"; }
+
+// ------------------------------------------------------------------ batched sensors
+
+}  // extern "C"
+
+struct sim_batch_s {
+    std::vector<sim_t*> sims;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    struct Group {
+        int tile_idx = 0;
+        std::vector<int> members;
+        KArgs* d_args = nullptr;
+        int* d_tile_base = nullptr;
+        int* d_node_base = nullptr;
+        int tile_blocks = 0, node_blocks = 0;
+        std::vector<KArgs> h_args;
+    };
+    std::vector<Group> groups;
+    std::string err;
+};
+
+static int bfail(sim_batch_t* b, int code, const std::string& msg) {
+    if (b) b->err = msg;
+    return code;
+}
+
+#define BHIPCHK(b, call)                                                                   \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return bfail((b), SIM_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// Group the sensors by tile shape; per group the device records of its members
+// and the prefix sums that map a launch's blocks to (sensor, tile / node block).
+static int batch_build_groups(sim_batch_t* b) {
+    for (auto& g : b->groups) {
+        (void)hipFree(g.d_args);
+        (void)hipFree(g.d_tile_base);
+        (void)hipFree(g.d_node_base);
+    }
+    b->groups.clear();
+    for (int i = 0; i < (int)b->sims.size(); ++i) {
+        const int t = b->sims[i]->tile_idx;
+        int gi = -1;
+        for (int k = 0; k < (int)b->groups.size(); ++k)
+            if (b->groups[k].tile_idx == t) gi = k;
+        if (gi < 0) {
+            b->groups.emplace_back();
+            gi = (int)b->groups.size() - 1;
+            b->groups[gi].tile_idx = t;
+        }
+        b->groups[gi].members.push_back(i);
+    }
+    for (auto& g : b->groups) {
+        const int n = (int)g.members.size();
+        std::vector<int> tb(n + 1, 0), nb(n + 1, 0);
+        for (int k = 0; k < n; ++k) {
+            const sim_t* s = b->sims[g.members[k]];
+            tb[k + 1] = tb[k] + s->n_tiles;
+            nb[k + 1] = nb[k] + (int)((s->n_nodes + kBlock - 1) / kBlock);
+        }
+        g.tile_blocks = tb[n];
+        g.node_blocks = nb[n];
+        BHIPCHK(b, hipMalloc(&g.d_args, n * sizeof(KArgs)));
+        BHIPCHK(b, hipMalloc(&g.d_tile_base, (n + 1) * sizeof(int)));
+        BHIPCHK(b, hipMalloc(&g.d_node_base, (n + 1) * sizeof(int)));
+        BHIPCHK(b, hipMemcpy(g.d_tile_base, tb.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice));
+        BHIPCHK(b, hipMemcpy(g.d_node_base, nb.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice));
+        g.h_args.assign(n, KArgs());
+    }
+    return SIM_OK;
+}
+
+static int batch_sync_args(sim_batch_t* b) {
+    for (auto& g : b->groups) {
+        bool changed = false;
+        for (int k = 0; k < (int)g.members.size(); ++k) {
+            const KArgs a = kargs(b->sims[g.members[k]]);
+            if (std::memcmp(&a, &g.h_args[k], sizeof(KArgs)) != 0) {
+                g.h_args[k] = a;
+                changed = true;
+            }
+        }
+        if (changed) {
+            BHIPCHK(b, hipStreamSynchronize(b->stream));
+            BHIPCHK(b, hipMemcpy(g.d_args, g.h_args.data(), g.members.size() * sizeof(KArgs),
+                                 hipMemcpyHostToDevice));
+        }
+    }
+    return SIM_OK;
+}
+
+extern "C" {
+
+int sim_batch_create(const sim_params* params, int32_t n, const int32_t* tiles, void* hip_stream,
+                     sim_batch_t** out) {
+    if (!out || !params || n < 1) return SIM_EINVAL;
+    *out = nullptr;
+    for (int i = 1; i < n; ++i)
+        if (params[i].dt != params[0].dt || params[i].subcycle != params[0].subcycle ||
+            params[i].rest_limit != params[0].rest_limit) {
+            std::fprintf(stderr, "sim_batch_create: sensors of a batch share dt, subcycle and rest_limit\n");
+            return SIM_EINVAL;
+        }
+    sim_batch_t* b = new sim_batch_t();
+    if (hip_stream) {
+        b->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreate(&b->stream) != hipSuccess) { delete b; return SIM_EHIP; }
+        b->own_stream = true;
+    }
+    for (int i = 0; i < n; ++i) {
+        sim_t* s = nullptr;
+        int rc = sim_create(&params[i], b->stream, &s);
+        if (rc) { sim_batch_destroy(b); return rc; }
+        b->sims.push_back(s);
+        if (tiles) {
+            rc = sim_set_tile_threads(s, tiles[4 * i], tiles[4 * i + 1], tiles[4 * i + 2], tiles[4 * i + 3]);
+            if (rc) {
+                std::fprintf(stderr, "sim_batch_create: sensor %d: %s\n", i, s->err.c_str());
+                sim_batch_destroy(b);
+                return rc;
+            }
+        }
+    }
+    int rc = batch_build_groups(b);
+    if (rc) { sim_batch_destroy(b); return rc; }
+    *out = b;
+    return SIM_OK;
+}
+
+void sim_batch_destroy(sim_batch_t* b) {
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    for (auto& g : b->groups) {
+        (void)hipFree(g.d_args);
+        (void)hipFree(g.d_tile_base);
+        (void)hipFree(g.d_node_base);
+    }
+    for (sim_t* s : b->sims) sim_destroy(s);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+int sim_batch_size(const sim_batch_t* b, int32_t* n) {
+    if (!b || !n) return SIM_EINVAL;
+    *n = (int32_t)b->sims.size();
+    return SIM_OK;
+}
+
+int sim_batch_get(sim_batch_t* b, int32_t i, sim_t** out) {
+    if (!b || !out || i < 0 || i >= (int)b->sims.size()) return SIM_EINVAL;
+    *out = b->sims[i];
+    return SIM_OK;
+}
+
+int sim_batch_set_indenter_poses(sim_batch_t* b, const double* pos, const double* quat_wxyz) {
+    if (!b || !pos || !quat_wxyz) return bfail(b, SIM_EINVAL, "null argument");
+    for (int i = 0; i < (int)b->sims.size(); ++i) {
+        const int rc = sim_set_indenter_pose(b->sims[i], pos + 3 * i, quat_wxyz + 4 * i);
+        if (rc) return bfail(b, rc, "sensor " + std::to_string(i) + ": " + b->sims[i]->err);
+    }
+    return SIM_OK;
+}
+
+int sim_batch_step(sim_batch_t* b, int32_t n_substeps) {
+    if (!b) return SIM_EINVAL;
+    if (n_substeps < 1) return bfail(b, SIM_EINVAL, "n_substeps must be >= 1");
+    const int n = (int)b->sims.size();
+    std::vector<int> npass_max, npass;
+    for (int i = 0; i < n; ++i) {
+        sim_t* s = b->sims[i];
+        const int rc = prepare_step(s, n_substeps, npass);
+        if (rc) return bfail(b, rc, "sensor " + std::to_string(i) + ": " + s->err);
+        if (npass_max.empty()) npass_max = npass;
+        for (size_t j = 0; j < npass.size(); ++j) npass_max[j] = std::max(npass_max[j], npass[j]);
+    }
+    int rc = batch_sync_args(b);
+    if (rc) return rc;
+    sim_t* s0 = b->sims[0];
+    for (int i = 1; i < n; ++i) {
+        const sim_t* s = b->sims[i];
+        if (s->cur != s0->cur || s->sbin != s0->sbin || s->pending != s0->pending ||
+            ((s->gstep ^ s0->gstep) & 1))
+            return bfail(b, SIM_ESTATE, "sensors of a batch must be stepped together");
+    }
+    const long long N = (long long)npass_max.size();
+    std::vector<LaunchSet> sets;
+    for (auto& g : b->groups) {
+        LaunchSet L;
+        L.ops = &kTileOps[g.tile_idx];
+        L.m = BatchMap{g.d_args, g.d_tile_base, g.d_node_base, (int)g.members.size()};
+        L.tile_blocks = g.tile_blocks;
+        L.node_blocks = g.node_blocks;
+        L.n = (int)g.members.size();
+        L.limit_slots = std::min(34, s0->P.rest_limit + 2);
+        L.st = b->stream;
+        sets.push_back(L);
+    }
+    if (!s0->pending) {
+        for (auto& L : sets) L.ops->p2g(L.m, L.tile_blocks, s0->cur, b->stream);
+        for (sim_t* s : b->sims) s->sbin = s->cur;
+    }
+    int cur = s0->cur, sbin = s0->sbin;
+    long long g = s0->gstep;
+    for (long long j = 0; j < N; ++j) {
+        for (auto& L : sets)
+            launch_step(L, (int)j, npass_max[j], cur, sbin, (int)(g & 1), j == N - 1 ? 1 : 0, nullptr, nullptr);
+        sbin = cur;
+        cur ^= 1;
+        g += 1;
+    }
+    BHIPCHK(b, hipGetLastError());
+    for (sim_t* s : b->sims) finish_call(s, n_substeps, N);
+    return SIM_OK;
+}
+
+int sim_batch_synchronize(sim_batch_t* b) {
+    if (!b) return SIM_EINVAL;
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    for (int i = 0; i < (int)b->sims.size(); ++i) {
+        const int rc = check_device_error(b->sims[i]);
+        if (rc) return bfail(b, rc, "sensor " + std::to_string(i) + ": " + b->sims[i]->err);
+    }
+    return SIM_OK;
+}
+
+int sim_batch_heightmaps(sim_batch_t* b, float* out, int32_t W, int32_t H, int32_t out_on_device) {
+    if (!b || !out || W < 1 || H < 1) return bfail(b, SIM_EINVAL, "bad raster arguments");
+    for (int i = 0; i < (int)b->sims.size(); ++i) {
+        const int rc = sim_surface_heightmap(b->sims[i], out + (size_t)i * W * H, W, H, out_on_device);
+        if (rc) return bfail(b, rc, "sensor " + std::to_string(i) + ": " + b->sims[i]->err);
+    }
+    return SIM_OK;
+}
+
+int sim_batch_displacements(sim_batch_t* b, float* out, int32_t W, int32_t H, int32_t out_on_device) {
+    if (!b || !out || W < 1 || H < 1) return bfail(b, SIM_EINVAL, "bad raster arguments");
+    for (int i = 0; i < (int)b->sims.size(); ++i) {
+        const int rc = sim_surface_displacement(b->sims[i], out + (size_t)i * W * H * 3, W, H, out_on_device);
+        if (rc) return bfail(b, rc, "sensor " + std::to_string(i) + ": " + b->sims[i]->err);
+    }
+    return SIM_OK;
+}
+
+const char* sim_batch_last_error(const sim_batch_t* b) { return b ? b->err.c_str() : "null handle"; }
+
+// Tile-shape autotuner: time `steps` executed steps of a shallow press on a
+// sensor with these parameters for every compiled tile shape (HIP events on
+// the sensor's stream) and return the fastest.
+int sim_autotune_tile(const sim_params* p, int32_t steps, void* hip_stream, int32_t out[4], double* out_ms) {
+    if (!p || !out || steps < 1) return SIM_EINVAL;
+    sim_t* s = nullptr;
+    int rc = sim_create(p, hip_stream, &s);
+    if (rc) return rc;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) { sim_destroy(s); return SIM_EHIP; }
+    double best = 1e300;
+    int best_k = -1;
+    const int sub = std::max(1, steps / std::max(1, p->subcycle));
+    for (int k = 0; k < kNumTileOps && rc == SIM_OK; ++k) {
+        const TileOps& o = kTileOps[k];
+        rc = sim_set_tile_threads(s, o.T[0], o.T[1], o.T[2], o.threads);
+        if (rc) break;
+        double pos[3] = {s->pos[0], s->pos[1], s->pos[2] - 1e-3 * p->dx};
+        rc = sim_set_indenter_pose(s, pos, s->quat);
+        if (!rc) rc = sim_step(s, 1);                       // warm-up
+        if (rc) break;
+        pos[2] -= 1e-3 * p->dx;
+        rc = sim_set_indenter_pose(s, pos, s->quat);
+        if (rc) break;
+        (void)hipEventRecord(e0, s->stream);
+        rc = sim_step(s, sub);
+        (void)hipEventRecord(e1, s->stream);
+        if (rc) break;
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) { best = ms; best_k = k; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc == SIM_OK) rc = check_device_error(s);
+    sim_destroy(s);
+    if (rc) return rc;
+    for (int q = 0; q < 3; ++q) out[q] = kTileOps[best_k].T[q];
+    out[3] = kTileOps[best_k].threads;
+    if (out_ms) *out_ms = best / (double)(sub * p->subcycle);
+    return SIM_OK;
+}
 
 }  // extern "C"

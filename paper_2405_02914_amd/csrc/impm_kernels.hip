@@ -163,11 +163,17 @@ __global__ void k_fill(float* p, long long n, float val) {
 // Stand-alone particle-to-grid of the first exchange of a step (after creation or
 // an external state write): one block per tile, partials to the tile's scratch.
 template <class TL>
-__global__ __launch_bounds__(TL::NT) void k_p2g(KArgs a, const uint32_t* __restrict__ order,
-                                                const uint32_t* __restrict__ bstart) {
+__global__ __launch_bounds__(TL::NT) void k_p2g(BatchMap m, int cur) {
     extern __shared__ unsigned long long lds_u64[];
     unsigned long long* acc = lds_u64;
-    const int t = blockIdx.x;
+    int s = 0, t = blockIdx.x;
+    if (m.tile_base) {
+        s = batch_find(m.tile_base, m.n, t);
+        t -= m.tile_base[s];
+    }
+    const KArgs& a = m.args[s];
+    const uint32_t* __restrict__ order = a.order[cur];
+    const uint32_t* __restrict__ bstart = a.bstart[cur];
     const uint32_t s0 = bstart[t], cnt = bstart[t + 1] - s0;
     if (cnt == 0) return;
     int tc[3];
@@ -197,10 +203,16 @@ __global__ __launch_bounds__(TL::NT) void k_p2g(KArgs a, const uint32_t* __restr
 // EXTRA: the same for the passes after the first of a step, which run only while
 // the relative-rest test fails.
 template <class TL, bool EXTRA>
-__global__ __launch_bounds__(kBlock) void k_grid(KArgs a, const uint32_t* __restrict__ bstart,
-                                                 int step, int pass) {
+__global__ __launch_bounds__(kBlock) void k_grid(BatchMap m, int sbin, int step, int pass) {
+    int s = 0, nb = blockIdx.x;
+    if (m.node_base) {
+        s = batch_find(m.node_base, m.n, nb);
+        nb -= m.node_base[s];
+    }
+    const KArgs& a = m.args[s];
     if (a.st->finished[pass]) return;
-    const long long nid = blockIdx.x * (long long)kBlock + threadIdx.x;
+    const uint32_t* __restrict__ bstart = a.bstart[sbin];
+    const long long nid = nb * (long long)kBlock + threadIdx.x;
     const long long n_nodes = (long long)a.nn[0] * a.nn[1] * a.nn[2];
     if (nid >= n_nodes) return;
     const int i = (int)(nid % a.nn[0]);
@@ -254,15 +266,22 @@ __global__ __launch_bounds__(kBlock) void k_grid(KArgs a, const uint32_t* __rest
 //     otherwise transfer it (same x and F, new v and C) to the next pass's grid.
 // EXTRA marks the launches for passes after the first of a step.
 template <class TL, bool EXTRA>
-__global__ __launch_bounds__(TL::NT) void k_g2p2g(KArgs a, const uint32_t* __restrict__ order,
-                                                  const uint32_t* __restrict__ bstart, int step,
-                                                  long long gstep, int pass, int store_vc) {
+__global__ __launch_bounds__(TL::NT) void k_g2p2g(BatchMap m, int cur, int step, int par, int pass,
+                                                  int store_vc) {
+    int s = 0, t = blockIdx.x;
+    if (m.tile_base) {
+        s = batch_find(m.tile_base, m.n, t);
+        t -= m.tile_base[s];
+    }
+    const KArgs& a = m.args[s];
     if (a.st->finished[pass]) {
         // carry the flag to the next pass slot so that every later pass of the
         // step is skipped as well
-        if (blockIdx.x == 0 && threadIdx.x == 0) a.st->finished[pass + 1] = 1;
+        if (t == 0 && threadIdx.x == 0) a.st->finished[pass + 1] = 1;
         return;
     }
+    const uint32_t* __restrict__ order = a.order[cur];
+    const uint32_t* __restrict__ bstart = a.bstart[cur];
     extern __shared__ unsigned long long lds_u64[];
     unsigned long long* acc = lds_u64;                                   // 4 * PVOL
     float4* gv = reinterpret_cast<float4*>(lds_u64 + 4 * TL::AVOL);      // GVOL
@@ -272,9 +291,7 @@ __global__ __launch_bounds__(TL::NT) void k_g2p2g(KArgs a, const uint32_t* __res
     int* sh = running + kDirs;                                           // [0] = final
 
     const int tid = threadIdx.x;
-    const int t = blockIdx.x;
     const StepPose& sp = a.poses[step];
-    const int par = (int)(gstep & 1);
 
     // ---- 1. relative-rest decision
     if (tid < 27) {
@@ -528,8 +545,9 @@ __global__ __launch_bounds__(TL::NT) void k_g2p2g(KArgs a, const uint32_t* __res
 // Counting sort, scan part: exclusive prefix sum of the next step's tile sizes
 // (accumulated by the fused kernel), one block; clears the counts and the
 // per-step loop flags for the next step.
-__global__ __launch_bounds__(1024) void k_scan(KArgs a, uint32_t* __restrict__ bstart_next,
-                                               int limit_slots) {
+__global__ __launch_bounds__(1024) void k_scan(BatchMap m, int next, int limit_slots) {
+    const KArgs& a = m.args[blockIdx.x];
+    uint32_t* __restrict__ bstart_next = a.bstart[next];
     __shared__ uint32_t part[1024];
     __shared__ uint32_t carry;
     const int tid = threadIdx.x;
@@ -562,12 +580,18 @@ __global__ __launch_bounds__(1024) void k_scan(KArgs a, uint32_t* __restrict__ b
 // Counting sort, scatter part: the particles of tile t that move in direction
 // d go to next-order positions bstart_next[t + d] + (particles that entered
 // t + d from the directions before d, in a fixed order) + rank.
-__global__ __launch_bounds__(kBlock) void k_scatter(KArgs a, const uint32_t* __restrict__ order,
-                                                    const uint32_t* __restrict__ bstart,
-                                                    const uint32_t* __restrict__ bstart_next,
-                                                    uint32_t* __restrict__ order_next) {
+__global__ __launch_bounds__(kBlock) void k_scatter(BatchMap m, int cur) {
     __shared__ uint32_t off[kDirs];
-    const int t = blockIdx.x;
+    int s = 0, t = blockIdx.x;
+    if (m.tile_base) {
+        s = batch_find(m.tile_base, m.n, t);
+        t -= m.tile_base[s];
+    }
+    const KArgs& a = m.args[s];
+    const uint32_t* __restrict__ order = a.order[cur];
+    const uint32_t* __restrict__ bstart = a.bstart[cur];
+    const uint32_t* __restrict__ bstart_next = a.bstart[cur ^ 1];
+    uint32_t* __restrict__ order_next = a.order[cur ^ 1];
     const uint32_t s0 = bstart[t], cnt = bstart[t + 1] - s0;
     if (cnt == 0) return;
     const int tid = threadIdx.x;
@@ -611,7 +635,9 @@ __global__ __launch_bounds__(kBlock) void k_scatter(KArgs a, const uint32_t* __r
 }
 
 // Surface raster: every surface particle adds its quadratic B-spline weights
-// (pitch = pixel size) and weighted displacement to a W x H accumulator.
+// (pitch = pixel size) and weighted displacement (in cells) to a W x H
+// accumulator of 64-bit fixed-point sums (2^-32), so the maps are exact and
+// independent of the order of the atomics.
 __global__ void k_surface_accum(KArgs a, SurfArgs s) {
     const long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (id >= a.n) return;
@@ -628,8 +654,7 @@ __global__ void k_surface_accum(KArgs a, SurfArgs s) {
     load_particle(a, id, cell, f);
     const int rc[3] = {ci + s.pad_l, cj + s.pad_l, ck + s.pad_b};
     float u[3];
-    for (int q = 0; q < 3; ++q)
-        u[q] = ((float)(cell[q] - rc[q]) + (f[q] - s.rest_r[3 * sidx + q])) * s.dx;
+    for (int q = 0; q < 3; ++q) u[q] = (float)(cell[q] - rc[q]) + (f[q] - s.rest_r[3 * sidx + q]);
     const double px = ((double)(cell[0] - s.pad_l) + (double)f[0]) / s.pitch_x - 0.5;
     const double py = ((double)(cell[1] - s.pad_l) + (double)f[1]) / s.pitch_y - 0.5;
     const int bx = (int)floor(px + 0.5) - 1, by = (int)floor(py + 0.5) - 1;
@@ -647,42 +672,41 @@ __global__ void k_surface_accum(KArgs a, SurfArgs s) {
         for (int cx = 0; cx < 3; ++cx) {
             const int ux = bx + cx;
             if (ux < 0 || ux >= s.W) continue;
-            const float wt = wx[cx] * wy[cy];
+            const float wt = wx[cx] * wy[cy] * kFixScaleF;
             if (wt == 0.f) continue;
-            float* d = reinterpret_cast<float*>(s.acc + (size_t)vy * s.W + ux);
-            atomicAdd(d + 0, wt);
-            atomicAdd(d + 1, wt * u[0]);
-            atomicAdd(d + 2, wt * u[1]);
-            atomicAdd(d + 3, wt * u[2]);
+            unsigned long long* d = s.acc + 4 * ((size_t)vy * s.W + ux);
+            atomicAdd(d + 0, to_fixed_scaled(wt, kFixMagic));
+            atomicAdd(d + 1, to_fixed_scaled(wt * u[0], kFixMagic));
+            atomicAdd(d + 2, to_fixed_scaled(wt * u[1], kFixMagic));
+            atomicAdd(d + 3, to_fixed_scaled(wt * u[2], kFixMagic));
         }
     }
 }
 
-__global__ void k_surface_finish(const float4* __restrict__ acc, int npix, float top, int mode,
-                                 float* __restrict__ out) {
+__global__ void k_surface_finish(const unsigned long long* __restrict__ acc, int npix, float top,
+                                 float dx, int mode, float* __restrict__ out) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= npix) return;
-    const float4 c = acc[q];
-    const float inv = c.x > 0.f ? 1.0f / c.x : 0.f;
+    long long v[4];
+    for (int k = 0; k < 4; ++k) v[k] = ((long long)(acc[4 * q + k] << 13)) >> 13;
+    const double inv = v[0] > 0 ? (double)dx / (double)v[0] : 0.0;
     if (mode == 0) {
-        out[q] = top + c.w * inv;
+        out[q] = top + (float)((double)v[3] * inv);
     } else {
-        out[3 * q + 0] = c.y * inv;
-        out[3 * q + 1] = c.z * inv;
-        out[3 * q + 2] = c.w * inv;
+        out[3 * q + 0] = (float)((double)v[1] * inv);
+        out[3 * q + 1] = (float)((double)v[2] * inv);
+        out[3 * q + 2] = (float)((double)v[3] * inv);
     }
 }
 
 // Tile shapes compiled into the library (cells per axis): explicit kernel
 // instantiations, seen by both the device and the host compilation pass.
-#define IMPM_TILE_KERNELS(X, Y, Z, N)                                                                  \
-    template __global__ void k_p2g<Tile<X, Y, Z, N>>(KArgs, const uint32_t*, const uint32_t*);         \
-    template __global__ void k_grid<Tile<X, Y, Z, N>, false>(KArgs, const uint32_t*, int, int);        \
-    template __global__ void k_grid<Tile<X, Y, Z, N>, true>(KArgs, const uint32_t*, int, int);         \
-    template __global__ void k_g2p2g<Tile<X, Y, Z, N>, false>(KArgs, const uint32_t*, const uint32_t*, \
-                                                              int, long long, int, int);               \
-    template __global__ void k_g2p2g<Tile<X, Y, Z, N>, true>(KArgs, const uint32_t*, const uint32_t*,  \
-                                                             int, long long, int, int);
+#define IMPM_TILE_KERNELS(X, Y, Z, N)                                                             \
+    template __global__ void k_p2g<Tile<X, Y, Z, N>>(BatchMap, int);                              \
+    template __global__ void k_grid<Tile<X, Y, Z, N>, false>(BatchMap, int, int, int);            \
+    template __global__ void k_grid<Tile<X, Y, Z, N>, true>(BatchMap, int, int, int);             \
+    template __global__ void k_g2p2g<Tile<X, Y, Z, N>, false>(BatchMap, int, int, int, int, int); \
+    template __global__ void k_g2p2g<Tile<X, Y, Z, N>, true>(BatchMap, int, int, int, int, int);
 IMPM_TILE_KERNELS(8, 8, 2, 256)
 IMPM_TILE_KERNELS(8, 8, 2, 512)
 IMPM_TILE_KERNELS(4, 8, 4, 256)
@@ -701,24 +725,24 @@ IMPM_TILE_KERNELS(8, 8, 8, 512)
 template <int TX, int TY, int TZ, int NB>
 struct TileLaunch {
     using TL = Tile<TX, TY, TZ, NB>;
-    static void p2g(const KArgs& a, const uint32_t* order, const uint32_t* bstart, hipStream_t st) {
-        hipLaunchKernelGGL(k_p2g<TL>, dim3(a.n_tiles), dim3(NB), TL::LDS_P2G, st, a, order, bstart);
+    static void p2g(const BatchMap& m, int tile_blocks, int cur, hipStream_t st) {
+        hipLaunchKernelGGL(k_p2g<TL>, dim3(tile_blocks), dim3(NB), TL::LDS_P2G, st, m, cur);
     }
-    static void grid(const KArgs& a, const uint32_t* bstart, int step, int pass, bool extra, int blocks,
+    static void grid(const BatchMap& m, int node_blocks, int sbin, int step, int pass, bool extra,
                      hipStream_t st) {
         if (extra)
-            hipLaunchKernelGGL((k_grid<TL, true>), dim3(blocks), dim3(kBlock), 0, st, a, bstart, step, pass);
+            hipLaunchKernelGGL((k_grid<TL, true>), dim3(node_blocks), dim3(kBlock), 0, st, m, sbin, step, pass);
         else
-            hipLaunchKernelGGL((k_grid<TL, false>), dim3(blocks), dim3(kBlock), 0, st, a, bstart, step, pass);
+            hipLaunchKernelGGL((k_grid<TL, false>), dim3(node_blocks), dim3(kBlock), 0, st, m, sbin, step, pass);
     }
-    static void g2p2g(const KArgs& a, const uint32_t* order, const uint32_t* bstart, int step, long long gstep,
-                      int pass, int store_vc, bool extra, hipStream_t st) {
+    static void g2p2g(const BatchMap& m, int tile_blocks, int cur, int step, int par, int pass, int store_vc,
+                      bool extra, hipStream_t st) {
         if (extra)
-            hipLaunchKernelGGL((k_g2p2g<TL, true>), dim3(a.n_tiles), dim3(NB), TL::LDS_G2P2G, st, a, order,
-                               bstart, step, gstep, pass, store_vc);
+            hipLaunchKernelGGL((k_g2p2g<TL, true>), dim3(tile_blocks), dim3(NB), TL::LDS_G2P2G, st, m, cur, step,
+                               par, pass, store_vc);
         else
-            hipLaunchKernelGGL((k_g2p2g<TL, false>), dim3(a.n_tiles), dim3(NB), TL::LDS_G2P2G, st, a,
-                               order, bstart, step, gstep, pass, store_vc);
+            hipLaunchKernelGGL((k_g2p2g<TL, false>), dim3(tile_blocks), dim3(NB), TL::LDS_G2P2G, st, m, cur, step,
+                               par, pass, store_vc);
     }
     static constexpr TileOps ops() {
         return TileOps{{TX, TY, TZ}, NB, TL::PVOL, TL::LDS_G2P2G, &p2g, &grid, &g2p2g};

@@ -53,7 +53,11 @@ EXPORTS = ("sim_params_default", "sim_create", "sim_destroy", "sim_set_indenter_
            "sim_synchronize", "sim_surface_heightmap", "sim_surface_displacement", "sim_get_stats",
            "sim_num_particles", "sim_grid_dims", "sim_read_particles", "sim_write_particles",
            "sim_read_rest", "sim_debug_keep_grid", "sim_read_grid", "sim_debug_force_passes",
-           "sim_set_tile", "sim_set_tile_threads", "sim_profile", "sim_profile_read", "sim_last_error")
+           "sim_set_tile", "sim_set_tile_threads", "sim_profile", "sim_profile_read", "sim_last_error",
+           "sim_batch_create", "sim_batch_destroy", "sim_batch_size", "sim_batch_get",
+           "sim_batch_set_indenter_poses", "sim_batch_step", "sim_batch_synchronize",
+           "sim_batch_heightmaps", "sim_batch_displacements", "sim_batch_last_error",
+           "sim_autotune_tile")
 
 _lib = None
 
@@ -92,8 +96,22 @@ def lib():
     L.sim_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     L.sim_last_error.argtypes = [vp]
     L.sim_last_error.restype = C.c_char_p
+    L.sim_batch_create.argtypes = [C.POINTER(sim_params), i32, vp, vp, C.POINTER(vp)]
+    L.sim_batch_destroy.argtypes = [vp]
+    L.sim_batch_destroy.restype = None
+    L.sim_batch_size.argtypes = [vp, C.POINTER(C.c_int32)]
+    L.sim_batch_get.argtypes = [vp, i32, C.POINTER(vp)]
+    L.sim_batch_set_indenter_poses.argtypes = [vp, dp, dp]
+    L.sim_batch_step.argtypes = [vp, i32]
+    L.sim_batch_synchronize.argtypes = [vp]
+    L.sim_batch_heightmaps.argtypes = [vp, fp, i32, i32, i32]
+    L.sim_batch_displacements.argtypes = [vp, fp, i32, i32, i32]
+    L.sim_batch_last_error.argtypes = [vp]
+    L.sim_batch_last_error.restype = C.c_char_p
+    L.sim_autotune_tile.argtypes = [C.POINTER(sim_params), i32, vp, C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_double)]
     for name in EXPORTS:
-        if name not in ("sim_destroy", "sim_last_error"):
+        if name not in ("sim_destroy", "sim_last_error", "sim_batch_destroy", "sim_batch_last_error"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -246,3 +264,106 @@ def sim_params_default() -> sim_params:
     if rc != SIM_OK:
         raise SimError(rc, "sim_params_default")
     return p
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream().cuda_stream
+    return C.c_void_p(stream)
+
+
+class _Borrowed(Sim):
+    """A sensor owned by a batch (not destroyed by Python)."""
+
+    def __init__(self, handle, params):
+        self.params = params
+        self.h = handle
+        n = C.c_int64()
+        self._chk(lib().sim_num_particles(self.h, C.byref(n)))
+        self.n = n.value
+        d = (C.c_int32 * 3)()
+        self._chk(lib().sim_grid_dims(self.h, d))
+        self.nodes = tuple(d)
+        self.n_nodes = int(np.prod(self.nodes))
+
+    def close(self):
+        self.h = None
+
+
+class Batch:
+    """Many independent sensors stepped together (a sim_batch_t handle)."""
+
+    def __init__(self, params_list, tiles=None, stream=None):
+        n = len(params_list)
+        arr = (sim_params * n)(*[to_params(p) for p in params_list])
+        self._arr = arr
+        t = None
+        if tiles is not None:
+            t = np.ascontiguousarray(np.asarray(tiles, np.int32).reshape(n, 4))
+        h = C.c_void_p()
+        rc = lib().sim_batch_create(arr, n, _p(t), _stream(stream), C.byref(h))
+        if rc != SIM_OK:
+            raise SimError(rc, "sim_batch_create rejected the parameters")
+        self.h = h
+        self.n = n
+        self.sensors = []
+        for i in range(n):
+            sh = C.c_void_p()
+            self._chk(lib().sim_batch_get(self.h, i, C.byref(sh)))
+            self.sensors.append(_Borrowed(sh, params_list[i]))
+
+    def _chk(self, rc):
+        if rc != SIM_OK:
+            raise SimError(rc, lib().sim_batch_last_error(self.h).decode() if self.h else "")
+
+    def close(self):
+        if getattr(self, "h", None):
+            for s in self.sensors:
+                s.close()
+            lib().sim_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sim_batch_set_indenter_poses(self, pos, quat):
+        self._chk(lib().sim_batch_set_indenter_poses(self.h, _p(np.ascontiguousarray(pos, np.float64)),
+                                                     _p(np.ascontiguousarray(quat, np.float64))))
+
+    def sim_batch_step(self, n):
+        self._chk(lib().sim_batch_step(self.h, int(n)))
+
+    def sim_batch_synchronize(self):
+        self._chk(lib().sim_batch_synchronize(self.h))
+
+    def sim_batch_heightmaps(self, W, H, out=None):
+        if out is not None:
+            self._chk(lib().sim_batch_heightmaps(self.h, C.c_void_p(out.data_ptr()), W, H, 1))
+            return out
+        o = np.zeros((self.n, H, W), np.float32)
+        self._chk(lib().sim_batch_heightmaps(self.h, _p(o), W, H, 0))
+        return o
+
+    def sim_batch_displacements(self, W, H, out=None):
+        if out is not None:
+            self._chk(lib().sim_batch_displacements(self.h, C.c_void_p(out.data_ptr()), W, H, 1))
+            return out
+        o = np.zeros((self.n, H, W, 3), np.float32)
+        self._chk(lib().sim_batch_displacements(self.h, _p(o), W, H, 0))
+        return o
+
+
+def sim_autotune_tile(params, steps=8, stream=None):
+    """Fastest compiled tile shape (tx, ty, tz, threads) for these sensor
+    parameters and its time per executed step (ms)."""
+    q = to_params(params)
+    out = (C.c_int32 * 4)()
+    ms = C.c_double()
+    rc = lib().sim_autotune_tile(C.byref(q), int(steps), _stream(stream), out, C.byref(ms))
+    if rc != SIM_OK:
+        raise SimError(rc, "sim_autotune_tile")
+    return tuple(out), ms.value

@@ -188,3 +188,67 @@ def random_state(params: SensorParams, x_rest: np.ndarray, seed: int,
     G = rng.normal(0.0, g_scale, size=(n, 3, 3))
     return (representable_positions(params, x), v.astype(np.float32),
             C.astype(np.float32), G.astype(np.float32))
+
+
+def _schedule(pose0, n_total, press, slip, slip_dir, rot_deg, frame=50, press_frac=0.25):
+    """Press `press` straight down over the first press_frac of the substeps,
+    then slip `slip` along direction slip_dir (radians in the x-y plane) while
+    rotating rot_deg about the normal over the rest; segments end at frame
+    boundaries and at the phase change.  Returns (n, target_pos, target_quat)."""
+    x0, y0, z0 = pose0[:3]
+    n_press = int(round(n_total * press_frac))
+    cuts = sorted(set(list(range(frame, n_total + 1, frame)) + [n_press, n_total]))
+    segs, done = [], 0
+    for end in cuts:
+        if end <= done:
+            continue
+        if end <= n_press:
+            a = end / n_press
+            pos, q = (x0, y0, z0 - press * a), (1.0, 0.0, 0.0, 0.0)
+        else:
+            b = (end - n_press) / (n_total - n_press)
+            pos = (x0 + slip * b * math.cos(slip_dir), y0 + slip * b * math.sin(slip_dir), z0 - press)
+            q = quat_about_z(rot_deg * b)
+        segs.append((end - done, pos, q))
+        done = end
+    return segs
+
+
+def config3(n_sensors: int = 64, seed: int = 3, k_range=(4, 12), dx: float = 0.5e-3,
+            n_substeps: int = 500, subcycle: int = 2):
+    """Batch of independent sensors: cells (8k, 8k, 2k) with k ~ U{k_range}, 8
+    particles per cell; indenter ~ U{sphere r 2-6 mm, capsule r 2-4 mm with
+    half-length 1-4 mm, rounded box half-sides 1.5-4 mm}; press depth
+    U[0.3, 1.5] mm over the first quarter of the substeps, then slip U[0, 3] mm in
+    a direction U[0, 2 pi) and rotation U[-45, 45] degrees.  Returns the list of
+    SensorParams and the list of schedules."""
+    rng = np.random.default_rng(seed)
+    params, scheds = [], []
+    pad = padding_for(dx)
+    for i in range(n_sensors):
+        k = int(rng.integers(k_range[0], k_range[1] + 1))
+        cells = (8 * k, 8 * k, 2 * k)
+        L, H = 8 * k * dx, 2 * k * dx
+        kind = int(rng.integers(0, 3))
+        if kind == 0:
+            r = float(rng.uniform(2e-3, 6e-3))
+            shape = dict(shape=SHAPE_SPHERE, radius=r)
+            drop = r
+        elif kind == 1:
+            r = float(rng.uniform(2e-3, 4e-3))
+            shape = dict(shape=SHAPE_CAPSULE, radius=r, half_length=float(rng.uniform(1e-3, 4e-3)))
+            drop = r
+        else:
+            hx, hy = float(rng.uniform(1.5e-3, 4e-3)), float(rng.uniform(1.5e-3, 4e-3))
+            shape = dict(shape=SHAPE_BOX, half_extent=(hx, hy, 2e-3), fillet=0.5e-3)
+            drop = 2e-3
+        p = SensorParams(cells=cells, dx=dx, pad_lateral=pad, pad_top=pad, seed=1000 + i,
+                         subcycle=subcycle, pose0=(L / 2, L / 2, H + drop, 1.0, 0.0, 0.0, 0.0),
+                         **shape)
+        press = float(rng.uniform(0.3e-3, 1.5e-3))
+        slip = float(rng.uniform(0.0, 3e-3))
+        ang = float(rng.uniform(0.0, 2 * math.pi))
+        rot = float(rng.uniform(-45.0, 45.0))
+        params.append(p)
+        scheds.append(_schedule(p.pose0, n_substeps, press, slip, ang, rot))
+    return params, scheds
