@@ -15,7 +15,15 @@ with the height map of each 50-substep frame included.  The reported value is
 particle-updates per second: particles x executed steps / wall time.
 
     python bench.py [--gpus 1] [--steps 2000] [--warmup 50]
+    python bench.py --workload batch       # 64 batched sensors, 500 substeps
     python bench.py --copy-calibration     # 1 GiB device copy for counter scaling
+
+The batch workload: 64 independent sensors of 32x32x8 to 96x96x24 cells (dx
+0.5 mm, 8 particles per cell, about 40 M particles in all) with seeded sphere,
+capsule, rounded-box and Perlin height-field indenters pressed 0.3-1.5 mm, then
+slipped 0-3 mm and rotated up to 45 degrees over 500 substeps (2 executed steps
+each); tile shapes from the autotuner per sensor size; every call of the batch
+is one HIP graph launch.  A step is one configured substep of all 64 sensors.
 """
 import argparse
 import json
@@ -52,6 +60,8 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=4, help="oracle executed steps timed")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--tile", default=None, help="tile cells tx,ty,tz[,threads] of the binned order")
+    ap.add_argument("--workload", choices=("sensor", "batch"), default="sensor")
+    ap.add_argument("--graph", type=int, default=None, help="1/0: replay step sequences as HIP graphs")
     return ap.parse_args()
 
 
@@ -106,6 +116,83 @@ def run_frames(sim, segs, first, count, hm_out):
     return done
 
 
+def run_batch_segments(b, scheds, count):
+    """Advance every sensor of the batch `count` substeps along its schedule (the
+    schedules share their segment boundaries)."""
+    done, k = 0, 0
+    while done < count and k < len(scheds[0]):
+        n = scheds[0][k][0]
+        if n > count - done:
+            raise ValueError("steps must cover whole segments of the schedule")
+        b.sim_batch_set_indenter_poses([s[k][1] for s in scheds], [s[k][2] for s in scheds])
+        b.sim_batch_step(n)
+        done += n
+        k += 1
+    return done
+
+
+def bench_batch(args):
+    import numpy as np
+    import torch
+    from paper_2405_02914_amd import impm, workloads as W
+    torch.cuda.set_device(0)
+    params, scheds = W.config3()
+    total = sum(s[0] for s in scheds[0])
+    steps = min(args.steps, total)
+    # autotuned tile shape per sensor size class
+    tiles, tuned = [], {}
+    for p in params:
+        if p.cells not in tuned:
+            t, ms = impm.sim_autotune_tile(p, steps=8)
+            tuned[p.cells] = (t, ms)
+        tiles.append(tuned[p.cells][0])
+    graph = True if args.graph is None else bool(args.graph)
+    if args.warmup:
+        w = impm.Batch(params, tiles=tiles)
+        w.sim_batch_set_graph(graph)
+        run_batch_segments(w, scheds, min(args.warmup, total))
+        w.sim_batch_synchronize()
+        w.close()
+        del w
+    b = impm.Batch(params, tiles=tiles)
+    b.sim_batch_set_graph(graph)
+    hm = torch.empty(len(params) * 128 * 128, device="cuda", dtype=torch.float32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = run_batch_segments(b, scheds, steps)
+    b.sim_batch_heightmaps(128, 128, out=hm)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    b.sim_batch_synchronize()
+    wall = t1 - t0
+    stats = [s.sim_get_stats() for s in b.sensors]
+    ns = [s.n for s in b.sensors]
+    upd = sum(n * st["steps"] for n, st in zip(ns, stats))
+    ppass = sum(n * st["passes"] for n, st in zip(ns, stats))
+    achieved = ALG_BYTES_PER_PARTICLE_PASS * ppass / wall / 1e9
+    out = {
+        "metric": "IMPM particle-updates/s",
+        "value": upd / wall,
+        "unit": "particle-updates/s",
+        "n_gpus": 1, "steps": done, "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / done,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{len(params)} batched IMPM sensors, 32x32x8 to 96x96x24 cells, dx 0.5 mm, "
+                               f"{sum(ns)} particles, mixed sphere/capsule/box/height-field indenters, "
+                               f"press-slip-rotate over {total} substeps",
+                   "particles": sum(ns), "subcycle": params[0].subcycle, "graph": graph,
+                   "passes_per_step": round(ppass / max(upd, 1), 3),
+                   "tiles": {f"{c[0]}x{c[1]}x{c[2]}": list(t) for c, (t, _) in sorted(tuned.items())},
+                   "particle_passes_per_s": ppass / wall},
+        "roofline": {"bound": "hbm", "kernel": "whole step (all kernels, wall clock)",
+                     "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None},
+    }
+    b.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -115,6 +202,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not supported",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.workload == "batch":
+        bench_batch(args)
+        return
     import numpy as np
     import torch
     from paper_2405_02914_amd import impm, workloads as W
@@ -139,7 +229,10 @@ def main():
     sim = impm.Sim(p)
     if args.tile:
         sim.sim_set_tile(*[int(v) for v in args.tile.split(",")])
-    sim.sim_profile(True)
+    if args.graph:
+        sim.sim_set_graph(True)
+    else:
+        sim.sim_profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     run_frames(sim, segs, 0, args.steps, hm)
@@ -152,8 +245,8 @@ def main():
     n = sim.n
     steps_exec = st["steps"]
     value = n * steps_exec / wall
-    avg_ms = kern_ms / max(kern_launches, 1)
-    achieved = ALG_BYTES_PER_PARTICLE_PASS * n / (avg_ms * 1e-3) / 1e9
+    avg_ms = kern_ms / kern_launches if kern_launches else float("nan")
+    achieved = ALG_BYTES_PER_PARTICLE_PASS * n / (avg_ms * 1e-3) / 1e9   # nan when not profiled
     roofline = {"bound": "hbm", "kernel": "k_g2p2g<false>", "achieved": round(achieved, 1),
                 "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                 "traffic": PMC_TRAFFIC_BYTES, "traffic_unit": "bytes/launch",

@@ -51,7 +51,8 @@ enum {
     SIM_ESTATE = -5     /* call not valid in the handle's state */
 };
 
-enum { SIM_SHAPE_NONE = 0, SIM_SHAPE_SPHERE = 1, SIM_SHAPE_CAPSULE = 2, SIM_SHAPE_BOX = 3 };
+enum { SIM_SHAPE_NONE = 0, SIM_SHAPE_SPHERE = 1, SIM_SHAPE_CAPSULE = 2, SIM_SHAPE_BOX = 3,
+       SIM_SHAPE_HEIGHTFIELD = 4 };
 enum { SIM_MODE_IMPM = 0, SIM_MODE_PLAIN = 1 };
 
 /* Device error bits reported by sim_get_stats (SIM_ENUMERIC when non-zero). */
@@ -82,6 +83,16 @@ typedef struct {
     double pose0[7];           /* initial indenter pose: position xyz (m), quaternion wxyz */
     int32_t stress_each_pass;  /* 1: every pass of the loop re-adds the elastic impulse */
     int32_t _pad1;
+    /* SIM_SHAPE_HEIGHTFIELD: the solid above the surface z = h(x, y) (body frame)
+     * over the disc x^2 + y^2 <= hf_half^2; h is the bilinear interpolation of
+     * hf[j * hf_n + i], the height at (-hf_half + i s, -hf_half + j s) with
+     * s = 2 hf_half / (hf_n - 1).  2 <= hf_n <= 4096.  The table is caller
+     * memory, read and copied by sim_create / sim_batch_create only.  The
+     * calibration point x_o is the lowest sample inside the disc. */
+    int32_t hf_n;
+    int32_t _pad2;
+    double hf_half;            /* footprint radius and table half-width (m) */
+    const double* hf;          /* hf_n * hf_n heights (m), row-major by y */
 } sim_params;
 
 typedef struct {
@@ -160,6 +171,12 @@ int sim_debug_force_passes(sim_t* s, const int32_t* passes, int32_t n);
 int sim_set_tile(sim_t* s, int32_t tx, int32_t ty, int32_t tz);
 int sim_set_tile_threads(sim_t* s, int32_t tx, int32_t ty, int32_t tz, int32_t threads);
 
+/* on != 0: each sim_step's launch sequence is captured once as a HIP graph
+ * (per sequence length, pass schedule and buffer parity) and replayed; the
+ * replay computes exactly what the eager launches compute.  Ignored while
+ * sim_profile is on.  Default off. */
+int sim_set_graph(sim_t* s, int32_t on);
+
 /* Time every first-pass fused exchange kernel (grid-to-particle, commit,
  * particle-to-grid) with HIP events on the handle's stream (on != 0).
  * sim_profile_read synchronises, returns the summed kernel time (ms) and the
@@ -186,7 +203,12 @@ int sim_batch_size(const sim_batch_t* b, int32_t* n);
 int sim_batch_get(sim_batch_t* b, int32_t i, sim_t** out);
 /* pos: n x 3, quat_wxyz: n x 4; each sensor's target for the next sim_batch_step. */
 int sim_batch_set_indenter_poses(sim_batch_t* b, const double* pos, const double* quat_wxyz);
+/* Enqueue n_substeps configured substeps of every sensor.  By default the whole
+ * launch sequence of the call is one HIP graph launch (captured on first use per
+ * sequence length and pass schedule, then replayed). */
 int sim_batch_step(sim_batch_t* b, int32_t n_substeps);
+/* on = 0: launch the kernels one by one instead of replaying a graph. */
+int sim_batch_set_graph(sim_batch_t* b, int32_t on);
 int sim_batch_synchronize(sim_batch_t* b);
 /* out: n x H x W (heightmaps) or n x H x W x 3 (displacements), host or device. */
 int sim_batch_heightmaps(sim_batch_t* b, float* out, int32_t W, int32_t H, int32_t out_on_device);

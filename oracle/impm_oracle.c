@@ -23,7 +23,9 @@
  *   - S_p is the fixed-corotated Kirchhoff stress tau = 2mu (F-R) F^T + lambda J (J-1) I,
  *     R the rotation of the polar decomposition of F (Newton iteration of Higham 1986);
  *   - the object is a rigid kinematic collider: every grid node inside the indenter
- *     at the start of the substep takes the rigid velocity (relative rest);
+ *     at the start of the substep takes the rigid velocity (relative rest); its
+ *     shape is a sphere, a capsule rod, a rounded box or a sampled height field
+ *     (the solid above a bilinear surface, over a disc footprint);
  *   - the relative-rest test uses the tangential (x,y) velocity 2-vectors,
  *     |v_e,t - v_o,t| <= threshold |v_o,t|, converged at once if |v_o,t| <= 1e-9 m/s;
  *   - F and x are committed once per substep with the final pass's C and v;
@@ -63,12 +65,19 @@ typedef struct {
     double rest_threshold;     /* threshold of Algorithm 1 */
     double fixed_z_fraction;
     /* indenter */
-    int32_t shape;             /* 0 none, 1 sphere, 2 capsule rod, 3 rounded box */
+    int32_t shape;             /* 0 none, 1 sphere, 2 capsule rod, 3 rounded box, 4 height field */
     int32_t _pad0;
     double radius, half_length, half_extent[3], fillet;
     double pose0[7];           /* position xyz (m), quaternion wxyz body->world */
     int32_t stress_each_pass;  /* 1: every pass of the loop re-adds ME_i (literal Alg. 1) */
     int32_t _pad1;
+    /* height field: hf_n x hf_n body-frame heights (row j, column i) sampled at
+     * (-hf_half + i step, -hf_half + j step), step = 2 hf_half / (hf_n - 1);
+     * copied at creation */
+    int32_t hf_n;
+    int32_t _pad2;
+    double hf_half;
+    const double *hf;
 } orc_params;
 
 typedef struct {
@@ -92,6 +101,7 @@ typedef struct {
     int32_t *pass_log;         /* passes of each executed step, capacity log_cap */
     int64_t log_cap, log_len;
     int32_t error;             /* 1: a stencil left the grid, 2: non-finite state, 3: det F <= 0 */
+    double *hf_copy;           /* the height-field table (shape 4) */
 } orc_sim;
 
 /* ---------------------------------------------------------------- SplitMix64 */
@@ -212,6 +222,24 @@ static void quat_rel_axis_angle(const double *q0, const double *q1, double *axis
 
 /* ---------------------------------------------------------------- indenter */
 
+/* Height-field indenter: bilinear interpolation of the sampled lower surface
+ * at body-frame (x, y); cells outside the table clamp to its edge cells. */
+static double hf_height(const orc_params *P, double x, double y) {
+    int n = P->hf_n;
+    double step = 2.0 * P->hf_half / (double)(n - 1);
+    double u = (x + P->hf_half) / step, v = (y + P->hf_half) / step;
+    int i0 = (int)floor(u), j0 = (int)floor(v);
+    if (i0 < 0) i0 = 0;
+    if (i0 > n - 2) i0 = n - 2;
+    if (j0 < 0) j0 = 0;
+    if (j0 > n - 2) j0 = n - 2;
+    double fu = u - (double)i0, fv = v - (double)j0;
+    const double *t = P->hf;
+    double z0 = (1.0 - fu) * t[j0 * n + i0] + fu * t[j0 * n + i0 + 1];
+    double z1 = (1.0 - fu) * t[(j0 + 1) * n + i0] + fu * t[(j0 + 1) * n + i0 + 1];
+    return (1.0 - fv) * z0 + fv * z1;
+}
+
 /* Signed-distance-like inside test in the body frame (phi <= 0 is inside). */
 static double body_phi(const orc_params *P, const double *p) {
     if (P->shape == 1) {
@@ -231,6 +259,10 @@ static double body_phi(const orc_params *P, const double *p) {
         }
         double inside_part = inmax < 0.0 ? inmax : 0.0;
         return sqrt(out2) + inside_part - P->fillet;
+    } else if (P->shape == 4) {
+        /* the solid above the sampled surface, over a disc of radius hf_half */
+        if (p[0] * p[0] + p[1] * p[1] > P->hf_half * P->hf_half) return 1.0;
+        return hf_height(P, p[0], p[1]) - p[2];
     }
     return 1.0; /* no indenter */
 }
@@ -245,6 +277,23 @@ static void body_lowest_point(const orc_params *P, double *p) {
         p[0] = -(P->half_extent[0] - P->fillet);
         p[1] = -(P->half_extent[1] - P->fillet);
         p[2] = -P->half_extent[2];
+    } else if (P->shape == 4) {
+        /* the lowest table sample inside the footprint disc */
+        int n = P->hf_n;
+        double step = 2.0 * P->hf_half / (double)(n - 1);
+        double best_z = 0.0, best_r2 = 0.0;
+        int found = 0;
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                double x = -P->hf_half + (double)i * step, y = -P->hf_half + (double)j * step;
+                double r2 = x * x + y * y;
+                if (r2 > P->hf_half * P->hf_half) continue;
+                double z = P->hf[j * n + i];
+                int better = !found || z < best_z ||
+                             (z == best_z && (r2 > best_r2 ||
+                                              (r2 == best_r2 && (x < p[0] || (x == p[0] && y < p[1])))));
+                if (better) { found = 1; best_z = z; best_r2 = r2; p[0] = x; p[1] = y; p[2] = z; }
+            }
     }
 }
 
@@ -331,14 +380,24 @@ void orc_destroy(orc_sim *s) {
     free(s->x); free(s->v); free(s->C); free(s->F); free(s->Xrest);
     free(s->bottom); free(s->surface); free(s->M); free(s->MG); free(s->V);
     free(s->forced); free(s->pass_log);
+    free((void *)s->hf_copy);
     free(s);
 }
 
 orc_sim *orc_create(const orc_params *P) {
     int m = cube_root_ppc(P->ppc);
     if (m < 1 || P->cells[0] < 1 || P->cells[1] < 1 || P->cells[2] < 1 || !(P->dx > 0.0)) return NULL;
+    if (P->shape == 4 && (P->hf_n < 2 || !P->hf || !(P->hf_half > 0.0))) return NULL;
     orc_sim *s = (orc_sim *)calloc(1, sizeof(orc_sim));
     s->P = *P;
+    if (P->shape == 4) {
+        size_t nb = (size_t)P->hf_n * P->hf_n * sizeof(double);
+        s->hf_copy = (double *)malloc(nb);
+        memcpy(s->hf_copy, P->hf, nb);
+        s->P.hf = s->hf_copy;
+    } else {
+        s->P.hf = NULL;
+    }
     int Nx = P->cells[0], Ny = P->cells[1], Nz = P->cells[2];
     s->n = (int64_t)Nx * Ny * Nz * P->ppc;
     s->nn[0] = Nx + 2 * P->pad_lateral + 1;

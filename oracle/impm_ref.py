@@ -40,6 +40,8 @@ class _Params(C.Structure):
         ("half_length", C.c_double), ("half_extent", C.c_double * 3),
         ("fillet", C.c_double), ("pose0", C.c_double * 7),
         ("stress_each_pass", C.c_int32), ("_pad1", C.c_int32),
+        ("hf_n", C.c_int32), ("_pad2", C.c_int32), ("hf_half", C.c_double),
+        ("hf", C.POINTER(C.c_double)),
     ]
 
 
@@ -113,6 +115,11 @@ def to_params(p) -> _Params:
     q.fillet = p.fillet
     q.pose0[:] = list(p.pose0)
     q.stress_each_pass = p.stress_each_pass
+    if getattr(p, "hf", None) is not None:
+        t = np.ascontiguousarray(p.hf, np.float64)
+        q.hf_n, q.hf_half = t.shape[0], p.hf_half
+        q.hf = t.ctypes.data_as(C.POINTER(C.c_double))
+        q._keep = t                      # the oracle copies the table at creation
     return q
 
 

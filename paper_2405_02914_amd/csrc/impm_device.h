@@ -57,6 +57,9 @@ struct KArgs {
     int shape;
     float dx, inv_dx, h, h_over_dx, kst, mu2, lam, c4dx;   // c4dx = 4 / dx
     double dxd, rest_threshold, radius, half_length, he[3], fillet;
+    const double* hf;          // height-field table (hf_n x hf_n), shape 4
+    int hf_n;
+    double hf_half;
     float mp;         // particle mass (kg), for the debug grid copy
     long long n;      // particles
     long long e;      // calibration particle id
@@ -244,6 +247,18 @@ __device__ __forceinline__ int node_inside(const KArgs& a, const StepPose& sp, i
         }
         const double inside_part = inmax < 0.0 ? inmax : 0.0;
         phi = sqrt(out2) + inside_part - a.fillet;
+    } else if (a.shape == 4) {
+        // the solid above a bilinear sampled surface over a disc footprint
+        if (p[0] * p[0] + p[1] * p[1] > a.hf_half * a.hf_half) return 0;
+        const int n = a.hf_n;
+        const double step = 2.0 * a.hf_half / (double)(n - 1);
+        const double u = (p[0] + a.hf_half) / step, v = (p[1] + a.hf_half) / step;
+        const int i0 = min(max((int)floor(u), 0), n - 2), j0 = min(max((int)floor(v), 0), n - 2);
+        const double fu = u - (double)i0, fv = v - (double)j0;
+        const double* t = a.hf + (size_t)j0 * n + i0;
+        const double z0 = (1.0 - fu) * t[0] + fu * t[1];
+        const double z1 = (1.0 - fu) * t[n] + fu * t[n + 1];
+        phi = ((1.0 - fv) * z0 + fv * z1) - p[2];
     } else {
         return 0;
     }

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -25,8 +26,57 @@ __global__ void k_surface_finish(const unsigned long long* acc, int npix, float 
 
 using namespace impm;
 
+// Instantiated HIP graphs of step sequences, keyed by everything that is baked
+// into their launches (sequence length, buffer parities, pass counts, tile
+// shapes and grid sizes).  The graphs read every per-call input (poses, kernel
+// records, loop flags) from device memory, so a replay equals the eager launch
+// sequence.  Captured on a library-owned stream and replayed on the caller's.
+struct GraphCache {
+    hipStream_t cap = nullptr;
+    std::map<std::vector<long long>, hipGraphExec_t> execs;
+    void clear() {
+        for (auto& kv : execs) (void)hipGraphExecDestroy(kv.second);
+        execs.clear();
+    }
+    ~GraphCache() {
+        clear();
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
+
+// Capture the launches that emit(stream) enqueues as one graph the first time
+// `key` is seen, then launch the graph on `st`.
+template <class F>
+static hipError_t graph_run(GraphCache& gc, const std::vector<long long>& key, hipStream_t st, F emit) {
+    auto it = gc.execs.find(key);
+    if (it == gc.execs.end()) {
+        hipError_t e;
+        if (!gc.cap && (e = hipStreamCreateWithFlags(&gc.cap, hipStreamNonBlocking)) != hipSuccess) return e;
+        if (gc.execs.size() >= 16) gc.clear();
+        if ((e = hipStreamBeginCapture(gc.cap, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
+        emit(gc.cap);
+        hipGraph_t g = nullptr;
+        const hipError_t el = hipGetLastError();
+        e = hipStreamEndCapture(gc.cap, &g);
+        if (el != hipSuccess || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return el != hipSuccess ? el : e;
+        }
+        hipGraphExec_t x = nullptr;
+        e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return e;
+        it = gc.execs.emplace(key, x).first;
+    }
+    return hipGraphLaunch(it->second, st);
+}
+
 struct sim_s {
     sim_params P;
+    bool use_graph = false;       // replay step sequences as HIP graphs
+    GraphCache graphs;
+    std::vector<double> hf_host;  // height-field table (P.hf points here)
+    double* d_hf = nullptr;
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int device = 0;
@@ -166,6 +216,22 @@ static void lowest_point(const sim_params& P, double* p) {
         p[0] = -(P.half_extent[0] - P.fillet);
         p[1] = -(P.half_extent[1] - P.fillet);
         p[2] = -P.half_extent[2];
+    } else if (P.shape == SIM_SHAPE_HEIGHTFIELD) {
+        // the lowest table sample inside the footprint disc
+        const int n = P.hf_n;
+        const double step = 2.0 * P.hf_half / (double)(n - 1);
+        double bz = 0.0, br2 = 0.0;
+        bool found = false;
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                const double x = -P.hf_half + (double)i * step, y = -P.hf_half + (double)j * step;
+                const double r2 = x * x + y * y;
+                if (r2 > P.hf_half * P.hf_half) continue;
+                const double z = P.hf[(size_t)j * n + i];
+                bool better = !found || z < bz;
+                if (found && z == bz) better = r2 > br2 || (r2 == br2 && (x < p[0] || (x == p[0] && y < p[1])));
+                if (better) { found = true; bz = z; br2 = r2; p[0] = x; p[1] = y; p[2] = z; }
+            }
     }
 }
 
@@ -237,6 +303,9 @@ static KArgs kargs(const sim_t* s) {
     a.half_length = P.half_length;
     for (int q = 0; q < 3; ++q) a.he[q] = P.half_extent[q];
     a.fillet = P.fillet;
+    a.hf = s->d_hf;
+    a.hf_n = P.hf_n;
+    a.hf_half = P.hf_half;
     a.mp = (float)s->mp;
     a.n = s->n;
     a.e = s->e;
@@ -487,7 +556,15 @@ static int validate(const sim_params* p, std::string& why) {
     if (p->rest_limit < 1 || p->rest_limit > 32) { why = "rest_limit must be in [1, 32]"; return SIM_EINVAL; }
     if (!(p->rest_threshold >= 0)) { why = "rest_threshold must be >= 0"; return SIM_EINVAL; }
     if (p->mode != SIM_MODE_IMPM && p->mode != SIM_MODE_PLAIN) { why = "bad mode"; return SIM_EINVAL; }
-    if (p->shape < 0 || p->shape > 3) { why = "bad shape"; return SIM_EINVAL; }
+    if (p->shape < 0 || p->shape > SIM_SHAPE_HEIGHTFIELD) { why = "bad shape"; return SIM_EINVAL; }
+    if (p->shape == SIM_SHAPE_HEIGHTFIELD) {
+        if (!p->hf || p->hf_n < 2 || p->hf_n > 4096 || !(p->hf_half > 0) || !std::isfinite(p->hf_half)) {
+            why = "height field needs hf != NULL, 2 <= hf_n <= 4096 and hf_half > 0";
+            return SIM_EINVAL;
+        }
+        for (long long q = 0; q < (long long)p->hf_n * p->hf_n; ++q)
+            if (!std::isfinite(p->hf[q])) { why = "height field has a non-finite sample"; return SIM_EINVAL; }
+    }
     const int nn[3] = {p->cells[0] + 2 * p->pad_lateral + 1, p->cells[1] + 2 * p->pad_lateral + 1,
                        p->cells[2] + p->pad_bottom + p->pad_top + 1};
     for (int q = 0; q < 3; ++q)
@@ -510,6 +587,13 @@ int sim_create(const sim_params* p, void* hip_stream, sim_t** out) {
     }
     sim_t* s = new sim_t();
     s->P = *p;
+    if (p->shape == SIM_SHAPE_HEIGHTFIELD) {
+        s->hf_host.assign(p->hf, p->hf + (size_t)p->hf_n * p->hf_n);
+        s->P.hf = s->hf_host.data();
+    } else {
+        s->P.hf = nullptr;
+        s->P.hf_n = 0;
+    }
     const sim_params& P = s->P;
     for (int k = 1; k <= 4; ++k) if (k * k * k == P.ppc) s->m = k;
     const int m = s->m;
@@ -541,6 +625,12 @@ int sim_create(const sim_params* p, void* hip_stream, sim_t** out) {
         hipMalloc(&s->st, sizeof(DevState)) != hipSuccess)
         return bail(SIM_ENOMEM);
     if (alloc_tiles(s) != SIM_OK) return bail(SIM_ENOMEM);
+    if (P.shape == SIM_SHAPE_HEIGHTFIELD) {
+        if (hipMalloc(&s->d_hf, s->hf_host.size() * sizeof(double)) != hipSuccess) return bail(SIM_ENOMEM);
+        if (hipMemcpy(s->d_hf, s->hf_host.data(), s->hf_host.size() * sizeof(double), hipMemcpyHostToDevice) !=
+            hipSuccess)
+            return bail(SIM_EHIP);
+    }
 
     // stratified jittered particles: one per sub-cell of the m^3 split of each cell
     std::vector<float> host(n * NPLANES, 0.0f);
@@ -624,7 +714,7 @@ void sim_destroy(sim_t* s) {
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     void* bufs[] = {s->soa, s->cell, s->flags, s->order[0], s->order[1], s->bstart[0], s->bstart[1],
                     s->dirrank, s->dircount, s->newcnt, s->scratch, s->gridV, s->dbgM, s->dbgMG,
-                    s->st, s->poses, s->surf_rest, s->surf_acc, s->out_tmp, s->d_args};
+                    s->st, s->poses, s->surf_rest, s->surf_acc, s->out_tmp, s->d_args, s->d_hf};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     for (int k = 0; k < 2; ++k) {
@@ -692,6 +782,25 @@ int sim_step(sim_t* s, int32_t n_substeps) {
     }
     int cur = s->cur, sbin = s->sbin;
     long long g = s->gstep;
+    if (s->use_graph && !s->prof) {
+        std::vector<long long> key = {N, cur, sbin, g & 1, s->tile_idx, L.tile_blocks, L.node_blocks};
+        key.insert(key.end(), npass.begin(), npass.end());
+        const hipError_t e = graph_run(s->graphs, key, s->stream, [&](hipStream_t cs) {
+            LaunchSet Lc = L;
+            Lc.st = cs;
+            int c = cur, sb = sbin;
+            long long gg = g;
+            for (long long j = 0; j < N; ++j) {
+                launch_step(Lc, (int)j, npass[j], c, sb, (int)(gg & 1), j == N - 1 ? 1 : 0, nullptr, nullptr);
+                sb = c;
+                c ^= 1;
+                gg += 1;
+            }
+        });
+        if (e != hipSuccess) return fail(s, SIM_EHIP, std::string("step graph: ") + hipGetErrorString(e));
+        finish_call(s, n_substeps, N);
+        return SIM_OK;
+    }
     for (long long j = 0; j < N; ++j) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (s->prof) {
@@ -927,6 +1036,16 @@ int sim_debug_force_passes(sim_t* s, const int32_t* passes, int32_t n) {
     return SIM_OK;
 }
 
+int sim_set_graph(sim_t* s, int32_t on) {
+    if (!s) return SIM_EINVAL;
+    s->use_graph = on != 0;
+    if (!s->use_graph) {
+        HIPCHK(s, hipStreamSynchronize(s->stream));
+        s->graphs.clear();
+    }
+    return SIM_OK;
+}
+
 int sim_profile(sim_t* s, int32_t on) {
     if (!s) return SIM_EINVAL;
     s->prof = on != 0;
@@ -970,6 +1089,8 @@ struct sim_batch_s {
         std::vector<KArgs> h_args;
     };
     std::vector<Group> groups;
+    bool use_graph = true;
+    GraphCache graphs;
     std::string err;
 };
 
@@ -1140,6 +1261,10 @@ int sim_batch_step(sim_batch_t* b, int32_t n_substeps) {
             return bfail(b, SIM_ESTATE, "sensors of a batch must be stepped together");
     }
     const long long N = (long long)npass_max.size();
+    for (auto& g : b->groups)
+        for (int k : g.members)
+            if (b->sims[k]->tile_idx != g.tile_idx)
+                return bfail(b, SIM_ESTATE, "sensor " + std::to_string(k) + ": tile shape changed after batch creation");
     std::vector<LaunchSet> sets;
     for (auto& g : b->groups) {
         LaunchSet L;
@@ -1158,12 +1283,26 @@ int sim_batch_step(sim_batch_t* b, int32_t n_substeps) {
     }
     int cur = s0->cur, sbin = s0->sbin;
     long long g = s0->gstep;
-    for (long long j = 0; j < N; ++j) {
-        for (auto& L : sets)
-            launch_step(L, (int)j, npass_max[j], cur, sbin, (int)(g & 1), j == N - 1 ? 1 : 0, nullptr, nullptr);
-        sbin = cur;
-        cur ^= 1;
-        g += 1;
+    auto emit = [&](hipStream_t st) {
+        int c = cur, sb = sbin;
+        long long gg = g;
+        for (long long j = 0; j < N; ++j) {
+            for (auto L : sets) {
+                L.st = st;
+                launch_step(L, (int)j, npass_max[j], c, sb, (int)(gg & 1), j == N - 1 ? 1 : 0, nullptr, nullptr);
+            }
+            sb = c;
+            c ^= 1;
+            gg += 1;
+        }
+    };
+    if (b->use_graph) {
+        std::vector<long long> key = {N, cur, sbin, g & 1};
+        key.insert(key.end(), npass_max.begin(), npass_max.end());
+        const hipError_t e = graph_run(b->graphs, key, b->stream, emit);
+        if (e != hipSuccess) return bfail(b, SIM_EHIP, std::string("batch step graph: ") + hipGetErrorString(e));
+    } else {
+        emit(b->stream);
     }
     BHIPCHK(b, hipGetLastError());
     for (sim_t* s : b->sims) finish_call(s, n_substeps, N);
@@ -1194,6 +1333,16 @@ int sim_batch_displacements(sim_batch_t* b, float* out, int32_t W, int32_t H, in
     for (int i = 0; i < (int)b->sims.size(); ++i) {
         const int rc = sim_surface_displacement(b->sims[i], out + (size_t)i * W * H * 3, W, H, out_on_device);
         if (rc) return bfail(b, rc, "sensor " + std::to_string(i) + ": " + b->sims[i]->err);
+    }
+    return SIM_OK;
+}
+
+int sim_batch_set_graph(sim_batch_t* b, int32_t on) {
+    if (!b) return SIM_EINVAL;
+    b->use_graph = on != 0;
+    if (!b->use_graph) {
+        BHIPCHK(b, hipStreamSynchronize(b->stream));
+        b->graphs.clear();
     }
     return SIM_OK;
 }

@@ -36,7 +36,8 @@ class sim_params(C.Structure):
         ("fixed_z_fraction", C.c_double), ("shape", C.c_int32), ("_pad0", C.c_int32),
         ("radius", C.c_double), ("half_length", C.c_double), ("half_extent", C.c_double * 3),
         ("fillet", C.c_double), ("pose0", C.c_double * 7), ("stress_each_pass", C.c_int32),
-        ("_pad1", C.c_int32),
+        ("_pad1", C.c_int32), ("hf_n", C.c_int32), ("_pad2", C.c_int32), ("hf_half", C.c_double),
+        ("hf", C.POINTER(C.c_double)),
     ]
 
 
@@ -57,7 +58,7 @@ EXPORTS = ("sim_params_default", "sim_create", "sim_destroy", "sim_set_indenter_
            "sim_batch_create", "sim_batch_destroy", "sim_batch_size", "sim_batch_get",
            "sim_batch_set_indenter_poses", "sim_batch_step", "sim_batch_synchronize",
            "sim_batch_heightmaps", "sim_batch_displacements", "sim_batch_last_error",
-           "sim_autotune_tile")
+           "sim_autotune_tile", "sim_set_graph", "sim_batch_set_graph")
 
 _lib = None
 
@@ -93,6 +94,8 @@ def lib():
     L.sim_set_tile.argtypes = [vp, i32, i32, i32]
     L.sim_set_tile_threads.argtypes = [vp, i32, i32, i32, i32]
     L.sim_profile.argtypes = [vp, i32]
+    L.sim_set_graph.argtypes = [vp, i32]
+    L.sim_batch_set_graph.argtypes = [vp, i32]
     L.sim_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     L.sim_last_error.argtypes = [vp]
     L.sim_last_error.restype = C.c_char_p
@@ -135,6 +138,11 @@ def to_params(p) -> sim_params:
     q.fillet = p.fillet
     q.pose0[:] = list(p.pose0)
     q.stress_each_pass = p.stress_each_pass
+    if getattr(p, "hf", None) is not None:
+        t = np.ascontiguousarray(p.hf, np.float64)
+        q.hf_n, q.hf_half = t.shape[0], p.hf_half
+        q.hf = t.ctypes.data_as(C.POINTER(C.c_double))
+        q._keep = t                      # the library copies the table at creation
     return q
 
 
@@ -246,6 +254,9 @@ class Sim:
         a = np.ascontiguousarray(passes, np.int32)
         self._chk(lib().sim_debug_force_passes(self.h, _p(a), a.size))
 
+    def sim_set_graph(self, on=True):
+        self._chk(lib().sim_set_graph(self.h, int(on)))
+
     def sim_profile(self, on=True):
         self._chk(lib().sim_profile(self.h, int(on)))
 
@@ -296,7 +307,8 @@ class Batch:
 
     def __init__(self, params_list, tiles=None, stream=None):
         n = len(params_list)
-        arr = (sim_params * n)(*[to_params(p) for p in params_list])
+        recs = [to_params(p) for p in params_list]     # hold the height-field tables
+        arr = (sim_params * n)(*recs)
         self._arr = arr
         t = None
         if tiles is not None:
@@ -333,6 +345,9 @@ class Batch:
     def sim_batch_set_indenter_poses(self, pos, quat):
         self._chk(lib().sim_batch_set_indenter_poses(self.h, _p(np.ascontiguousarray(pos, np.float64)),
                                                      _p(np.ascontiguousarray(quat, np.float64))))
+
+    def sim_batch_set_graph(self, on=True):
+        self._chk(lib().sim_batch_set_graph(self.h, int(on)))
 
     def sim_batch_step(self, n):
         self._chk(lib().sim_batch_step(self.h, int(n)))

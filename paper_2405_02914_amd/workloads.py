@@ -16,7 +16,7 @@ import math
 
 import numpy as np
 
-SHAPE_NONE, SHAPE_SPHERE, SHAPE_CAPSULE, SHAPE_BOX = 0, 1, 2, 3
+SHAPE_NONE, SHAPE_SPHERE, SHAPE_CAPSULE, SHAPE_BOX, SHAPE_HEIGHTFIELD = 0, 1, 2, 3, 4
 MODE_IMPM, MODE_PLAIN = 0, 1
 
 
@@ -47,6 +47,9 @@ class SensorParams:
     fillet: float = 0.0
     pose0: tuple = (8.0e-3, 8.0e-3, 8.0e-3, 1.0, 0.0, 0.0, 0.0)
     stress_each_pass: int = 0         # 1: every IMPM pass re-adds the elastic impulse
+    # height-field indenter: (n, n) body-frame heights over [-hf_half, hf_half]^2
+    hf: object = dataclasses.field(default=None, compare=False, repr=False)
+    hf_half: float = 0.0
 
     @property
     def n_particles(self) -> int:
@@ -73,6 +76,46 @@ class SensorParams:
 def padding_for(dx: float) -> int:
     """Lateral and top padding in cells: at least 4 cells and at least 2 mm."""
     return max(4, int(math.ceil(2.0e-3 / dx - 1e-9)))
+
+
+def perlin2(x, y, seed: int):
+    """Perlin's gradient noise in 2-D (improved fade 6t^5 - 15t^4 + 10t^3, eight
+    gradient directions picked by a seeded permutation hash); values in about
+    [-1, 1], zero at integer lattice points."""
+    perm = np.random.default_rng(seed).permutation(256)
+    perm = np.concatenate([perm, perm])
+    xi, yi = np.floor(x).astype(np.int64), np.floor(y).astype(np.int64)
+    fx, fy = x - xi, y - yi
+    xi &= 255
+    yi &= 255
+    g = np.array([(1, 1), (-1, 1), (1, -1), (-1, -1), (1, 0), (-1, 0), (0, 1), (0, -1)], np.float64)
+
+    def corner(dx, dy):
+        h = perm[perm[xi + dx] + yi + dy] & 7
+        return g[h, 0] * (fx - dx) + g[h, 1] * (fy - dy)
+
+    def fade(t):
+        return t * t * t * (t * (t * 6.0 - 15.0) + 10.0)
+
+    u, v = fade(fx), fade(fy)
+    a = corner(0, 0) + u * (corner(1, 0) - corner(0, 0))
+    b = corner(0, 1) + u * (corner(1, 1) - corner(0, 1))
+    return a + v * (b - a)
+
+
+def heightfield_table(seed: int, footprint: float, amplitude: float, wavelength: float,
+                      bowl_radius: float, n: int = 65):
+    """Lower surface of a textured indenter: amplitude * perlin(x / wavelength,
+    y / wavelength) + r^2 / (2 bowl_radius) sampled on an n x n lattice over
+    [-footprint, footprint]^2 (row j = y), shifted so that its lowest sample
+    inside the disc r <= footprint is at height 0."""
+    t = np.linspace(-footprint, footprint, n)
+    X, Y = np.meshgrid(t, t, indexing="xy")
+    off = np.random.default_rng(seed + 1).uniform(0.0, 64.0, size=2)
+    z = amplitude * perlin2(X / wavelength + off[0], Y / wavelength + off[1], seed) \
+        + (X * X + Y * Y) / (2.0 * bowl_radius)
+    disc = X * X + Y * Y <= footprint * footprint
+    return z - z[disc].min()
 
 
 def quat_about_z(deg: float) -> tuple:
@@ -218,7 +261,9 @@ def config3(n_sensors: int = 64, seed: int = 3, k_range=(4, 12), dx: float = 0.5
             n_substeps: int = 500, subcycle: int = 2):
     """Batch of independent sensors: cells (8k, 8k, 2k) with k ~ U{k_range}, 8
     particles per cell; indenter ~ U{sphere r 2-6 mm, capsule r 2-4 mm with
-    half-length 1-4 mm, rounded box half-sides 1.5-4 mm}; press depth
+    half-length 1-4 mm, rounded box half-sides 1.5-4 mm, Perlin height field
+    with amplitude 0.2-0.5 mm, wavelength 1.5-4 mm, footprint radius 3-6 mm and
+    bowl radius 5-15 mm}; press depth
     U[0.3, 1.5] mm over the first quarter of the substeps, then slip U[0, 3] mm in
     a direction U[0, 2 pi) and rotation U[-45, 45] degrees.  Returns the list of
     SensorParams and the list of schedules."""
@@ -229,7 +274,7 @@ def config3(n_sensors: int = 64, seed: int = 3, k_range=(4, 12), dx: float = 0.5
         k = int(rng.integers(k_range[0], k_range[1] + 1))
         cells = (8 * k, 8 * k, 2 * k)
         L, H = 8 * k * dx, 2 * k * dx
-        kind = int(rng.integers(0, 3))
+        kind = int(rng.integers(0, 4))
         if kind == 0:
             r = float(rng.uniform(2e-3, 6e-3))
             shape = dict(shape=SHAPE_SPHERE, radius=r)
@@ -238,10 +283,16 @@ def config3(n_sensors: int = 64, seed: int = 3, k_range=(4, 12), dx: float = 0.5
             r = float(rng.uniform(2e-3, 4e-3))
             shape = dict(shape=SHAPE_CAPSULE, radius=r, half_length=float(rng.uniform(1e-3, 4e-3)))
             drop = r
-        else:
+        elif kind == 2:
             hx, hy = float(rng.uniform(1.5e-3, 4e-3)), float(rng.uniform(1.5e-3, 4e-3))
             shape = dict(shape=SHAPE_BOX, half_extent=(hx, hy, 2e-3), fillet=0.5e-3)
             drop = 2e-3
+        else:
+            foot = float(rng.uniform(3e-3, 6e-3))
+            tab = heightfield_table(int(rng.integers(0, 2**31)), foot, float(rng.uniform(0.2e-3, 0.5e-3)),
+                                    float(rng.uniform(1.5e-3, 4e-3)), float(rng.uniform(5e-3, 15e-3)))
+            shape = dict(shape=SHAPE_HEIGHTFIELD, hf=tab, hf_half=foot)
+            drop = 0.0
         p = SensorParams(cells=cells, dx=dx, pad_lateral=pad, pad_top=pad, seed=1000 + i,
                          subcycle=subcycle, pose0=(L / 2, L / 2, H + drop, 1.0, 0.0, 0.0, 0.0),
                          **shape)

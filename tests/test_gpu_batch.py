@@ -74,6 +74,47 @@ def test_batch_member_matches_oracle(gpu, oracle_lib):
     b.close()
 
 
+def _state_equal(a, b):
+    return all(np.array_equal(u, w) for u, w in zip(a.sim_read_particles(), b.sim_read_particles()))
+
+
+def test_graph_replay_equals_eager(gpu):
+    """Graph replays (batch and single sensor) against the eager launches, checked
+    after every call, with host reads and height maps between replays; the
+    sequences repeat, so most calls replay an already captured graph."""
+    params, scheds = small_batch(n=3, n_substeps=60)
+    bg = gpu.Batch(params)                  # graph replay (the default)
+    be = gpu.Batch(params)
+    be.sim_batch_set_graph(False)
+    sg, se = gpu.Sim(params[0]), gpu.Sim(params[0])
+    sg.sim_set_graph(True)
+    # the schedules cut at the press/slip change and every 50 substeps; advance
+    # them in chunks of 5 substeps so the same graph is replayed many times
+    for k in range(len(scheds[0])):
+        n, _, _ = scheds[0][k]
+        pos = np.array([s[k][1] for s in scheds])
+        quat = np.array([s[k][2] for s in scheds])
+        for b in (bg, be):
+            b.sim_batch_set_indenter_poses(pos, quat)
+        for s in (sg, se):
+            s.sim_set_indenter_pose(pos[0], quat[0])
+        done = 0
+        while done < n:
+            m = min(5, n - done)
+            for b in (bg, be):
+                b.sim_batch_step(m)
+            for s in (sg, se):
+                s.sim_step(m)
+            done += m
+            for i in range(len(params)):
+                assert _state_equal(bg.sensors[i], be.sensors[i]), (k, done, i)
+            assert _state_equal(sg, se), (k, done)
+            assert np.array_equal(sg.sim_surface_heightmap(16, 16), se.sim_surface_heightmap(16, 16))
+    assert sg.sim_get_stats()["passes"] == se.sim_get_stats()["passes"]
+    for x in (bg, be, sg, se):
+        x.close()
+
+
 def test_batch_rejects_mismatched_steps(gpu):
     params, _ = small_batch(n=2)
     with pytest.raises(gpu.SimError):

@@ -188,6 +188,37 @@ def test_slip_and_rotation_with_oracle_pass_schedule(gpu, ref):
     assert np.abs(x2 - xo).max() <= 1e-2 * p.dx
 
 
+def test_heightfield_indenter_matches_oracle(gpu, ref):
+    """A textured (Perlin height-field) indenter pressed, slipped and rotated:
+    same calibration points and, on the oracle's pass schedule, the same
+    particle positions."""
+    p = W.small_sensor(cells=(16, 16, 6), subcycle=2)
+    L = 16 * p.dx
+    tab = W.heightfield_table(11, 2.5e-3, 0.4e-3, 1.5e-3, 8e-3)
+    p = p.replace(shape=W.SHAPE_HEIGHTFIELD, hf=tab, hf_half=2.5e-3,
+                  pose0=(L / 2, L / 2, p.height, 1.0, 0.0, 0.0, 0.0))
+    c = np.array(p.pose0[:3])
+    segs = [(20, tuple(c + [0, 0, -0.4e-3]), (1, 0, 0, 0)),
+            (30, tuple(c + [0.3e-3, 0.2e-3, -0.4e-3]), W.quat_about_z(-25))]
+    o = ref.OracleSim(p)
+    o.enable_pass_log(10000)
+    g = gpu.Sim(p)
+    st = g.sim_get_stats()
+    assert st["calib_particle"] == o.calib_particle
+    assert np.allclose(st["xo"], o.xo(), rtol=0, atol=1e-15)
+    o.run_schedule(segs)
+    g.sim_debug_force_passes(o.pass_log())
+    g.run_schedule(segs)
+    xg = g.sim_read_particles()[0]
+    xo = o.state()[0]
+    err = np.abs(xg - xo).max()
+    X0 = o.rest()[0]
+    print(f"height field: max|dx| = {err / p.dx:.3e} dx, max displacement "
+          f"{np.abs(xo - X0).max() / p.dx:.2f} dx", flush=True)
+    assert np.abs(xo - X0).max() > 0.3 * p.dx
+    assert err <= 1e-3 * p.dx
+
+
 def test_rest_is_bitwise_preserved(gpu):
     p = W.small_sensor(cells=(12, 12, 4), shape=W.SHAPE_NONE, subcycle=2)
     g = gpu.Sim(p)

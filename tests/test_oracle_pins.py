@@ -414,6 +414,57 @@ def test_inside_mask_capsule_rotated(ref):
     assert np.array_equal(got[~near], want[~near])
 
 
+def _hf_sensor(tab, half, z_lift=0.0):
+    p = W.small_sensor(cells=(10, 10, 4))
+    L = 10 * p.dx
+    return p.replace(shape=W.SHAPE_HEIGHTFIELD, hf=tab, hf_half=half,
+                     pose0=(L / 2, L / 2, p.height + z_lift, 1.0, 0.0, 0.0, 0.0))
+
+
+def test_inside_mask_heightfield_plane_rotated(ref):
+    """A height field sampled from a plane is that plane under bilinear
+    interpolation: rotated 30 degrees about z, the nodes inside are those over
+    the footprint disc and above the tilted plane (body frame)."""
+    half, n = 2.1e-3, 9
+    a, b, c = 0.31, -0.17, -0.9e-3
+    t = np.linspace(-half, half, n)
+    X_, Y_ = np.meshgrid(t, t, indexing="xy")
+    p = _hf_sensor(a * X_ + b * Y_ + c, half)
+    s = ref.OracleSim(p)
+    q = W.quat_about_z(30)
+    s.set_target_pose(p.pose0[:3], q)
+    s.step(1)
+    th = np.radians(30)
+    Rz = np.array([[np.cos(th), -np.sin(th), 0], [np.sin(th), np.cos(th), 0], [0, 0, 1]])
+    d = brute.node_positions(p) - np.array(p.pose0[:3])
+    pb = d @ Rz                       # body coordinates: R^T d for each row
+    r2 = pb[:, 0] ** 2 + pb[:, 1] ** 2
+    phi = a * pb[:, 0] + b * pb[:, 1] + c - pb[:, 2]
+    want = (r2 <= half * half) & (phi <= 0)
+    near = (np.abs(phi) < 1e-12) | (np.abs(np.sqrt(r2) - half) < 1e-12)
+    got = s.inside_mask()
+    assert want.sum() > 50
+    assert np.array_equal(got[~near], want[~near])
+
+
+def test_heightfield_calibration_point(ref):
+    """x_o of a height field is its lowest sample inside the footprint disc: a
+    unique off-centre minimum is found, and for a flat table the tie goes to the
+    samples farthest from the axis, then the smallest x, then the smallest y."""
+    half, n = 2.0e-3, 9
+    t = np.linspace(-half, half, n)
+    X_, Y_ = np.meshgrid(t, t, indexing="xy")
+    tab = (X_ - t[5]) ** 2 + (Y_ - t[2]) ** 2 + 1e-4
+    tab[0, 0] = -1.0                  # outside the disc: ignored
+    p = _hf_sensor(tab, half)
+    s = ref.OracleSim(p)
+    assert np.allclose(s.xo(), np.array(p.pose0[:3]) + [t[5], t[2], 1e-4], atol=1e-15)
+    flat = np.full((n, n), 3e-4)
+    p = _hf_sensor(flat, half)
+    s = ref.OracleSim(p)
+    assert np.array_equal(s.xo(), np.array(p.pose0[:3]) + [-half, 0.0, 3e-4])
+
+
 def test_pose_reaches_target_and_xo_tracks(ref):
     p = W.small_sensor(cells=(6, 6, 3), radius=1.2e-3)
     s = ref.OracleSim(p)
