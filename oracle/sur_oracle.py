@@ -197,13 +197,13 @@ class SurrogateOracle:
         return theta - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
-def assemble_input(depth_m, pose6, prev_mm, bf16=True):
-    """Network input (N, H, W, 10): depth (m -> mm, clipped to [-3, 3]), the six
+def assemble_input(depth_mm, pose6, prev_mm, bf16=True):
+    """Network input (N, H, W, 10): depth (mm, clipped to [-3, 3]), the six
     pose-change values at every pixel, the previous displacement (mm)."""
-    depth_m = np.asarray(depth_m, np.float64)
-    N, H, W = depth_m.shape
+    depth_mm = np.asarray(depth_mm, np.float64)
+    N, H, W = depth_mm.shape
     X = np.empty((N, H, W, 10))
-    X[..., 0] = np.clip(depth_m * 1000.0, -3.0, 3.0)
+    X[..., 0] = np.clip(depth_mm, -3.0, 3.0)
     X[..., 1:7] = np.asarray(pose6, np.float64)[:, None, None, :]
     X[..., 7:10] = prev_mm
     return bf16_round(X) if bf16 else X

@@ -303,3 +303,37 @@ def config3(n_sensors: int = 64, seed: int = 3, k_range=(4, 12), dx: float = 0.5
         params.append(p)
         scheds.append(_schedule(p.pose0, n_substeps, press, slip, ang, rot))
     return params, scheds
+
+
+# ---------------------------------------------------------------- surrogate inputs
+
+def surrogate_layer_shapes(channels=(32, 64, 128, 256), in_ch=10):
+    """(cin, cout) of the 14 convolutions of the surrogate in parameter order."""
+    c0, c1, c2, c3 = channels
+    return [(in_ch, c0), (c0, c0), (c0, c1), (c1, c1), (c1, c2), (c2, c2), (c2, c3), (c3, c3),
+            (c3, c2), (c2, c2), (c2, c1), (c1, c1), (c1, c0), (c0, c0)]
+
+
+def surrogate_weights(channels=(32, 64, 128, 256), seed=0, head_scale=0.05, bias_scale=0.05):
+    """Seeded flat parameter vector in the surrogate's layout: He-normal
+    convolution weights W[Cout][3][3][Cin], small random biases, a small head."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for ci, co in surrogate_layer_shapes(channels):
+        parts.append(rng.normal(0.0, math.sqrt(2.0 / (9 * ci)), co * 9 * ci))
+        parts.append(rng.normal(0.0, bias_scale, co))
+    parts.append(rng.normal(0.0, head_scale, 3 * channels[0]))
+    parts.append(rng.normal(0.0, bias_scale, 3))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def surrogate_batch(n, H, W, seed=0):
+    """Seeded synthetic surrogate inputs (float32): depth (mm) ~ U[-4, 4], pose
+    change ~ N(0, 0.2), previous displacement ~ N(0, 0.3) mm and a target that
+    differs from it by ~ N(0, 0.05) mm."""
+    rng = np.random.default_rng(seed)
+    depth = rng.uniform(-4.0, 4.0, (n, H, W)).astype(np.float32)
+    pose = rng.normal(0.0, 0.2, (n, 6)).astype(np.float32)
+    prev = rng.normal(0.0, 0.3, (n, H, W, 3)).astype(np.float32)
+    tgt = (prev + rng.normal(0.0, 0.05, (n, H, W, 3))).astype(np.float32)
+    return depth, pose, prev, tgt

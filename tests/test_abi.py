@@ -1,5 +1,5 @@
-"""The C ABI library loads and exports every entry point include/impm.h
-declares (no device calls: runs without a GPU)."""
+"""The C ABI library loads and exports every entry point include/impm.h and
+include/sur.h declare (no device calls: runs without a GPU)."""
 import ctypes
 import os
 import re
@@ -8,12 +8,13 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "impm.h")
+SUR_HEADER = os.path.join(ROOT, "include", "sur.h")
 
 
-def declared_functions():
-    text = open(HEADER).read()
+def declared_functions(header=HEADER, prefix="sim"):
+    text = open(header).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(sim_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(" + prefix + r"_[a-z_]+)\s*\(", text)))
 
 
 def test_header_declares_the_boundary():
@@ -30,6 +31,18 @@ def test_library_exports_every_declared_symbol():
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
     assert set(declared_functions()) <= set(impm.EXPORTS)
+
+
+def test_library_exports_every_surrogate_symbol():
+    from paper_2405_02914_amd import impm, sur
+    lib = ctypes.CDLL(impm.LIB_PATH)
+    names = declared_functions(SUR_HEADER, "sur")
+    for n in ("sur_create", "sur_infer", "sur_train_step", "sur_save", "sur_load", "sur_destroy"):
+        assert n in names
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(names) <= set(sur.EXPORTS)
+    assert ctypes.sizeof(sur.sur_params) == 4 * 8 + 8 + 4 * 4
 
 
 def test_binding_struct_layouts_match_header():

@@ -159,7 +159,7 @@ def test_bf16_network_rounds_activations():
 
 
 def test_assemble_input_channels():
-    depth = np.array([[[0.5e-3, -4e-3], [4e-3, 0.0]]])
+    depth = np.array([[[0.5, -4.0], [4.0, 0.0]]])
     pose = np.array([[0.1, -0.2, 0.0, 0.01, 0.0, -0.03]])
     prev = np.arange(12, dtype=np.float64).reshape(1, 2, 2, 3) * 0.01
     X = S.assemble_input(depth, pose, prev, bf16=False)
