@@ -144,6 +144,14 @@ int sim_surface_heightmap(sim_t* s, float* out, int32_t W, int32_t H, int32_t ou
 /* The same interpolation of the full displacement x - X_rest: H*W*3 floats. */
 int sim_surface_displacement(sim_t* s, float* out, int32_t W, int32_t H, int32_t out_on_device);
 
+/* Depth of the indenter below the slab's top face along the vertical line
+ * through each pixel centre (as for the height map): (H - z_low) * scale, where
+ * z_low is the indenter's lowest point on that line at the current pose (the
+ * object's "depth data" of Sec. IV-B, the surrogate's main input); -1e9 where
+ * the line misses the indenter.  Needs a pose rotated about z only (else
+ * SIM_EINVAL).  out: W*H floats, host or device memory. */
+int sim_indenter_depthmap(sim_t* s, float* out, int32_t W, int32_t H, double scale, int32_t out_on_device);
+
 int sim_get_stats(sim_t* s, sim_stats* out);
 int sim_num_particles(const sim_t* s, int64_t* n);
 int sim_grid_dims(const sim_t* s, int32_t nodes[3]);
@@ -213,6 +221,8 @@ int sim_batch_synchronize(sim_batch_t* b);
 /* out: n x H x W (heightmaps) or n x H x W x 3 (displacements), host or device. */
 int sim_batch_heightmaps(sim_batch_t* b, float* out, int32_t W, int32_t H, int32_t out_on_device);
 int sim_batch_displacements(sim_batch_t* b, float* out, int32_t W, int32_t H, int32_t out_on_device);
+/* n x H x W indenter depth maps (sim_indenter_depthmap of every sensor). */
+int sim_batch_depthmaps(sim_batch_t* b, float* out, int32_t W, int32_t H, double scale, int32_t out_on_device);
 const char* sim_batch_last_error(const sim_batch_t* b);
 
 /* Time `steps` executed steps of a sensor with these parameters for every

@@ -832,3 +832,60 @@ void orc_surface_heightmap(const orc_sim *s, double *out, int W, int H) {
     for (size_t q = 0; q < (size_t)W * H; ++q) out[q] = top + d[3 * q + 2];
     free(d);
 }
+
+/* ---------------------------------------------------------------- indenter depth map */
+
+/* Signed inside measure (<= 0 inside) of the indenter at its current pose for
+ * n world points X (n x 3): the test that node_inside applies to grid nodes. */
+void orc_point_phi(const orc_sim *s, const double *X, int64_t n, double *phi) {
+    double R[9];
+    quat_to_matrix(s->quat, R);
+    for (int64_t q = 0; q < n; ++q) {
+        double d[3] = {X[3 * q] - s->pos[0], X[3 * q + 1] - s->pos[1], X[3 * q + 2] - s->pos[2]};
+        double p[3];
+        for (int a = 0; a < 3; ++a) p[a] = R[a] * d[0] + R[3 + a] * d[1] + R[6 + a] * d[2];
+        phi[q] = s->P.shape == 0 ? 1.0 : body_phi(&s->P, p);
+    }
+}
+
+/* Depth of the indenter below the slab's top face along the vertical line
+ * through each pixel centre ((u+1/2) Lx/W, (v+1/2) Ly/H), times `scale`:
+ * (top - z_low) scale, with z_low the lowest point of the indenter on that
+ * line; -1e9 where the line misses it.  The indenter may only be rotated
+ * about z (then its body z axis is vertical); returns -1 otherwise. */
+int orc_indenter_depthmap(const orc_sim *s, int W, int H, double scale, double *out) {
+    const double *q = s->quat;
+    if (fabs(q[1]) > 1e-9 || fabs(q[2]) > 1e-9) return -1;
+    double R[9];
+    quat_to_matrix(q, R);
+    const orc_params *P = &s->P;
+    double Lx = (double)P->cells[0] * P->dx, Ly = (double)P->cells[1] * P->dx;
+    double top = (double)P->cells[2] * P->dx;
+    for (int v = 0; v < H; ++v)
+        for (int u = 0; u < W; ++u) {
+            double dx = ((double)u + 0.5) * Lx / (double)W - s->pos[0];
+            double dy = ((double)v + 0.5) * Ly / (double)H - s->pos[1];
+            double px = R[0] * dx + R[3] * dy, py = R[1] * dx + R[4] * dy;
+            int hit = 0;
+            double zb = 0.0;
+            if (P->shape == 1) {
+                double r2 = px * px + py * py;
+                if (r2 <= P->radius * P->radius) { hit = 1; zb = -sqrt(P->radius * P->radius - r2); }
+            } else if (P->shape == 2) {
+                double h = P->half_length;
+                double t = px < -h ? -h : (px > h ? h : px);
+                double d2 = (px - t) * (px - t) + py * py;
+                if (d2 <= P->radius * P->radius) { hit = 1; zb = -sqrt(P->radius * P->radius - d2); }
+            } else if (P->shape == 3) {
+                double f = P->fillet;
+                double qx = fabs(px) - (P->half_extent[0] - f), qy = fabs(py) - (P->half_extent[1] - f);
+                double ox = qx > 0.0 ? qx : 0.0, oy = qy > 0.0 ? qy : 0.0;
+                double o2 = ox * ox + oy * oy;
+                if (o2 <= f * f) { hit = 1; zb = -(P->half_extent[2] - f) - sqrt(f * f - o2); }
+            } else if (P->shape == 4) {
+                if (px * px + py * py <= P->hf_half * P->hf_half) { hit = 1; zb = hf_height(P, px, py); }
+            }
+            out[(size_t)v * W + u] = hit ? (top - (s->pos[2] + zb)) * scale : -1e9;
+        }
+    return 0;
+}

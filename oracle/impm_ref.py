@@ -87,6 +87,9 @@ def lib():
         L.orc_phase_g2p.argtypes = [P, C.c_int]
         L.orc_phase_commit.argtypes = [P, C.c_double]
         L.orc_inside_mask.argtypes = [P, u8]
+        L.orc_point_phi.argtypes = [P, dp, C.c_int64, dp]
+        L.orc_indenter_depthmap.argtypes = [P, C.c_int, C.c_int, C.c_double, dp]
+        L.orc_indenter_depthmap.restype = C.c_int
         L.orc_energy.restype = C.c_double
         L.orc_energy.argtypes = [P]
         L.orc_surface_displacement.argtypes = [P, dp, C.c_int, C.c_int]
@@ -224,6 +227,16 @@ class OracleSim:
 
     def commit(self, h=None):
         lib().orc_phase_commit(self.h, self.params.dt if h is None else h)
+
+    def point_phi(self, X):
+        X = np.ascontiguousarray(X, np.float64).reshape(-1, 3)
+        out = np.zeros(len(X)); lib().orc_point_phi(self.h, X, len(X), out); return out
+
+    def indenter_depthmap(self, W, H, scale=1.0):
+        out = np.zeros((H, W))
+        if lib().orc_indenter_depthmap(self.h, W, H, scale, out) != 0:
+            raise ValueError("the depth map needs an indenter rotated about z only")
+        return out
 
     def inside_mask(self):
         m = np.zeros(self.n_nodes, np.uint8); lib().orc_inside_mask(self.h, m); return m.astype(bool)

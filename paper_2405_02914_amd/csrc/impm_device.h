@@ -89,6 +89,14 @@ struct SurfArgs {
     unsigned long long* acc;     // H*W x 4 fixed-point sums (w, w ux, w uy, w uz), u in cells
 };
 
+// Indenter depth map: pixel grid over the slab and the indenter's current pose
+// (rotation about z only, so the body z axis is vertical).
+struct DepthArgs {
+    int W, H;
+    double Lx, Ly, top, scale;
+    double c[3], R[9];        // centre and body->world rotation (row-major)
+};
+
 // One launch processes the tiles (or node blocks) of one or several sensors:
 // args[s] is sensor s's record in device memory; tile_base and node_base are
 // prefix sums of the sensors' tile counts and node-block counts (null for a

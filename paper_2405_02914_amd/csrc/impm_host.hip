@@ -20,6 +20,7 @@ __global__ void k_fill(float* p, long long n, float val);
 __global__ void k_scan(BatchMap m, int next, int limit_slots);
 __global__ void k_scatter(BatchMap m, int cur);
 __global__ void k_surface_accum(KArgs a, SurfArgs s);
+__global__ void k_depthmap(KArgs a, DepthArgs g, float* out);
 __global__ void k_surface_finish(const unsigned long long* acc, int npix, float top, float dx, int mode,
                                  float* out);
 }  // namespace impm
@@ -872,6 +873,39 @@ static int surface_raster(sim_t* s, float* out, int W, int H, int on_device, int
     return SIM_OK;
 }
 
+int sim_indenter_depthmap(sim_t* s, float* out, int32_t W, int32_t H, double scale, int32_t out_on_device) {
+    if (!s || !out || W < 1 || H < 1 || (long long)W * H > (1LL << 30) || !std::isfinite(scale))
+        return fail(s, SIM_EINVAL, "bad depth map arguments");
+    if (std::fabs(s->quat[1]) > 1e-9 || std::fabs(s->quat[2]) > 1e-9)
+        return fail(s, SIM_EINVAL, "the depth map needs an indenter rotated about z only");
+    const long long npix = (long long)W * H;
+    float* dst = out;
+    if (!out_on_device) {
+        if (npix > s->out_cap) {
+            if (s->out_tmp) (void)hipFree(s->out_tmp);
+            s->out_tmp = nullptr;
+            HIPCHK(s, hipMalloc(&s->out_tmp, npix * sizeof(float)));
+            s->out_cap = npix;
+        }
+        dst = s->out_tmp;
+    }
+    DepthArgs g;
+    g.W = W; g.H = H;
+    g.Lx = (double)s->P.cells[0] * s->P.dx;
+    g.Ly = (double)s->P.cells[1] * s->P.dx;
+    g.top = (double)s->P.cells[2] * s->P.dx;
+    g.scale = scale;
+    std::memcpy(g.c, s->pos, sizeof(g.c));
+    quat_matrix(s->quat, g.R);
+    hipLaunchKernelGGL(k_depthmap, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, s->stream, kargs(s), g, dst);
+    HIPCHK(s, hipGetLastError());
+    if (!out_on_device) {
+        HIPCHK(s, hipMemcpyAsync(out, dst, npix * sizeof(float), hipMemcpyDeviceToHost, s->stream));
+        HIPCHK(s, hipStreamSynchronize(s->stream));
+    }
+    return SIM_OK;
+}
+
 int sim_surface_heightmap(sim_t* s, float* out, int32_t W, int32_t H, int32_t out_on_device) {
     return surface_raster(s, out, W, H, out_on_device, 0);
 }
@@ -1323,6 +1357,15 @@ int sim_batch_heightmaps(sim_batch_t* b, float* out, int32_t W, int32_t H, int32
     if (!b || !out || W < 1 || H < 1) return bfail(b, SIM_EINVAL, "bad raster arguments");
     for (int i = 0; i < (int)b->sims.size(); ++i) {
         const int rc = sim_surface_heightmap(b->sims[i], out + (size_t)i * W * H, W, H, out_on_device);
+        if (rc) return bfail(b, rc, "sensor " + std::to_string(i) + ": " + b->sims[i]->err);
+    }
+    return SIM_OK;
+}
+
+int sim_batch_depthmaps(sim_batch_t* b, float* out, int32_t W, int32_t H, double scale, int32_t out_on_device) {
+    if (!b || !out || W < 1 || H < 1) return bfail(b, SIM_EINVAL, "bad depth map arguments");
+    for (int i = 0; i < (int)b->sims.size(); ++i) {
+        const int rc = sim_indenter_depthmap(b->sims[i], out + (size_t)i * W * H, W, H, scale, out_on_device);
         if (rc) return bfail(b, rc, "sensor " + std::to_string(i) + ": " + b->sims[i]->err);
     }
     return SIM_OK;

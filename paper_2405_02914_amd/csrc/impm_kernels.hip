@@ -683,6 +683,52 @@ __global__ void k_surface_accum(KArgs a, SurfArgs s) {
     }
 }
 
+// Depth of the indenter below the slab's top face along each pixel's vertical
+// line: (top - z_low) * scale with z_low its lowest point on the line, -1e9
+// where the line misses it.  FP64, evaluated as the body-frame formulas of the
+// four shapes (the lower half of the sphere and capsule, the rounded box's
+// bottom face with its fillet, the height field's bilinear surface).
+__global__ __launch_bounds__(256) void k_depthmap(KArgs a, DepthArgs g, float* __restrict__ out) {
+#pragma clang fp contract(off)
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= g.W * g.H) return;
+    const int u = q % g.W, v = q / g.W;
+    const double dx = ((double)u + 0.5) * g.Lx / (double)g.W - g.c[0];
+    const double dy = ((double)v + 0.5) * g.Ly / (double)g.H - g.c[1];
+    const double px = g.R[0] * dx + g.R[3] * dy, py = g.R[1] * dx + g.R[4] * dy;
+    bool hit = false;
+    double zb = 0.0;
+    if (a.shape == 1) {
+        const double r2 = px * px + py * py;
+        if (r2 <= a.radius * a.radius) { hit = true; zb = -sqrt(a.radius * a.radius - r2); }
+    } else if (a.shape == 2) {
+        const double h = a.half_length;
+        const double t = px < -h ? -h : (px > h ? h : px);
+        const double d2 = (px - t) * (px - t) + py * py;
+        if (d2 <= a.radius * a.radius) { hit = true; zb = -sqrt(a.radius * a.radius - d2); }
+    } else if (a.shape == 3) {
+        const double f = a.fillet;
+        const double qx = fabs(px) - (a.he[0] - f), qy = fabs(py) - (a.he[1] - f);
+        const double ox = qx > 0.0 ? qx : 0.0, oy = qy > 0.0 ? qy : 0.0;
+        const double o2 = ox * ox + oy * oy;
+        if (o2 <= f * f) { hit = true; zb = -(a.he[2] - f) - sqrt(f * f - o2); }
+    } else if (a.shape == 4) {
+        if (px * px + py * py <= a.hf_half * a.hf_half) {
+            const int n = a.hf_n;
+            const double step = 2.0 * a.hf_half / (double)(n - 1);
+            const double fu0 = (px + a.hf_half) / step, fv0 = (py + a.hf_half) / step;
+            const int i0 = min(max((int)floor(fu0), 0), n - 2), j0 = min(max((int)floor(fv0), 0), n - 2);
+            const double fu = fu0 - (double)i0, fv = fv0 - (double)j0;
+            const double* t = a.hf + (size_t)j0 * n + i0;
+            const double z0 = (1.0 - fu) * t[0] + fu * t[1];
+            const double z1 = (1.0 - fu) * t[n] + fu * t[n + 1];
+            hit = true;
+            zb = (1.0 - fv) * z0 + fv * z1;
+        }
+    }
+    out[q] = hit ? (float)((g.top - (g.c[2] + zb)) * g.scale) : -1e9f;
+}
+
 __global__ void k_surface_finish(const unsigned long long* __restrict__ acc, int npix, float top,
                                  float dx, int mode, float* __restrict__ out) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;

@@ -58,7 +58,8 @@ EXPORTS = ("sim_params_default", "sim_create", "sim_destroy", "sim_set_indenter_
            "sim_batch_create", "sim_batch_destroy", "sim_batch_size", "sim_batch_get",
            "sim_batch_set_indenter_poses", "sim_batch_step", "sim_batch_synchronize",
            "sim_batch_heightmaps", "sim_batch_displacements", "sim_batch_last_error",
-           "sim_autotune_tile", "sim_set_graph", "sim_batch_set_graph")
+           "sim_autotune_tile", "sim_set_graph", "sim_batch_set_graph", "sim_indenter_depthmap",
+           "sim_batch_depthmaps")
 
 _lib = None
 
@@ -95,6 +96,8 @@ def lib():
     L.sim_set_tile_threads.argtypes = [vp, i32, i32, i32, i32]
     L.sim_profile.argtypes = [vp, i32]
     L.sim_set_graph.argtypes = [vp, i32]
+    L.sim_indenter_depthmap.argtypes = [vp, fp, i32, i32, C.c_double, i32]
+    L.sim_batch_depthmaps.argtypes = [vp, fp, i32, i32, C.c_double, i32]
     L.sim_batch_set_graph.argtypes = [vp, i32]
     L.sim_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     L.sim_last_error.argtypes = [vp]
@@ -198,6 +201,16 @@ class Sim:
 
     def sim_synchronize(self):
         self._chk(lib().sim_synchronize(self.h))
+
+    def sim_indenter_depthmap(self, W, H, scale=1.0, out=None):
+        """(H - z_low) * scale per pixel; host numpy (H, W) unless `out` is a
+        device tensor of H*W floats."""
+        if out is not None:
+            self._chk(lib().sim_indenter_depthmap(self.h, C.c_void_p(out.data_ptr()), W, H, float(scale), 1))
+            return out
+        o = np.zeros((H, W), np.float32)
+        self._chk(lib().sim_indenter_depthmap(self.h, _p(o), W, H, float(scale), 0))
+        return o
 
     def sim_surface_heightmap(self, W, H, out=None):
         """Host numpy (H, W) unless `out` is a device tensor of H*W floats."""
@@ -361,6 +374,14 @@ class Batch:
             return out
         o = np.zeros((self.n, H, W), np.float32)
         self._chk(lib().sim_batch_heightmaps(self.h, _p(o), W, H, 0))
+        return o
+
+    def sim_batch_depthmaps(self, W, H, scale=1.0, out=None):
+        if out is not None:
+            self._chk(lib().sim_batch_depthmaps(self.h, C.c_void_p(out.data_ptr()), W, H, float(scale), 1))
+            return out
+        o = np.zeros((self.n, H, W), np.float32)
+        self._chk(lib().sim_batch_depthmaps(self.h, _p(o), W, H, float(scale), 0))
         return o
 
     def sim_batch_displacements(self, W, H, out=None):

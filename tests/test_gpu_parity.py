@@ -281,3 +281,37 @@ def test_config2_full_size_first_substep(gpu, ref):
     g.sim_set_indenter_pose(tgt, q); g.sim_step(1)
     o.set_target_pose(tgt, q); o.step(1)
     compare_states(g, o, xo0, "config2 first substep", dx=p.dx)
+
+
+@pytest.mark.parametrize("shape", [W.SHAPE_SPHERE, W.SHAPE_CAPSULE, W.SHAPE_BOX, W.SHAPE_HEIGHTFIELD])
+def test_indenter_depthmap_matches_oracle(gpu, ref, shape):
+    """Depth maps (mm) of the four indenter shapes, rotated 35 degrees about z,
+    held just above the slab (no contact)."""
+    p = W.small_sensor(cells=(16, 16, 4))
+    L = 16 * p.dx
+    z = p.height + 0.3e-3
+    if shape == W.SHAPE_SPHERE:
+        p = p.replace(radius=2.5e-3, pose0=(L / 2, L / 2, z + 2.5e-3, 1, 0, 0, 0))
+    elif shape == W.SHAPE_CAPSULE:
+        p = p.replace(shape=shape, radius=1.2e-3, half_length=2.0e-3, pose0=(L / 2, L / 2, z + 1.2e-3, 1, 0, 0, 0))
+    elif shape == W.SHAPE_BOX:
+        p = p.replace(shape=shape, half_extent=(2.0e-3, 1.5e-3, 1.0e-3), fillet=0.4e-3,
+                      pose0=(L / 2, L / 2, z + 1.0e-3, 1, 0, 0, 0))
+    else:
+        tab = W.heightfield_table(3, 3.0e-3, 0.3e-3, 2.0e-3, 8e-3)
+        p = p.replace(shape=shape, hf=tab, hf_half=3.0e-3, pose0=(L / 2, L / 2, z, 1, 0, 0, 0))
+    g, o = both(gpu, ref, p)
+    q = W.quat_about_z(35)
+    g.sim_set_indenter_pose(p.pose0[:3], q)
+    o.set_target_pose(p.pose0[:3], q)
+    g.sim_step(1)
+    o.step(1)
+    dg = g.sim_indenter_depthmap(40, 36, scale=1000.0)
+    do = o.indenter_depthmap(40, 36, scale=1000.0)
+    hit = do > -1e8
+    assert 20 < hit.sum() < hit.size
+    assert np.array_equal(dg > -1e8, hit)
+    err = np.abs(dg[hit] - do[hit]).max()
+    print(f"[depth] shape {shape}: max |err| {err:.2e} mm", flush=True)
+    assert err <= 1e-5
+    assert (dg[~hit] == -1e9).all()

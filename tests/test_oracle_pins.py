@@ -643,3 +643,43 @@ def test_elastic_impulse_once_per_step_is_the_stable_reading(ref):
         except FloatingPointError:
             res[sep] = "invalid"
     assert res == {1: "invalid", 0: "ok"}, res
+
+
+@pytest.mark.parametrize("shape", [W.SHAPE_SPHERE, W.SHAPE_CAPSULE, W.SHAPE_BOX, W.SHAPE_HEIGHTFIELD])
+def test_indenter_depthmap_agrees_with_inside_test(ref, shape):
+    """The depth map's lowest point on each pixel's vertical line is the
+    indenter's boundary: 1e-9 m above it is inside, 1e-9 m below is outside;
+    a line that misses the indenter is outside at every height sampled."""
+    p = W.small_sensor(cells=(16, 16, 4))
+    L = 16 * p.dx
+    if shape == W.SHAPE_SPHERE:
+        p = p.replace(radius=2.5e-3, pose0=(L / 2, L / 2, p.height + 2.0e-3, 1, 0, 0, 0))
+    elif shape == W.SHAPE_CAPSULE:
+        p = p.replace(shape=shape, radius=1.2e-3, half_length=2.0e-3,
+                      pose0=(L / 2, L / 2, p.height + 1.0e-3, 1, 0, 0, 0))
+    elif shape == W.SHAPE_BOX:
+        p = p.replace(shape=shape, half_extent=(2.0e-3, 1.5e-3, 1.0e-3), fillet=0.4e-3,
+                      pose0=(L / 2, L / 2, p.height + 0.8e-3, 1, 0, 0, 0))
+    else:
+        tab = W.heightfield_table(3, 3.0e-3, 0.3e-3, 2.0e-3, 8e-3)
+        p = p.replace(shape=shape, hf=tab, hf_half=3.0e-3, pose0=(L / 2, L / 2, p.height - 0.2e-3, 1, 0, 0, 0))
+    s = ref.OracleSim(p)
+    s.set_target_pose(p.pose0[:3], W.quat_about_z(35))
+    s.step(1)                               # rotated 35 degrees about z
+    Wd, H = 24, 20
+    d = s.indenter_depthmap(Wd, H)
+    u, v = np.meshgrid((np.arange(Wd) + 0.5) * L / Wd, (np.arange(H) + 0.5) * L / H)
+    hit = d > -1e8
+    assert 10 < hit.sum() < hit.size
+    zl = p.height - d[hit]
+    up = np.stack([u[hit], v[hit], zl + 1e-9], -1)
+    dn = np.stack([u[hit], v[hit], zl - 1e-9], -1)
+    assert (s.point_phi(up) <= 0).all()
+    assert (s.point_phi(dn) > 0).all()
+    for z in np.linspace(-0.01, 0.02, 61):
+        miss = np.stack([u[~hit], v[~hit], np.full((~hit).sum(), z)], -1)
+        assert (s.point_phi(miss) > 0).all()
+    # a tilted indenter is rejected
+    t = ref.OracleSim(p.replace(pose0=tuple(p.pose0[:3]) + (np.cos(0.1), np.sin(0.1), 0.0, 0.0)))
+    with pytest.raises(ValueError):
+        t.indenter_depthmap(8, 8)
