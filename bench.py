@@ -16,6 +16,7 @@ particle-updates per second: particles x executed steps / wall time.
 
     python bench.py [--gpus 1] [--steps 2000] [--warmup 50]
     python bench.py --workload batch       # 64 batched sensors, 500 substeps
+    python bench.py --workload surrogate   # surrogate training and serving vs IMPM
     python bench.py --copy-calibration     # 1 GiB device copy for counter scaling
 
 The batch workload: 64 independent sensors of 32x32x8 to 96x96x24 cells (dx
@@ -60,7 +61,7 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=4, help="oracle executed steps timed")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--tile", default=None, help="tile cells tx,ty,tz[,threads] of the binned order")
-    ap.add_argument("--workload", choices=("sensor", "batch"), default="sensor")
+    ap.add_argument("--workload", choices=("sensor", "batch", "surrogate"), default="sensor")
     ap.add_argument("--graph", type=int, default=None, help="1/0: replay step sequences as HIP graphs")
     return ap.parse_args()
 
@@ -193,6 +194,73 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+PEAK_BF16_TFLOPS = 2500.0
+
+
+def surrogate_flops(H=128, W=128, channels=(32, 64, 128, 256), in_ch=10):
+    """Algorithmic FLOPs per sample of the surrogate: forward (every 3x3
+    convolution 2 * 9 * Cin * Cout per output pixel, the 1x1 head) and a
+    training step (forward, data gradient of convolutions 1-13, weight
+    gradient of all)."""
+    c0, c1, c2, c3 = channels
+    res = [(H, W), (H // 2, W // 2), (H // 4, W // 4), (H // 8, W // 8)]
+    layers = [(in_ch, c0, 0), (c0, c0, 0), (c0, c1, 1), (c1, c1, 1), (c1, c2, 2), (c2, c2, 2), (c2, c3, 3),
+              (c3, c3, 3), (c3, c2, 2), (c2, c2, 2), (c2, c1, 1), (c1, c1, 1), (c1, c0, 0), (c0, c0, 0)]
+    per = [2.0 * 9 * ci * co * res[l][0] * res[l][1] for ci, co, l in layers]
+    head = 2.0 * c0 * 3 * H * W
+    fwd = sum(per) + head
+    train = fwd + sum(per[1:]) + sum(per) + 2 * head
+    return fwd, train
+
+
+def bench_surrogate(args):
+    """Surrogate on IMPM data: a compact run of the whole pipeline (IMPM
+    trajectories from the batched simulator, Adam training with the BF16 MFMA
+    kernels, held-out RMS error, serving rate)."""
+    import torch
+    from paper_2405_02914_amd import sur, surrogate_train as T, workloads as W
+    torch.cuda.set_device(0)
+    st = torch.cuda.Stream()
+    n_train, n_test, steps, batch, serve = 96, 16, max(args.steps, 200), 64, 256
+    ptr, s_tr = W.surrogate_trajectories(n_train, seed=1)
+    pte, s_te = W.surrogate_trajectories(n_test, seed=2)
+    dtr = T.generate(ptr, s_tr, st, log=lambda *a, **k: print(*a, file=sys.stderr, **k))
+    dte = T.generate(pte, s_te, st, log=lambda *a, **k: print(*a, file=sys.stderr, **k))
+    net = sur.Surrogate(T.RES, T.RES, max_batch=serve, stream=st.cuda_stream)
+    T.train(net, dtr, args.warmup, batch, st, log=lambda *a, **k: None)          # warm-up steps
+    losses, secs = T.train(net, dtr, steps, batch, st, log=lambda *a, **k: print(*a, file=sys.stderr, **k))
+    ev = T.evaluate(net, dte, st)
+    fps, lat = T.inference_rate(net, dte, st, serve, reps=20)
+    fwd, trn = surrogate_flops()
+    step_ms = 1e3 * secs / steps
+    achieved = trn * batch / (step_ms * 1e-3) / 1e12
+    out = {
+        "metric": "surrogate vs IMPM frames/s",
+        "value": fps,
+        "unit": "frames/s",
+        "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": step_ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "U-shaped conv surrogate 32-64-128-256 on 128x128 maps, trained on IMPM "
+                               "trajectories of 32x32x8 mm sensors (64x64x16 cells, dx 0.5 mm) with random "
+                               "indenters; serving batch 256",
+                   "train_trajectories": dtr.T, "test_trajectories": dte.T, "train_batch": batch,
+                   "serve_batch": serve, "impm_frames_per_s": dtr.impm_frames_per_s,
+                   "speedup_vs_impm": fps / dtr.impm_frames_per_s,
+                   "rms_one_step_mm": ev["rms_one_step_mm"], "rms_rollout_mm": ev["rms_rollout_mm"],
+                   "rms_persistence_mm": ev["rms_persistence_mm"],
+                   "train_gflop_per_sample": trn / 1e9, "infer_gflop_per_sample": fwd / 1e9,
+                   "serve_batch_ms": 1e3 * lat},
+        "roofline": {"bound": "mfma", "kernel": "whole training step (all kernels, wall clock)",
+                     "achieved": round(achieved, 1), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "traffic": None,
+                     "inference_tflops": round(fwd * fps / 1e12, 1)},
+    }
+    net.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -204,6 +272,9 @@ def main():
         sys.exit(2)
     if args.workload == "batch":
         bench_batch(args)
+        return
+    if args.workload == "surrogate":
+        bench_surrogate(args)
         return
     import numpy as np
     import torch

@@ -81,6 +81,9 @@ int sur_infer(sur_t* s, const float* depth_mm, const float* pose6, const float* 
 int sur_train_step(sur_t* s, const float* depth_mm, const float* pose6, const float* prev_mm,
                    const float* target_mm, int32_t n, float* loss_out);
 
+/* Learning rate of the following Adam steps (a schedule is the caller's). */
+int sur_set_lr(sur_t* s, float lr);
+
 /* Same as sur_train_step without the update: leaves the gradients for
  * sur_get_grads (n_params floats, layout of sur_get_params). */
 int sur_compute_grads(sur_t* s, const float* depth_mm, const float* pose6, const float* prev_mm,

@@ -844,6 +844,13 @@ int sur_train_step(sur_t* s, const float* depth_mm, const float* pose6, const fl
     return SUR_OK;
 }
 
+int sur_set_lr(sur_t* s, float lr) {
+    if (!s) return SUR_EINVAL;
+    if (!(lr >= 0.f) || !std::isfinite(lr)) return sfail(s, SUR_EINVAL, "bad learning rate");
+    s->P.lr = lr;
+    return SUR_OK;
+}
+
 int sur_get_grads(sur_t* s, float* out_host) {
     if (!s || !out_host) return SUR_EINVAL;
     std::vector<float> in(s->n_int);

@@ -25,7 +25,7 @@ class sur_params(C.Structure):
 
 EXPORTS = ("sur_params_default", "sur_create", "sur_destroy", "sur_num_params", "sur_infer", "sur_train_step",
            "sur_compute_grads", "sur_get_grads", "sur_get_params", "sur_set_params", "sur_save", "sur_load",
-           "sur_debug_read", "sur_last_error")
+           "sur_debug_read", "sur_set_lr", "sur_last_error")
 
 _bound = False
 
@@ -50,6 +50,7 @@ def lib():
     L.sur_save.argtypes = [vp, C.c_char_p]
     L.sur_load.argtypes = [vp, C.c_char_p]
     L.sur_debug_read.argtypes = [vp, i32, i32, fp]
+    L.sur_set_lr.argtypes = [vp, C.c_float]
     L.sur_last_error.argtypes = [vp]
     L.sur_last_error.restype = C.c_char_p
     for name in EXPORTS:
@@ -130,6 +131,9 @@ class Surrogate:
         self._chk(lib().sur_compute_grads(self.h, _dev(depth), _dev(pose), _dev(prev), _dev(target),
                                           depth.shape[0], C.byref(loss)))
         return loss.value
+
+    def sur_set_lr(self, lr):
+        self._chk(lib().sur_set_lr(self.h, float(lr)))
 
     def sur_get_grads(self):
         g = np.zeros(self.n_params, np.float32)

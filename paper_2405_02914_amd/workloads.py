@@ -263,46 +263,81 @@ def config3(n_sensors: int = 64, seed: int = 3, k_range=(4, 12), dx: float = 0.5
     particles per cell; indenter ~ U{sphere r 2-6 mm, capsule r 2-4 mm with
     half-length 1-4 mm, rounded box half-sides 1.5-4 mm, Perlin height field
     with amplitude 0.2-0.5 mm, wavelength 1.5-4 mm, footprint radius 3-6 mm and
-    bowl radius 5-15 mm}; press depth
+    a bowl that rises 2.5-3.5 mm at the footprint's edge}; press depth
     U[0.3, 1.5] mm over the first quarter of the substeps, then slip U[0, 3] mm in
     a direction U[0, 2 pi) and rotation U[-45, 45] degrees.  Returns the list of
     SensorParams and the list of schedules."""
     rng = np.random.default_rng(seed)
     params, scheds = [], []
-    pad = padding_for(dx)
     for i in range(n_sensors):
         k = int(rng.integers(k_range[0], k_range[1] + 1))
-        cells = (8 * k, 8 * k, 2 * k)
-        L, H = 8 * k * dx, 2 * k * dx
-        kind = int(rng.integers(0, 4))
-        if kind == 0:
-            r = float(rng.uniform(2e-3, 6e-3))
-            shape = dict(shape=SHAPE_SPHERE, radius=r)
-            drop = r
-        elif kind == 1:
-            r = float(rng.uniform(2e-3, 4e-3))
-            shape = dict(shape=SHAPE_CAPSULE, radius=r, half_length=float(rng.uniform(1e-3, 4e-3)))
-            drop = r
-        elif kind == 2:
-            hx, hy = float(rng.uniform(1.5e-3, 4e-3)), float(rng.uniform(1.5e-3, 4e-3))
-            shape = dict(shape=SHAPE_BOX, half_extent=(hx, hy, 2e-3), fillet=0.5e-3)
-            drop = 2e-3
-        else:
-            foot = float(rng.uniform(3e-3, 6e-3))
-            tab = heightfield_table(int(rng.integers(0, 2**31)), foot, float(rng.uniform(0.2e-3, 0.5e-3)),
-                                    float(rng.uniform(1.5e-3, 4e-3)), float(rng.uniform(5e-3, 15e-3)))
-            shape = dict(shape=SHAPE_HEIGHTFIELD, hf=tab, hf_half=foot)
-            drop = 0.0
-        p = SensorParams(cells=cells, dx=dx, pad_lateral=pad, pad_top=pad, seed=1000 + i,
-                         subcycle=subcycle, pose0=(L / 2, L / 2, H + drop, 1.0, 0.0, 0.0, 0.0),
-                         **shape)
-        press = float(rng.uniform(0.3e-3, 1.5e-3))
-        slip = float(rng.uniform(0.0, 3e-3))
-        ang = float(rng.uniform(0.0, 2 * math.pi))
-        rot = float(rng.uniform(-45.0, 45.0))
+        p, sch = _random_trajectory(rng, (8 * k, 8 * k, 2 * k), dx, subcycle, n_substeps, 1000 + i)
         params.append(p)
-        scheds.append(_schedule(p.pose0, n_substeps, press, slip, ang, rot))
+        scheds.append(sch)
     return params, scheds
+
+
+def _random_trajectory(rng, cells, dx, subcycle, n_substeps, seed):
+    """One sensor with a random indenter (the distribution of config3) whose
+    lowest point starts on the slab's top over its centre, and its schedule."""
+    L, H = cells[0] * dx, cells[2] * dx
+    pad = padding_for(dx)
+    kind = int(rng.integers(0, 4))
+    if kind == 0:
+        r = float(rng.uniform(2e-3, 6e-3))
+        shape = dict(shape=SHAPE_SPHERE, radius=r)
+        drop = r
+    elif kind == 1:
+        r = float(rng.uniform(2e-3, 4e-3))
+        shape = dict(shape=SHAPE_CAPSULE, radius=r, half_length=float(rng.uniform(1e-3, 4e-3)))
+        drop = r
+    elif kind == 2:
+        hx, hy = float(rng.uniform(1.5e-3, 4e-3)), float(rng.uniform(1.5e-3, 4e-3))
+        shape = dict(shape=SHAPE_BOX, half_extent=(hx, hy, 2e-3), fillet=0.5e-3)
+        drop = 2e-3
+    else:
+        # the bowl rises rim = 2.5-3.5 mm at the footprint's edge, so the
+        # solid's vertical side wall stays above the slab at every press depth
+        foot = float(rng.uniform(3e-3, 6e-3))
+        amp, lam = float(rng.uniform(0.2e-3, 0.5e-3)), float(rng.uniform(1.5e-3, 4e-3))
+        rim = float(rng.uniform(2.5e-3, 3.5e-3))
+        tab = heightfield_table(int(rng.integers(0, 2**31)), foot, amp, lam, foot * foot / (2.0 * rim))
+        shape = dict(shape=SHAPE_HEIGHTFIELD, hf=tab, hf_half=foot)
+        drop = 0.0
+    p = SensorParams(cells=tuple(cells), dx=dx, pad_lateral=pad, pad_top=pad, seed=seed,
+                     subcycle=subcycle, pose0=(L / 2, L / 2, H + drop, 1.0, 0.0, 0.0, 0.0), **shape)
+    press = float(rng.uniform(0.3e-3, 1.5e-3))
+    slip = float(rng.uniform(0.0, 3e-3))
+    ang = float(rng.uniform(0.0, 2 * math.pi))
+    rot = float(rng.uniform(-45.0, 45.0))
+    return p, _schedule(p.pose0, n_substeps, press, slip, ang, rot)
+
+
+def surrogate_trajectories(n: int, seed: int, cells=(64, 64, 16), dx: float = 0.5e-3, n_substeps: int = 1000,
+                           subcycle: int = 2):
+    """Training or test trajectories for the surrogate: sensors with the
+    32 x 32 x 8 mm footprint of config2 (at dx 0.5 mm by default) and config3's
+    random indenters and press / slip / rotate schedules; frames every 50
+    substeps.  Returns (params, schedules)."""
+    rng = np.random.default_rng(seed)
+    out = [_random_trajectory(rng, cells, dx, subcycle, n_substeps, 100000 * seed + i) for i in range(n)]
+    return [o[0] for o in out], [o[1] for o in out]
+
+
+def pose_change(pose_a, pose_b):
+    """Surrogate pose input from pose a (pos m, quat wxyz) to pose b:
+    translation in mm and the rotation vector (rad) of q_b q_a^-1."""
+    pa, qa = np.asarray(pose_a[0], np.float64), np.asarray(pose_a[1], np.float64)
+    pb, qb = np.asarray(pose_b[0], np.float64), np.asarray(pose_b[1], np.float64)
+    w1, x1, y1, z1 = qb
+    w2, x2, y2, z2 = qa[0], -qa[1], -qa[2], -qa[3]
+    r = np.array([w1 * w2 - x1 * x2 - y1 * y2 - z1 * z2, w1 * x2 + x1 * w2 + y1 * z2 - z1 * y2,
+                  w1 * y2 - x1 * z2 + y1 * w2 + z1 * x2, w1 * z2 + x1 * y2 - y1 * x2 + z1 * w2])
+    if r[0] < 0:
+        r = -r
+    s = np.linalg.norm(r[1:])
+    rv = np.zeros(3) if s == 0 else r[1:] / s * 2.0 * math.atan2(s, r[0])
+    return np.concatenate([(pb - pa) * 1000.0, rv]).astype(np.float32)
 
 
 # ---------------------------------------------------------------- surrogate inputs
