@@ -231,6 +231,19 @@ def bench_surrogate(args):
     losses, secs = T.train(net, dtr, steps, batch, st, log=lambda *a, **k: print(*a, file=sys.stderr, **k))
     ev = T.evaluate(net, dte, st)
     fps, lat = T.inference_rate(net, dte, st, serve, reps=20)
+    # serving with IMPM fallback: held-out sensors against plain IMPM of the same trajectories
+    from paper_2405_02914_amd import serving
+    sp, ss = W.surrogate_trajectories(16, seed=31, n_substeps=50 * 40)
+    srv = serving.Server(sp, ss, net, st, record=True)
+    served = srv.run()
+    ref = T.generate(sp, ss, st, log=lambda *a, **k: None)
+    served["served_rms_mm"] = float(((srv.record[:, 1:] - ref.disp[:, 1:]) ** 2).mean().sqrt())
+    served["plain_impm_frames_per_s"] = ref.impm_frames_per_s
+    srv.close()
+    mp, ms = serving.sensor_mix(8, 40)
+    srv = serving.Server(mp, ms, net, st)
+    mixed = srv.run()
+    srv.close()
     fwd, trn = surrogate_flops()
     step_ms = 1e3 * secs / steps
     achieved = trn * batch / (step_ms * 1e-3) / 1e12
@@ -251,7 +264,8 @@ def bench_surrogate(args):
                    "rms_one_step_mm": ev["rms_one_step_mm"], "rms_rollout_mm": ev["rms_rollout_mm"],
                    "rms_persistence_mm": ev["rms_persistence_mm"],
                    "train_gflop_per_sample": trn / 1e9, "infer_gflop_per_sample": fwd / 1e9,
-                   "serve_batch_ms": 1e3 * lat},
+                   "serve_batch_ms": 1e3 * lat,
+                   "serving_64cells": served, "serving_mixed_64_96_128": mixed},
         "roofline": {"bound": "mfma", "kernel": "whole training step (all kernels, wall clock)",
                      "achieved": round(achieved, 1), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "traffic": None,

@@ -146,8 +146,10 @@ int sim_surface_displacement(sim_t* s, float* out, int32_t W, int32_t H, int32_t
 
 /* Depth of the indenter below the slab's top face along the vertical line
  * through each pixel centre (as for the height map): (H - z_low) * scale, where
- * z_low is the indenter's lowest point on that line at the current pose (the
- * object's "depth data" of Sec. IV-B, the surrogate's main input); -1e9 where
+ * z_low is the indenter's lowest point on that line at the target pose (the
+ * last sim_set_indenter_pose, which the next sim_step reaches; after a step,
+ * the current pose) -- the object's "depth data" of Sec. IV-B and the
+ * surrogate's main input; -1e9 where
  * the line misses the indenter.  Needs a pose rotated about z only (else
  * SIM_EINVAL).  out: W*H floats, host or device memory. */
 int sim_indenter_depthmap(sim_t* s, float* out, int32_t W, int32_t H, double scale, int32_t out_on_device);

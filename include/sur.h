@@ -81,6 +81,12 @@ int sur_infer(sur_t* s, const float* depth_mm, const float* pose6, const float* 
 int sur_train_step(sur_t* s, const float* depth_mm, const float* pose6, const float* prev_mm,
                    const float* target_mm, int32_t n, float* loss_out);
 
+/* Contact area of n samples (device pointers): area[i] = number of pixels of
+ * sample i with depth_mm + disp_mm[..., 2] >= -tol_mm, i.e. where the
+ * indenter's lower surface is within tol of the displaced elastomer surface
+ * or below it.  The serving loop's trigger for an IMPM re-solve. */
+int sur_contact_area(sur_t* s, const float* depth_mm, const float* disp_mm, int32_t n, float tol_mm, float* area);
+
 /* Learning rate of the following Adam steps (a schedule is the caller's). */
 int sur_set_lr(sur_t* s, float lr);
 

@@ -851,10 +851,11 @@ void orc_point_phi(const orc_sim *s, const double *X, int64_t n, double *phi) {
 /* Depth of the indenter below the slab's top face along the vertical line
  * through each pixel centre ((u+1/2) Lx/W, (v+1/2) Ly/H), times `scale`:
  * (top - z_low) scale, with z_low the lowest point of the indenter on that
- * line; -1e9 where the line misses it.  The indenter may only be rotated
- * about z (then its body z axis is vertical); returns -1 otherwise. */
+ * line at the target pose (the pose the next orc_step reaches; the current
+ * pose after a step); -1e9 where the line misses it.  The indenter may only be
+ * rotated about z (then its body z axis is vertical); returns -1 otherwise. */
 int orc_indenter_depthmap(const orc_sim *s, int W, int H, double scale, double *out) {
-    const double *q = s->quat;
+    const double *q = s->tquat;
     if (fabs(q[1]) > 1e-9 || fabs(q[2]) > 1e-9) return -1;
     double R[9];
     quat_to_matrix(q, R);
@@ -863,8 +864,8 @@ int orc_indenter_depthmap(const orc_sim *s, int W, int H, double scale, double *
     double top = (double)P->cells[2] * P->dx;
     for (int v = 0; v < H; ++v)
         for (int u = 0; u < W; ++u) {
-            double dx = ((double)u + 0.5) * Lx / (double)W - s->pos[0];
-            double dy = ((double)v + 0.5) * Ly / (double)H - s->pos[1];
+            double dx = ((double)u + 0.5) * Lx / (double)W - s->tpos[0];
+            double dy = ((double)v + 0.5) * Ly / (double)H - s->tpos[1];
             double px = R[0] * dx + R[3] * dy, py = R[1] * dx + R[4] * dy;
             int hit = 0;
             double zb = 0.0;
@@ -885,7 +886,7 @@ int orc_indenter_depthmap(const orc_sim *s, int W, int H, double scale, double *
             } else if (P->shape == 4) {
                 if (px * px + py * py <= P->hf_half * P->hf_half) { hit = 1; zb = hf_height(P, px, py); }
             }
-            out[(size_t)v * W + u] = hit ? (top - (s->pos[2] + zb)) * scale : -1e9;
+            out[(size_t)v * W + u] = hit ? (top - (s->tpos[2] + zb)) * scale : -1e9;
         }
     return 0;
 }

@@ -197,6 +197,15 @@ class SurrogateOracle:
         return theta - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
+def contact_area(depth_mm, disp_mm, tol_mm=0.02):
+    """Pixels per sample where the indenter's lower surface (slab top minus
+    depth) lies at or below the displaced surface plus tol:
+    top - depth <= top + u_z + tol."""
+    depth_mm = np.asarray(depth_mm, np.float64)
+    uz = np.asarray(disp_mm, np.float64)[..., 2]
+    return ((-depth_mm) <= uz + tol_mm).reshape(depth_mm.shape[0], -1).sum(1)
+
+
 def assemble_input(depth_mm, pose6, prev_mm, bf16=True):
     """Network input (N, H, W, 10): depth (mm, clipped to [-3, 3]), the six
     pose-change values at every pixel, the previous displacement (mm)."""

@@ -876,7 +876,7 @@ static int surface_raster(sim_t* s, float* out, int W, int H, int on_device, int
 int sim_indenter_depthmap(sim_t* s, float* out, int32_t W, int32_t H, double scale, int32_t out_on_device) {
     if (!s || !out || W < 1 || H < 1 || (long long)W * H > (1LL << 30) || !std::isfinite(scale))
         return fail(s, SIM_EINVAL, "bad depth map arguments");
-    if (std::fabs(s->quat[1]) > 1e-9 || std::fabs(s->quat[2]) > 1e-9)
+    if (std::fabs(s->tquat[1]) > 1e-9 || std::fabs(s->tquat[2]) > 1e-9)
         return fail(s, SIM_EINVAL, "the depth map needs an indenter rotated about z only");
     const long long npix = (long long)W * H;
     float* dst = out;
@@ -895,8 +895,8 @@ int sim_indenter_depthmap(sim_t* s, float* out, int32_t W, int32_t H, double sca
     g.Ly = (double)s->P.cells[1] * s->P.dx;
     g.top = (double)s->P.cells[2] * s->P.dx;
     g.scale = scale;
-    std::memcpy(g.c, s->pos, sizeof(g.c));
-    quat_matrix(s->quat, g.R);
+    std::memcpy(g.c, s->tpos, sizeof(g.c));
+    quat_matrix(s->tquat, g.R);
     hipLaunchKernelGGL(k_depthmap, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, s->stream, kargs(s), g, dst);
     HIPCHK(s, hipGetLastError());
     if (!out_on_device) {

@@ -425,6 +425,22 @@ __global__ __launch_bounds__(256) void k_cast_head(const float* th, int n, float
     if (i < n) whf[i] = bf2f(f2bf(th[i]));
 }
 
+// Contact area (pixels) of each sample: pixels where the indenter's lower
+// surface is within tol of the displaced elastomer surface or below it,
+// depth + u_z >= -tol (all mm).  One block per sample.
+__global__ __launch_bounds__(256) void k_contact_area(const float* depth, const float* disp, int HW, float tol,
+                                                      float* area) {
+    __shared__ int red[4];
+    const long long base = (long long)blockIdx.x * HW;
+    int c = 0;
+    for (int q = threadIdx.x; q < HW; q += 256) c += depth[base + q] + disp[(base + q) * 3 + 2] >= -tol ? 1 : 0;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) area[blockIdx.x] = (float)(red[0] + red[1] + red[2] + red[3]);
+}
+
 __global__ __launch_bounds__(256) void k_zero(float* p, long long n) {
     for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) p[i] = 0.f;
 }
@@ -840,6 +856,16 @@ int sur_train_step(sur_t* s, const float* depth_mm, const float* pose6, const fl
     hipLaunchKernelGGL(k_adam, dim3(blocks_for(s->n_int)), dim3(256), 0, s->stream, s->theta, s->grad, s->m, s->v,
                        s->n_int, s->P.lr, s->P.beta1, s->P.beta2, s->P.eps, (float)c1, (float)c2);
     cast_all(s);
+    SHIP(s, hipGetLastError());
+    return SUR_OK;
+}
+
+int sur_contact_area(sur_t* s, const float* depth_mm, const float* disp_mm, int32_t n, float tol_mm, float* area) {
+    if (!s) return SUR_EINVAL;
+    if (!depth_mm || !disp_mm || !area || n < 1 || !(tol_mm >= 0.f))
+        return sfail(s, SUR_EINVAL, "bad contact-area arguments");
+    hipLaunchKernelGGL(k_contact_area, dim3(n), dim3(256), 0, s->stream, depth_mm, disp_mm, s->P.H * s->P.W, tol_mm,
+                       area);
     SHIP(s, hipGetLastError());
     return SUR_OK;
 }

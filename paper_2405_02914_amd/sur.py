@@ -25,7 +25,7 @@ class sur_params(C.Structure):
 
 EXPORTS = ("sur_params_default", "sur_create", "sur_destroy", "sur_num_params", "sur_infer", "sur_train_step",
            "sur_compute_grads", "sur_get_grads", "sur_get_params", "sur_set_params", "sur_save", "sur_load",
-           "sur_debug_read", "sur_set_lr", "sur_last_error")
+           "sur_debug_read", "sur_set_lr", "sur_contact_area", "sur_last_error")
 
 _bound = False
 
@@ -51,6 +51,7 @@ def lib():
     L.sur_load.argtypes = [vp, C.c_char_p]
     L.sur_debug_read.argtypes = [vp, i32, i32, fp]
     L.sur_set_lr.argtypes = [vp, C.c_float]
+    L.sur_contact_area.argtypes = [vp, fp, fp, i32, C.c_float, fp]
     L.sur_last_error.argtypes = [vp]
     L.sur_last_error.restype = C.c_char_p
     for name in EXPORTS:
@@ -110,7 +111,10 @@ class Surrogate:
             self.h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:       # interpreter shutdown: module globals may be gone
+            pass
 
     def sur_infer(self, depth, pose, prev, out=None):
         import torch
@@ -131,6 +135,14 @@ class Surrogate:
         self._chk(lib().sur_compute_grads(self.h, _dev(depth), _dev(pose), _dev(prev), _dev(target),
                                           depth.shape[0], C.byref(loss)))
         return loss.value
+
+    def sur_contact_area(self, depth, disp, tol=0.02, out=None):
+        import torch
+        n = depth.shape[0]
+        if out is None:
+            out = torch.empty(n, device=depth.device, dtype=torch.float32)
+        self._chk(lib().sur_contact_area(self.h, _dev(depth), _dev(disp), n, float(tol), _dev(out)))
+        return out
 
     def sur_set_lr(self, lr):
         self._chk(lib().sur_set_lr(self.h, float(lr)))
