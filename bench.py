@@ -45,11 +45,11 @@ PEAK_HBM_GBS = 8000.0
 # grid's share (two 16 B node records per 8 particles, read and written, ~7 B).
 ALG_BYTES_PER_PARTICLE_PASS = 192.0 + 7.0
 # HBM bytes per launch of the fused kernel for this workload, from two
-# rocprofv3 --pmc runs (FETCH_SIZE 290963 KiB, WRITE_SIZE 447834 KiB per
-# dispatch) scaled by the counters' reading of a copy of known size (fetched
-# bytes = 2.0 x FETCH_SIZE, written = 1.0 x WRITE_SIZE); set to None whenever the
-# kernel changes until the counters are taken again.
-PMC_TRAFFIC_BYTES = (2.0 * 290963 + 447834) * 1024
+# rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) scaled by
+# the counters' reading of a copy of known size (fetched bytes = 2.0 x
+# FETCH_SIZE, written = 1.0 x WRITE_SIZE); None whenever the kernel has changed
+# since the counters were taken.
+PMC_TRAFFIC_BYTES = None
 
 
 def parse():

@@ -86,6 +86,7 @@ struct SurfArgs {
     float dx;
     long long n;
     const float* rest_r;         // 3 per surface particle: in-cell rest offsets
+    const uint32_t* id_of;       // particle id of each storage slot
     unsigned long long* acc;     // H*W x 4 fixed-point sums (w, w ux, w uy, w uz), u in cells
 };
 
@@ -129,7 +130,12 @@ struct TileOps {
                  hipStream_t st);
     void (*g2p2g)(const BatchMap& m, int tile_blocks, int cur, int step, int par, int pass,
                   int store_vc, bool extra, hipStream_t st);
+    // passes 1..npass-1 of a step in one cooperative launch
+    hipError_t (*extra)(const BatchMap& m, int tile_blocks, int node_blocks, int cur, int step, int par, int npass,
+                        int store_vc, hipStream_t st);
 };
+// Cooperative launches are never recorded into a HIP graph: graph replays
+// launch one node and one fused kernel per pass slot instead.
 extern const TileOps kTileOps[];
 extern const int kNumTileOps;
 

@@ -74,6 +74,11 @@ static hipError_t graph_run(GraphCache& gc, const std::vector<long long>& key, h
 
 struct sim_s {
     sim_params P;
+    // Device storage order ("slots"): the particles grouped by the stencil base
+    // node of the initial state, tile by tile, so that a tile's particles fill
+    // whole cache lines of every plane.  The ABI addresses particles by id.
+    std::vector<uint32_t> slot_of, id_of;
+    uint32_t* d_id_of = nullptr;
     bool use_graph = false;       // replay step sequences as HIP graphs
     GraphCache graphs;
     std::vector<double> hf_host;  // height-field table (P.hf points here)
@@ -309,7 +314,7 @@ static KArgs kargs(const sim_t* s) {
     a.hf_half = P.hf_half;
     a.mp = (float)s->mp;
     a.n = s->n;
-    a.e = s->e;
+    a.e = s->slot_of[s->e];
     a.soa = s->soa;
     a.cell = s->cell;
     a.flags = s->flags;
@@ -329,21 +334,52 @@ static KArgs kargs(const sim_t* s) {
     return a;
 }
 
-// Host-side counting sort of the particles by tile (stable in id order).
-static int rebin_host(sim_t* s, const std::vector<uint32_t>& cells, const std::vector<float>& offs) {
-    std::vector<uint32_t> cnt(s->n_tiles + 1, 0), tile(s->n);
-    for (long long id = 0; id < s->n; ++id) {
-        // tile of the stencil base node floor(x - 1/2)
-        const uint32_t c = cells[id];
+// Tile order of the particles: grouped by the tile of their stencil base node
+// floor(x - 1/2) and, inside a tile, round-robin over the base nodes (the first
+// particle of every base node, then the second, ...), so that the lanes of a
+// wave scatter to different nodes -- particles sharing a base node add to the
+// same 27 LDS addresses, and same-address LDS atomics of one instruction
+// serialise.  cnt receives the tile starts (n_tiles + 1).
+static void tile_order(const sim_t* s, const std::vector<uint32_t>& cells, const float* offs,
+                       std::vector<uint32_t>& order, std::vector<uint32_t>& cnt) {
+    const int T0 = s->T[0], T1 = s->T[1], T2 = s->T[2];
+    const long long n = s->n;
+    cnt.assign(s->n_tiles + 1, 0);
+    std::vector<uint64_t> key(n);
+    for (long long k = 0; k < n; ++k) {
+        const uint32_t c = cells[k];
         int b[3] = {(int)(c & 1023) - 1, (int)((c >> 10) & 1023) - 1, (int)((c >> 20) & 1023) - 1};
-        for (int q = 0; q < 3; ++q) b[q] += offs[(size_t)q * s->n + id] >= 0.5f ? 1 : 0;
-        const int t = ((b[2] / s->T[2]) * s->NT[1] + b[1] / s->T[1]) * s->NT[0] + b[0] / s->T[0];
-        tile[id] = t;
+        for (int q = 0; q < 3; ++q) b[q] += offs[(size_t)q * n + k] >= 0.5f ? 1 : 0;
+        const int t = ((b[2] / T2) * s->NT[1] + b[1] / T1) * s->NT[0] + b[0] / T0;
+        const uint64_t node = ((uint64_t)b[2] * s->nn[1] + b[1]) * s->nn[0] + b[0];   // < 2^30
+        key[k] = (node << 32) | (uint64_t)k;
         cnt[t + 1]++;
     }
+    std::sort(key.begin(), key.end());
+    // rank among the particles of the same base node (indices ascending), then
+    // sort by (tile, rank, base node in the tile), which is unique per particle
+    std::vector<std::pair<uint64_t, uint32_t>> ord(n);
+    uint32_t rank = 0;
+    for (long long q = 0; q < n; ++q) {
+        const uint64_t node = key[q] >> 32;
+        rank = (q > 0 && (key[q - 1] >> 32) == node) ? rank + 1 : 0;
+        const int b0 = (int)(node % s->nn[0]), b1 = (int)((node / s->nn[0]) % s->nn[1]);
+        const int b2 = (int)(node / ((uint64_t)s->nn[0] * s->nn[1]));
+        const uint64_t t = ((uint64_t)(b2 / T2) * s->NT[1] + b1 / T1) * s->NT[0] + b0 / T0;
+        const uint64_t local = ((uint64_t)(b2 % T2) * T1 + b1 % T1) * T0 + b0 % T0;   // < 512
+        ord[q] = {(t << 22) | ((uint64_t)std::min<uint32_t>(rank, 4095) << 10) | local,
+                  (uint32_t)(key[q] & 0xFFFFFFFFu)};
+    }
+    std::sort(ord.begin(), ord.end());
     for (int t = 0; t < s->n_tiles; ++t) cnt[t + 1] += cnt[t];
-    std::vector<uint32_t> order(s->n), pos(cnt.begin(), cnt.end() - 1);
-    for (long long id = 0; id < s->n; ++id) order[pos[tile[id]]++] = (uint32_t)id;
+    order.resize(n);
+    for (long long q = 0; q < n; ++q) order[q] = ord[q].second;
+}
+
+// Host-side binning of the stored particles (slots) by tile.
+static int rebin_host(sim_t* s, const std::vector<uint32_t>& cells, const std::vector<float>& offs) {
+    std::vector<uint32_t> order, cnt;
+    tile_order(s, cells, offs.data(), order, cnt);
     HIPCHK(s, hipMemcpyAsync(s->order[s->cur], order.data(), s->n * 4, hipMemcpyHostToDevice, s->stream));
     HIPCHK(s, hipMemcpyAsync(s->bstart[s->cur], cnt.data(), (s->n_tiles + 1) * 4, hipMemcpyHostToDevice,
                              s->stream));
@@ -405,9 +441,10 @@ static int refresh_binning(sim_t* s) {
     if (rc) return rc;
     uint32_t ce;
     float fe[3];
-    HIPCHK(s, hipMemcpy(&ce, s->cell + s->e, 4, hipMemcpyDeviceToHost));
+    const size_t se = s->slot_of[s->e];
+    HIPCHK(s, hipMemcpy(&ce, s->cell + se, 4, hipMemcpyDeviceToHost));
     for (int q = 0; q < 3; ++q)
-        HIPCHK(s, hipMemcpy(&fe[q], s->soa + (size_t)(F0 + q) * s->n + s->e, 4, hipMemcpyDeviceToHost));
+        HIPCHK(s, hipMemcpy(&fe[q], s->soa + (size_t)(F0 + q) * s->n + se, 4, hipMemcpyDeviceToHost));
     s->pending = false;
     return set_xe_snapshot(s, ce, fe);
 }
@@ -481,6 +518,16 @@ static int prepare_step(sim_t* s, int32_t n_substeps, std::vector<int>& npass) {
     return sync_args(s);
 }
 
+static bool coop_supported() {
+    static int ok = -1;
+    if (ok < 0) {
+        int dev = 0, coop = 0;
+        ok = hipGetDevice(&dev) == hipSuccess &&
+             hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) == hipSuccess && coop;
+    }
+    return ok == 1;
+}
+
 // One group of sensors that share a tile shape, launched together.
 struct LaunchSet {
     const TileOps* ops;
@@ -488,22 +535,31 @@ struct LaunchSet {
     int tile_blocks, node_blocks, n;
     int limit_slots;
     hipStream_t st;
+    bool coop;                 // passes after the first in one cooperative launch
 };
 
 // The kernels of one executed step: node kernel and fused exchange of the first
-// pass, the extra passes, then the counting sort of the next binned order.
-static void launch_step(const LaunchSet& L, int j, int npass, int cur, int sbin, int par, int store,
-                        hipEvent_t e0, hipEvent_t e1) {
+// pass, the passes after the first (one cooperative launch that stops when the
+// relative-rest test is met, or one node + fused launch per pass slot), then
+// the counting sort of the next binned order.
+static hipError_t launch_step(const LaunchSet& L, int j, int npass, int cur, int sbin, int par, int store,
+                              hipEvent_t e0, hipEvent_t e1) {
     L.ops->grid(L.m, L.node_blocks, sbin, j, 0, false, L.st);
     if (e0) (void)hipEventRecord(e0, L.st);
     L.ops->g2p2g(L.m, L.tile_blocks, cur, j, par, 0, store, false, L.st);
     if (e1) (void)hipEventRecord(e1, L.st);
-    for (int pass = 1; pass < npass; ++pass) {
-        L.ops->grid(L.m, L.node_blocks, cur, j, pass, true, L.st);
-        L.ops->g2p2g(L.m, L.tile_blocks, cur, j, par, pass, store, true, L.st);
+    hipError_t err = hipSuccess;
+    if (npass > 1 && L.coop) {
+        err = L.ops->extra(L.m, L.tile_blocks, L.node_blocks, cur, j, par, npass, store, L.st);
+    } else {
+        for (int pass = 1; pass < npass; ++pass) {
+            L.ops->grid(L.m, L.node_blocks, cur, j, pass, true, L.st);
+            L.ops->g2p2g(L.m, L.tile_blocks, cur, j, par, pass, store, true, L.st);
+        }
     }
     hipLaunchKernelGGL(k_scan, dim3(L.n), dim3(1024), 0, L.st, L.m, cur ^ 1, L.limit_slots);
     hipLaunchKernelGGL(k_scatter, dim3(L.tile_blocks), dim3(kBlock), 0, L.st, L.m, cur);
+    return err;
 }
 
 static void finish_call(sim_t* s, int32_t n_substeps, long long N) {
@@ -691,11 +747,36 @@ int sim_create(const sim_params* p, void* hip_stream, sim_t** out) {
         if (d2 < best) { best = d2; s->e = id; }
     }
     // G = 0 (F = I), v = 0, C = 0 already
+    const float fe[3] = {host[(size_t)F0 * n + s->e], host[(size_t)(F0 + 1) * n + s->e],
+                         host[(size_t)(F0 + 2) * n + s->e]};
+    const uint32_t ce = cells[s->e];
+    {
+        // storage order: the tile order of the initial state, so that a wave's
+        // loads and stores cover consecutive slots
+        std::vector<uint32_t> cnt;
+        tile_order(s, cells, host.data() + (size_t)F0 * n, s->id_of, cnt);
+        s->slot_of.resize(n);
+        for (size_t k = 0; k < n; ++k) s->slot_of[s->id_of[k]] = (uint32_t)k;
+        std::vector<float> hp(host.size());
+        std::vector<uint32_t> cp(n);
+        std::vector<uint8_t> fp(n);
+        for (size_t k = 0; k < n; ++k) {
+            const size_t id = s->id_of[k];
+            for (int q = 0; q < NPLANES; ++q) hp[(size_t)q * n + k] = host[(size_t)q * n + id];
+            cp[k] = cells[id];
+            fp[k] = flags[id];
+        }
+        host.swap(hp);
+        cells.swap(cp);
+        flags.swap(fp);
+    }
     if (hipMemcpy(s->soa, host.data(), n * NPLANES * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(s->cell, cells.data(), n * 4, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(s->flags, flags.data(), n, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(s->st, 0, sizeof(DevState)) != hipSuccess)
         return bail(SIM_EHIP);
+    if (hipMalloc(&s->d_id_of, n * 4) != hipSuccess) return bail(SIM_ENOMEM);
+    if (hipMemcpy(s->d_id_of, s->id_of.data(), n * 4, hipMemcpyHostToDevice) != hipSuccess) return bail(SIM_EHIP);
     if (hipMalloc(&s->surf_rest, srest.size() * sizeof(float)) != hipSuccess) return bail(SIM_ENOMEM);
     if (hipMemcpy(s->surf_rest, srest.data(), srest.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
         return bail(SIM_EHIP);
@@ -703,9 +784,7 @@ int sim_create(const sim_params* p, void* hip_stream, sim_t** out) {
         std::vector<float> offs(host.begin() + (size_t)F0 * n, host.begin() + (size_t)(F0 + 3) * n);
         if (rebin_host(s, cells, offs) != SIM_OK) return bail(SIM_EHIP);
     }
-    const float fe[3] = {host[(size_t)F0 * n + s->e], host[(size_t)(F0 + 1) * n + s->e],
-                         host[(size_t)(F0 + 2) * n + s->e]};
-    if (set_xe_snapshot(s, cells[s->e], fe) != SIM_OK) return bail(SIM_EHIP);
+    if (set_xe_snapshot(s, ce, fe) != SIM_OK) return bail(SIM_EHIP);
     *out = s;
     return SIM_OK;
 }
@@ -715,7 +794,8 @@ void sim_destroy(sim_t* s) {
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     void* bufs[] = {s->soa, s->cell, s->flags, s->order[0], s->order[1], s->bstart[0], s->bstart[1],
                     s->dirrank, s->dircount, s->newcnt, s->scratch, s->gridV, s->dbgM, s->dbgMG,
-                    s->st, s->poses, s->surf_rest, s->surf_acc, s->out_tmp, s->d_args, s->d_hf};
+                    s->st, s->poses, s->surf_rest, s->surf_acc, s->out_tmp, s->d_args, s->d_hf,
+                    s->d_id_of};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     for (int k = 0; k < 2; ++k) {
@@ -776,6 +856,7 @@ int sim_step(sim_t* s, int32_t n_substeps) {
     L.n = 1;
     L.limit_slots = std::min(34, s->P.rest_limit + 2);
     L.st = s->stream;
+    L.coop = !(s->use_graph && !s->prof) && coop_supported();   // eager launches only
     if (!s->pending) {
         L.ops->p2g(L.m, L.tile_blocks, s->cur, s->stream);
         HIPCHK(s, hipGetLastError());
@@ -786,18 +867,22 @@ int sim_step(sim_t* s, int32_t n_substeps) {
     if (s->use_graph && !s->prof) {
         std::vector<long long> key = {N, cur, sbin, g & 1, s->tile_idx, L.tile_blocks, L.node_blocks};
         key.insert(key.end(), npass.begin(), npass.end());
+        hipError_t le = hipSuccess;
         const hipError_t e = graph_run(s->graphs, key, s->stream, [&](hipStream_t cs) {
             LaunchSet Lc = L;
             Lc.st = cs;
             int c = cur, sb = sbin;
             long long gg = g;
             for (long long j = 0; j < N; ++j) {
-                launch_step(Lc, (int)j, npass[j], c, sb, (int)(gg & 1), j == N - 1 ? 1 : 0, nullptr, nullptr);
+                const hipError_t r =
+                    launch_step(Lc, (int)j, npass[j], c, sb, (int)(gg & 1), j == N - 1 ? 1 : 0, nullptr, nullptr);
+                if (le == hipSuccess) le = r;
                 sb = c;
                 c ^= 1;
                 gg += 1;
             }
         });
+        if (le != hipSuccess) return fail(s, SIM_EHIP, std::string("step launch: ") + hipGetErrorString(le));
         if (e != hipSuccess) return fail(s, SIM_EHIP, std::string("step graph: ") + hipGetErrorString(e));
         finish_call(s, n_substeps, N);
         return SIM_OK;
@@ -813,7 +898,7 @@ int sim_step(sim_t* s, int32_t n_substeps) {
             e0 = s->ev_pool[s->ev_used++];
             e1 = s->ev_pool[s->ev_used++];
         }
-        launch_step(L, (int)j, npass[j], cur, sbin, (int)(g & 1), j == N - 1 ? 1 : 0, e0, e1);
+        HIPCHK(s, launch_step(L, (int)j, npass[j], cur, sbin, (int)(g & 1), j == N - 1 ? 1 : 0, e0, e1));
         HIPCHK(s, hipGetLastError());
         sbin = cur;
         cur ^= 1;
@@ -858,6 +943,7 @@ static int surface_raster(sim_t* s, float* out, int W, int H, int on_device, int
     sa.dx = (float)s->P.dx;
     sa.n = s->n;
     sa.rest_r = s->surf_rest;
+    sa.id_of = s->d_id_of;
     sa.acc = s->surf_acc;
     hipLaunchKernelGGL(k_fill, dim3(std::min<long long>((npix * 8 + 255) / 256, 4096)), dim3(256), 0, s->stream,
                        reinterpret_cast<float*>(s->surf_acc), npix * 8, 0.0f);
@@ -958,17 +1044,20 @@ int sim_read_particles(sim_t* s, double* x, float* v, float* C, float* G) {
         HIPCHK(s, hipMemcpy(f.data(), s->soa + (size_t)F0 * n, 3 * n * 4, hipMemcpyDeviceToHost));
         const int off[3] = {s->P.pad_lateral, s->P.pad_lateral, s->P.pad_bottom};
         for (size_t id = 0; id < n; ++id) {
-            const uint32_t c = cells[id];
+            const size_t k = s->slot_of[id];
+            const uint32_t c = cells[k];
             const int cc[3] = {(int)(c & 1023), (int)((c >> 10) & 1023), (int)((c >> 20) & 1023)};
             for (int a = 0; a < 3; ++a)
-                x[3 * id + a] = ((double)(cc[a] - off[a]) + (double)f[a * n + id]) * s->P.dx;
+                x[3 * id + a] = ((double)(cc[a] - off[a]) + (double)f[a * n + k]) * s->P.dx;
         }
     }
     auto planes = [&](float* dst, int p0, int np) -> int {
         std::vector<float> tmp((size_t)np * n);
         HIPCHK(s, hipMemcpy(tmp.data(), s->soa + (size_t)p0 * n, (size_t)np * n * 4, hipMemcpyDeviceToHost));
-        for (size_t id = 0; id < n; ++id)
-            for (int q = 0; q < np; ++q) dst[np * id + q] = tmp[(size_t)q * n + id];
+        for (size_t id = 0; id < n; ++id) {
+            const size_t k = s->slot_of[id];
+            for (int q = 0; q < np; ++q) dst[np * id + q] = tmp[(size_t)q * n + k];
+        }
         return SIM_OK;
     };
     int rc;
@@ -996,17 +1085,19 @@ int sim_write_particles(sim_t* s, const double* x, const float* v, const float* 
                 cc[a] = (int)fl + off[a];
                 if (!std::isfinite(g) || cc[a] < 1 || cc[a] > s->nn[a] - 3)
                     return fail(s, SIM_EINVAL, "particle position outside the grid");
-                f[a * n + id] = fr;
+                f[a * n + s->slot_of[id]] = fr;
             }
-            cells[id] = pack_cell(cc);
+            cells[s->slot_of[id]] = pack_cell(cc);
         }
         HIPCHK(s, hipMemcpy(s->cell, cells.data(), n * 4, hipMemcpyHostToDevice));
         HIPCHK(s, hipMemcpy(s->soa + (size_t)F0 * n, f.data(), 3 * n * 4, hipMemcpyHostToDevice));
     }
     auto planes = [&](const float* src, int p0, int np) -> int {
         std::vector<float> tmp((size_t)np * n);
-        for (size_t id = 0; id < n; ++id)
-            for (int q = 0; q < np; ++q) tmp[(size_t)q * n + id] = src[np * id + q];
+        for (size_t id = 0; id < n; ++id) {
+            const size_t k = s->slot_of[id];
+            for (int q = 0; q < np; ++q) tmp[(size_t)q * n + k] = src[np * id + q];
+        }
         HIPCHK(s, hipMemcpy(s->soa + (size_t)p0 * n, tmp.data(), (size_t)np * n * 4, hipMemcpyHostToDevice));
         return SIM_OK;
     };
@@ -1032,7 +1123,11 @@ int sim_read_rest(sim_t* s, double* X, uint8_t* flags) {
                 X[3 * id + a] = ((double)ci[a] + (double)rest_offset(P.seed, id, a, si[a], m)) * P.dx;
         }
     }
-    if (flags) HIPCHK(s, hipMemcpy(flags, s->flags, s->n, hipMemcpyDeviceToHost));
+    if (flags) {
+        std::vector<uint8_t> fs(s->n);
+        HIPCHK(s, hipMemcpy(fs.data(), s->flags, s->n, hipMemcpyDeviceToHost));
+        for (long long id = 0; id < s->n; ++id) flags[id] = fs[s->slot_of[id]];
+    }
     return SIM_OK;
 }
 
@@ -1309,6 +1404,7 @@ int sim_batch_step(sim_batch_t* b, int32_t n_substeps) {
         L.n = (int)g.members.size();
         L.limit_slots = std::min(34, s0->P.rest_limit + 2);
         L.st = b->stream;
+        L.coop = !b->use_graph && coop_supported();                // eager launches only
         sets.push_back(L);
     }
     if (!s0->pending) {
@@ -1317,13 +1413,16 @@ int sim_batch_step(sim_batch_t* b, int32_t n_substeps) {
     }
     int cur = s0->cur, sbin = s0->sbin;
     long long g = s0->gstep;
+    hipError_t le = hipSuccess;
     auto emit = [&](hipStream_t st) {
         int c = cur, sb = sbin;
         long long gg = g;
         for (long long j = 0; j < N; ++j) {
             for (auto L : sets) {
                 L.st = st;
-                launch_step(L, (int)j, npass_max[j], c, sb, (int)(gg & 1), j == N - 1 ? 1 : 0, nullptr, nullptr);
+                const hipError_t r = launch_step(L, (int)j, npass_max[j], c, sb, (int)(gg & 1),
+                                                 j == N - 1 ? 1 : 0, nullptr, nullptr);
+                if (le == hipSuccess) le = r;
             }
             sb = c;
             c ^= 1;
@@ -1338,6 +1437,7 @@ int sim_batch_step(sim_batch_t* b, int32_t n_substeps) {
     } else {
         emit(b->stream);
     }
+    if (le != hipSuccess) return bfail(b, SIM_EHIP, std::string("batch step launch: ") + hipGetErrorString(le));
     BHIPCHK(b, hipGetLastError());
     for (sim_t* s : b->sims) finish_call(s, n_substeps, N);
     return SIM_OK;

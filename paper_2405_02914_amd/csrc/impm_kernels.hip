@@ -5,9 +5,17 @@
 // Algorithm 1, grid-to-particle (Eq. 6-7), the commit (Eq. 8-9) and the
 // particle-to-grid transfer of the next exchange.  Particles are binned by tile
 // with a counting sort every committed step.
+#include <hip/hip_cooperative_groups.h>
+
 #include "impm_device.h"
 
 namespace impm {
+
+// Loop flags are read at agent scope, past the compute unit's vector cache:
+// inside one cooperative launch other blocks write them between grid barriers.
+__device__ __forceinline__ int flag_load(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 __device__ __forceinline__ int tile_linear(const KArgs& a, const int tc[3]) {
     return (tc[2] * a.NT[1] + tc[1]) * a.NT[0] + tc[0];
@@ -203,14 +211,14 @@ __global__ __launch_bounds__(TL::NT) void k_p2g(BatchMap m, int cur) {
 // EXTRA: the same for the passes after the first of a step, which run only while
 // the relative-rest test fails.
 template <class TL, bool EXTRA>
-__global__ __launch_bounds__(kBlock) void k_grid(BatchMap m, int sbin, int step, int pass) {
-    int s = 0, nb = blockIdx.x;
+__device__ __forceinline__ void grid_block(const BatchMap& m, int gnb, int sbin, int step, int pass) {
+    int s = 0, nb = gnb;
     if (m.node_base) {
         s = batch_find(m.node_base, m.n, nb);
         nb -= m.node_base[s];
     }
     const KArgs& a = m.args[s];
-    if (a.st->finished[pass]) return;
+    if (flag_load(&a.st->finished[pass])) return;
     const uint32_t* __restrict__ bstart = a.bstart[sbin];
     const long long nid = nb * (long long)kBlock + threadIdx.x;
     const long long n_nodes = (long long)a.nn[0] * a.nn[1] * a.nn[2];
@@ -266,15 +274,15 @@ __global__ __launch_bounds__(kBlock) void k_grid(BatchMap m, int sbin, int step,
 //     otherwise transfer it (same x and F, new v and C) to the next pass's grid.
 // EXTRA marks the launches for passes after the first of a step.
 template <class TL, bool EXTRA>
-__global__ __launch_bounds__(TL::NT) void k_g2p2g(BatchMap m, int cur, int step, int par, int pass,
-                                                  int store_vc) {
-    int s = 0, t = blockIdx.x;
+__device__ __forceinline__ void g2p2g_tile(const BatchMap& m, int gt, int cur, int step, int par, int pass,
+                                           int store_vc) {
+    int s = 0, t = gt;
     if (m.tile_base) {
         s = batch_find(m.tile_base, m.n, t);
         t -= m.tile_base[s];
     }
     const KArgs& a = m.args[s];
-    if (a.st->finished[pass]) {
+    if (flag_load(&a.st->finished[pass])) {
         // carry the flag to the next pass slot so that every later pass of the
         // step is skipped as well
         if (t == 0 && threadIdx.x == 0) a.st->finished[pass + 1] = 1;
@@ -542,6 +550,64 @@ __global__ __launch_bounds__(TL::NT) void k_g2p2g(BatchMap m, int cur, int step,
     }
 }
 
+// The node and fused kernels stride over the launch's node blocks / tiles.  A
+// first-pass launch has one block per item; the launches of later passes use a
+// grid of at most kExtraBlocks blocks, so that a pass that the relative-rest
+// test has already made unnecessary costs a small dispatch rather than one
+// block per tile (every block exits on the step's flag).
+constexpr int kExtraBlocks = 1024;
+
+template <class TL, bool EXTRA>
+__global__ __launch_bounds__(kBlock) void k_grid(BatchMap m, int total, int sbin, int step, int pass) {
+    if (!EXTRA) {
+        grid_block<TL, EXTRA>(m, blockIdx.x, sbin, step, pass);
+        return;
+    }
+    for (int nb = blockIdx.x; nb < total; nb += gridDim.x) grid_block<TL, EXTRA>(m, nb, sbin, step, pass);
+}
+
+template <class TL, bool EXTRA>
+__global__ __launch_bounds__(TL::NT) void k_g2p2g(BatchMap m, int total, int cur, int step, int par, int pass,
+                                                  int store_vc) {
+    if (!EXTRA) {
+        g2p2g_tile<TL, EXTRA>(m, blockIdx.x, cur, step, par, pass, store_vc);
+        return;
+    }
+    for (int gt = blockIdx.x; gt < total; gt += gridDim.x) {
+        g2p2g_tile<TL, EXTRA>(m, gt, cur, step, par, pass, store_vc);
+        __syncthreads();   // the next tile reuses the block's LDS
+    }
+}
+
+// Passes 2..npass of a step in one cooperative launch (every block resident):
+// node phase, grid barrier, fused exchange phase, grid barrier, per pass.  The
+// loop stops as soon as every sensor's relative-rest test has ended its step,
+// so a step that converged at its first pass costs one short launch.  Agent-
+// scope fences around each barrier publish this phase's writes (node
+// velocities, tile partials, flags) and drop stale lines from the vector cache.
+template <class TL>
+__global__ __launch_bounds__(TL::NT) void k_extra_passes(BatchMap m, int tiles, int node_blocks, int cur, int step,
+                                                         int par, int npass, int store_vc) {
+    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+    for (int pass = 1; pass < npass; ++pass) {
+        bool done = true;
+        for (int s = 0; s < m.n; ++s) done = done && flag_load(&m.args[s].st->finished[pass]) != 0;
+        if (done) break;                      // the same decision in every block
+        if (threadIdx.x < kBlock)
+            for (int nb = blockIdx.x; nb < node_blocks; nb += gridDim.x) grid_block<TL, true>(m, nb, cur, step, pass);
+        __threadfence();
+        grid.sync();
+        __threadfence();
+        for (int gt = blockIdx.x; gt < tiles; gt += gridDim.x) {
+            g2p2g_tile<TL, true>(m, gt, cur, step, par, pass, store_vc);
+            __syncthreads();
+        }
+        __threadfence();
+        grid.sync();
+        __threadfence();
+    }
+}
+
 // Counting sort, scan part: exclusive prefix sum of the next step's tile sizes
 // (accumulated by the fused kernel), one block; clears the counts and the
 // per-step loop flags for the next step.
@@ -639,9 +705,10 @@ __global__ __launch_bounds__(kBlock) void k_scatter(BatchMap m, int cur) {
 // accumulator of 64-bit fixed-point sums (2^-32), so the maps are exact and
 // independent of the order of the atomics.
 __global__ void k_surface_accum(KArgs a, SurfArgs s) {
-    const long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (id >= a.n) return;
-    if (!(a.flags[id] & FLAG_SURFACE)) return;
+    const long long slot = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (slot >= a.n) return;
+    if (!(a.flags[slot] & FLAG_SURFACE)) return;
+    const long long id = s.id_of[slot];
     const int ppc = s.m * s.m * s.m;
     const long long cell_id = id / ppc;
     const int sub = (int)(id % ppc);
@@ -651,7 +718,7 @@ __global__ void k_surface_accum(KArgs a, SurfArgs s) {
     const long long sidx = ((long long)cj * s.Nx + ci) * s.m * s.m + sy * s.m + sx;
     int cell[3];
     float f[3];
-    load_particle(a, id, cell, f);
+    load_particle(a, slot, cell, f);
     const int rc[3] = {ci + s.pad_l, cj + s.pad_l, ck + s.pad_b};
     float u[3];
     for (int q = 0; q < 3; ++q) u[q] = (float)(cell[q] - rc[q]) + (f[q] - s.rest_r[3 * sidx + q]);
@@ -749,10 +816,11 @@ __global__ void k_surface_finish(const unsigned long long* __restrict__ acc, int
 // instantiations, seen by both the device and the host compilation pass.
 #define IMPM_TILE_KERNELS(X, Y, Z, N)                                                             \
     template __global__ void k_p2g<Tile<X, Y, Z, N>>(BatchMap, int);                              \
-    template __global__ void k_grid<Tile<X, Y, Z, N>, false>(BatchMap, int, int, int);            \
-    template __global__ void k_grid<Tile<X, Y, Z, N>, true>(BatchMap, int, int, int);             \
-    template __global__ void k_g2p2g<Tile<X, Y, Z, N>, false>(BatchMap, int, int, int, int, int); \
-    template __global__ void k_g2p2g<Tile<X, Y, Z, N>, true>(BatchMap, int, int, int, int, int);
+    template __global__ void k_grid<Tile<X, Y, Z, N>, false>(BatchMap, int, int, int, int);       \
+    template __global__ void k_grid<Tile<X, Y, Z, N>, true>(BatchMap, int, int, int, int);        \
+    template __global__ void k_g2p2g<Tile<X, Y, Z, N>, false>(BatchMap, int, int, int, int, int, int); \
+    template __global__ void k_g2p2g<Tile<X, Y, Z, N>, true>(BatchMap, int, int, int, int, int, int); \
+    template __global__ void k_extra_passes<Tile<X, Y, Z, N>>(BatchMap, int, int, int, int, int, int, int);
 IMPM_TILE_KERNELS(8, 8, 2, 256)
 IMPM_TILE_KERNELS(8, 8, 2, 512)
 IMPM_TILE_KERNELS(4, 8, 4, 256)
@@ -777,21 +845,44 @@ struct TileLaunch {
     static void grid(const BatchMap& m, int node_blocks, int sbin, int step, int pass, bool extra,
                      hipStream_t st) {
         if (extra)
-            hipLaunchKernelGGL((k_grid<TL, true>), dim3(node_blocks), dim3(kBlock), 0, st, m, sbin, step, pass);
+            hipLaunchKernelGGL((k_grid<TL, true>), dim3(std::min(node_blocks, kExtraBlocks)), dim3(kBlock), 0, st,
+                               m, node_blocks, sbin, step, pass);
         else
-            hipLaunchKernelGGL((k_grid<TL, false>), dim3(node_blocks), dim3(kBlock), 0, st, m, sbin, step, pass);
+            hipLaunchKernelGGL((k_grid<TL, false>), dim3(node_blocks), dim3(kBlock), 0, st, m, node_blocks, sbin,
+                               step, pass);
     }
     static void g2p2g(const BatchMap& m, int tile_blocks, int cur, int step, int par, int pass, int store_vc,
                       bool extra, hipStream_t st) {
         if (extra)
-            hipLaunchKernelGGL((k_g2p2g<TL, true>), dim3(tile_blocks), dim3(NB), TL::LDS_G2P2G, st, m, cur, step,
-                               par, pass, store_vc);
+            hipLaunchKernelGGL((k_g2p2g<TL, true>), dim3(std::min(tile_blocks, kExtraBlocks)), dim3(NB),
+                               TL::LDS_G2P2G, st, m, tile_blocks, cur, step, par, pass, store_vc);
         else
-            hipLaunchKernelGGL((k_g2p2g<TL, false>), dim3(tile_blocks), dim3(NB), TL::LDS_G2P2G, st, m, cur, step,
-                               par, pass, store_vc);
+            hipLaunchKernelGGL((k_g2p2g<TL, false>), dim3(tile_blocks), dim3(NB), TL::LDS_G2P2G, st, m, tile_blocks,
+                               cur, step, par, pass, store_vc);
+    }
+    static hipError_t extra(const BatchMap& m, int tile_blocks, int node_blocks, int cur, int step, int par,
+                            int npass, int store_vc, hipStream_t st) {
+        static int max_blocks = 0;    // resident blocks of this kernel on the device
+        if (max_blocks == 0) {
+            int dev = 0, cus = 0, per = 0;
+            hipError_t e = hipGetDevice(&dev);
+            if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+            if (e == hipSuccess)
+                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_extra_passes<TL>, NB, TL::LDS_G2P2G);
+            if (e != hipSuccess) return e;
+            max_blocks = per * cus;
+        }
+        if (max_blocks < 1) return hipErrorCooperativeLaunchTooLarge;
+        BatchMap mm = m;
+        int a_tiles = tile_blocks, a_nodes = node_blocks, a_cur = cur, a_step = step, a_par = par, a_np = npass,
+            a_st = store_vc;
+        void* args[] = {&mm, &a_tiles, &a_nodes, &a_cur, &a_step, &a_par, &a_np, &a_st};
+        const int grid = std::min(max_blocks, std::max(tile_blocks, node_blocks));
+        return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_extra_passes<TL>), dim3(grid), dim3(NB),
+                                          args, (unsigned)TL::LDS_G2P2G, st);
     }
     static constexpr TileOps ops() {
-        return TileOps{{TX, TY, TZ}, NB, TL::PVOL, TL::LDS_G2P2G, &p2g, &grid, &g2p2g};
+        return TileOps{{TX, TY, TZ}, NB, TL::PVOL, TL::LDS_G2P2G, &p2g, &grid, &g2p2g, &extra};
     }
 };
 
@@ -802,6 +893,7 @@ const TileOps kTileOps[] = {
     TileLaunch<4, 8, 2, 256>::ops(), TileLaunch<8, 8, 8, 512>::ops(),
 };
 const int kNumTileOps = sizeof(kTileOps) / sizeof(kTileOps[0]);
+
 #endif
 
 }  // namespace impm
