@@ -62,7 +62,8 @@ struct ConvArgs {
 // Source pixel of row pixel (n, y, x) for tap (ty, tx), or -1 (zero padding).
 //  forward:   input position s*y + t - 1 (of the 2x upsampled source if up)
 //  transpose: output position p with s*p + t - 1 = y (data gradient)
-__device__ __forceinline__ long long gather(const ConvArgs& a, int n, int y, int x, int ty, int tx) {
+// Indices are 32-bit: sur_create keeps every tensor below 2^31 elements.
+__device__ __forceinline__ int gather(const ConvArgs& a, int n, int y, int x, int ty, int tx) {
     int sy, sx;
     if (!a.transpose) {
         const int yy = y * a.stride + ty - 1, xx = x * a.stride + tx - 1;
@@ -82,7 +83,7 @@ __device__ __forceinline__ long long gather(const ConvArgs& a, int n, int y, int
         sy = yy;
         sx = xx;
     }
-    return ((long long)n * a.Hs + sy) * a.Ws + sx;
+    return (n * a.Hs + sy) * a.Ws + sx;
 }
 
 // Block = 4 waves laid out WVM x WVN; a wave owns WMT x WNT MFMA tiles of 16 x 16.
@@ -92,19 +93,20 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave % WVM, wn = wave / WVM;
     const int r = lane & 15, kq = lane >> 4;
-    const long long M = (long long)a.N * a.Hm * a.Wm;
-    const long long m0 = (long long)blockIdx.x * BM + wm * WMT * 16;
+    const int M = a.N * a.Hm * a.Wm;
+    const int m0 = blockIdx.x * BM + wm * WMT * 16;
     const int n0 = blockIdx.y * BN + wn * WNT * 16;
     int pn[WMT], py[WMT], px[WMT];
     bool pv[WMT];
 #pragma unroll
     for (int i = 0; i < WMT; ++i) {
-        const long long m = m0 + i * 16 + r;
+        const int m = m0 + i * 16 + r;
         pv[i] = m < M;
-        const long long mm = pv[i] ? m : 0;
-        px[i] = (int)(mm % a.Wm);
-        py[i] = (int)((mm / a.Wm) % a.Hm);
-        pn[i] = (int)(mm / ((long long)a.Wm * a.Hm));
+        const unsigned mm = pv[i] ? (unsigned)m : 0u;
+        const unsigned row = mm / (unsigned)a.Wm;
+        px[i] = (int)(mm - row * (unsigned)a.Wm);
+        pn[i] = (int)(row / (unsigned)a.Hm);
+        py[i] = (int)(row - (unsigned)pn[i] * (unsigned)a.Hm);
     }
     f32x4 acc[WMT][WNT];
 #pragma unroll
@@ -117,7 +119,7 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
         const uint16_t* sp[WMT];
 #pragma unroll
         for (int i = 0; i < WMT; ++i) {
-            const long long q = pv[i] ? gather(a, pn[i], py[i], px[i], ty, tx) : -1;
+            const int q = pv[i] ? gather(a, pn[i], py[i], px[i], ty, tx) : -1;
             sp[i] = q >= 0 ? a.src + q * a.Ka + kq * 8 : nullptr;
         }
         const uint16_t* wp[WNT];
@@ -143,10 +145,10 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
         for (int j = 0; j < WNT; ++j)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const long long m = m0 + i * 16 + kq * 4 + e;
+                const int m = m0 + i * 16 + kq * 4 + e;
                 if (m >= M) continue;
                 const int n = n0 + j * 16 + r;
-                const size_t o = (size_t)m * a.Nn + n;
+                const int o = m * a.Nn + n;
                 float v = acc[i][j][e];
                 if (a.epi == EPI_FWD) {
                     v += a.bias[n];
@@ -161,14 +163,147 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
             }
 }
 
+// Stride-1 convolutions without upsampling (forward, or the data gradient with
+// the transposed weights), staged through LDS.  A block owns a 16 x 16 pixel
+// tile of one image and 32 output columns; per 32-channel chunk it stages the
+// tile's 18 x 18 input patch (zero padded) and the 9 taps x 32 channels of its
+// 32 weight columns with all loads in flight at once, then runs the 9 taps
+// from LDS.  Wave w owns image rows 4w..4w+3 of the tile; an MFMA row block is
+// 16 consecutive pixels of one row.
+//   HALF = 0: stride 1, same resolution (18 x 18 patch);
+//   HALF = 1: forward convolution of the 2x upsampled source: tap positions
+//             y + t - 1 read source pixel (y + t - 1) >> 1 (10 x 10 patch);
+//   HALF = 2: data gradient of a stride-2 convolution: position y + 1 - t is
+//             a source pixel (y + 1 - t) / 2 only when even (10 x 10 patch).
+// Positions outside the source read the patch's zero border.
+constexpr int LDS_TILE = 16;                       // tile side (pixels)
+constexpr int LDS_PATCH = LDS_TILE + 2;            // patch side
+constexpr int LDS_BPITCH = 9 * 32 + 8;             // weight column pitch (elements)
+
+template <int HALF>
+__global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a) {
+    __shared__ __attribute__((aligned(16))) uint16_t sP[LDS_PATCH * LDS_PATCH * 32];
+    __shared__ __attribute__((aligned(16))) uint16_t sW[32 * LDS_BPITCH];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane & 15, kq = lane >> 4;
+    const int tiles_x = (a.Wm + LDS_TILE - 1) / LDS_TILE, tiles_y = (a.Hm + LDS_TILE - 1) / LDS_TILE;
+    const int bx = blockIdx.x % tiles_x, rest = blockIdx.x / tiles_x;
+    const int by = rest % tiles_y, n = rest / tiles_y;
+    const int x0 = bx * LDS_TILE, y0 = by * LDS_TILE;
+    const int n0 = blockIdx.y * 32;
+    // patch origin and side in source pixels
+    const int py0 = HALF ? (y0 - 1) >> 1 : y0 - 1, px0 = HALF ? (x0 - 1) >> 1 : x0 - 1;
+    constexpr int SIDE = HALF ? LDS_TILE / 2 + 2 : LDS_PATCH;
+    f32x4 acc[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    constexpr int PV = SIDE * SIDE * 4;            // 16-byte vectors of a patch chunk
+    constexpr int WV = 32 * 9 * 4;                 // 16-byte vectors of a weight chunk
+    constexpr int PPT = (PV + 255) / 256, WPT = (WV + 255) / 256;
+    for (int c0 = 0; c0 < a.Ka; c0 += 32) {
+        uint4 pv[PPT], wv[WPT];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int v = threadIdx.x + k * 256;
+            pv[k] = make_uint4(0, 0, 0, 0);
+            if (v < PV) {
+                const int pix = v >> 2, ch = (v & 3) * 8;
+                const int y = py0 + pix / SIDE, x = px0 + pix % SIDE;
+                if (y >= 0 && y < a.Hs && x >= 0 && x < a.Ws)
+                    pv[k] = *reinterpret_cast<const uint4*>(a.src + ((n * a.Hs + y) * a.Ws + x) * a.Ka + c0 + ch);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < WPT; ++k) {
+            const int v = threadIdx.x + k * 256;
+            wv[k] = make_uint4(0, 0, 0, 0);
+            if (v < WV) {
+                const int col = v / 36, t = (v / 4) % 9, ch = (v & 3) * 8;
+                wv[k] = *reinterpret_cast<const uint4*>(a.wt + ((size_t)(n0 + col) * 9 + t) * a.Ka + c0 + ch);
+            }
+        }
+        __syncthreads();                               // the previous chunk's reads are done
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int v = threadIdx.x + k * 256;
+            if (v < PV) reinterpret_cast<uint4*>(sP)[v] = pv[k];
+        }
+#pragma unroll
+        for (int k = 0; k < WPT; ++k) {
+            const int v = threadIdx.x + k * 256;
+            if (v < WV) {
+                const int col = v / 36, t = (v / 4) % 9, ch = (v & 3) * 8;
+                *reinterpret_cast<uint4*>(sW + col * LDS_BPITCH + t * 32 + ch) = wv[k];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int ty = t / 3, tx = t % 3;
+            bf16x8 av[4], bv[2];
+            if (HALF == 0) {
+                const int oy = a.transpose ? 2 - ty : ty, ox = a.transpose ? 2 - tx : tx;
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    av[i] = load8(sP + (((wave * 4 + i + oy) * LDS_PATCH) + r + ox) * 32 + kq * 8);
+            } else {
+                const int xx = HALF == 1 ? x0 + r + tx - 1 : x0 + r + 1 - tx;
+                const int lx = (xx >> 1) - px0;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int yy = HALF == 1 ? y0 + wave * 4 + i + ty - 1 : y0 + wave * 4 + i + 1 - ty;
+                    const bool ok = HALF == 1 || ((yy | xx) & 1) == 0;
+                    av[i] = ok ? load8(sP + (((yy >> 1) - py0) * SIDE + lx) * 32 + kq * 8) : zero8();
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j) bv[j] = load8(sW + (j * 16 + r) * LDS_BPITCH + t * 32 + kq * 8);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+        }
+    }
+    // D: lane holds rows 4*kq + e (pixels x0 + 4 kq + e) of column r of each tile
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int y = y0 + wave * 4 + i;
+        if (y >= a.Hm) continue;
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int x = x0 + kq * 4 + e;
+                if (x >= a.Wm) continue;
+                const int nn = n0 + j * 16 + r;
+                const int o = ((n * a.Hm + y) * a.Wm + x) * a.Nn + nn;
+                float v = acc[i][j][e];
+                if (a.epi == EPI_FWD) {
+                    v += a.bias[nn];
+                    if (a.add) v += bf2f(a.add[o]);
+                    a.out[o] = f2bf(fmaxf(v, 0.f));
+                } else if (a.epi == EPI_DX_MASK) {
+                    if (a.add) v += bf2f(a.add[o]);
+                    a.out[o] = f2bf(bf2f(a.mask[o]) > 0.f ? v : 0.f);
+                } else {
+                    a.outf[o] = v;
+                }
+            }
+    }
+}
+
 // ------------------------------------------------------------------ weight gradient
 
 struct DwArgs {
     const uint16_t* dz;     // [N*Ho*Wo][Cout]
     const uint16_t* src;    // layer input, NHWC [N][Hs][Ws][Cin] (low resolution if up)
     int N, Ho, Wo, Hs, Ws, Cout, Cin, stride, up;
-    long long ppb;          // pixels per block
+    int ppb;                // pixels per block
     float* dw;              // [Cout][9][Cin], accumulated
+    float* db;              // [Cout] bias gradient (column sums of dZ), accumulated; may be null
 };
 
 // dW[co][t][ci] = sum_p dZ[p][co] X(p, t)[ci].  Block: one tap, a TCO x TCI
@@ -183,9 +318,9 @@ __global__ __launch_bounds__(256) void k_conv_dw(DwArgs d) {
     const int t = blockIdx.z, ty = t / 3, tx = t % 3;
     const int nco = d.Cout / TCO;
     const int co0 = (blockIdx.y % nco) * TCO, ci0 = (blockIdx.y / nco) * TCI;
-    const long long P = (long long)d.N * d.Ho * d.Wo;
-    const long long pbeg = (long long)blockIdx.x * d.ppb;
-    const long long pend = std::min(P, pbeg + d.ppb);
+    const int P = d.N * d.Ho * d.Wo;
+    const int pbeg = blockIdx.x * d.ppb;
+    const int pend = min(P, pbeg + d.ppb);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wco = wave & 1, wci = wave >> 1;
     const int r = lane & 15, kq = lane >> 4;
@@ -195,11 +330,14 @@ __global__ __launch_bounds__(256) void k_conv_dw(DwArgs d) {
 #pragma unroll
         for (int j = 0; j < NJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int he = d.up ? 2 * d.Hs : d.Hs, we = d.up ? 2 * d.Ws : d.Ws;
+    // the tap-0 blocks of the first input-channel tile also sum dZ per column
+    const bool bias = d.db && t == 0 && ci0 == 0;
+    float bsum = 0.f;
 
-    for (long long pb = pbeg; pb < pend; pb += KP) {
+    for (int pb = pbeg; pb < pend; pb += KP) {
         for (int c = threadIdx.x; c < KP * (TCO / 8); c += 256) {
             const int pix = c / (TCO / 8), ch = (c % (TCO / 8)) * 8;
-            const long long p = pb + pix;
+            const int p = pb + pix;
             uint4 v = make_uint4(0, 0, 0, 0);
             if (p < pend) v = *reinterpret_cast<const uint4*>(d.dz + p * d.Cout + co0 + ch);
             const uint16_t* h = reinterpret_cast<const uint16_t*>(&v);
@@ -208,15 +346,17 @@ __global__ __launch_bounds__(256) void k_conv_dw(DwArgs d) {
         }
         for (int c = threadIdx.x; c < KP * (TCI / 8); c += 256) {
             const int pix = c / (TCI / 8), ch = (c % (TCI / 8)) * 8;
-            const long long p = pb + pix;
+            const int p = pb + pix;
             uint4 v = make_uint4(0, 0, 0, 0);
             if (p < pend) {
-                const int x = (int)(p % d.Wo), y = (int)((p / d.Wo) % d.Ho);
-                const int n = (int)(p / ((long long)d.Wo * d.Ho));
+                const unsigned row = (unsigned)p / (unsigned)d.Wo;
+                const int x = p - (int)row * d.Wo;
+                const int n = (int)(row / (unsigned)d.Ho);
+                const int y = (int)row - n * d.Ho;
                 const int yy = y * d.stride + ty - 1, xx = x * d.stride + tx - 1;
                 if (yy >= 0 && yy < he && xx >= 0 && xx < we) {
                     const int sy = d.up ? yy >> 1 : yy, sx = d.up ? xx >> 1 : xx;
-                    const long long q = ((long long)n * d.Hs + sy) * d.Ws + sx;
+                    const int q = (n * d.Hs + sy) * d.Ws + sx;
                     v = *reinterpret_cast<const uint4*>(d.src + q * d.Cin + ci0 + ch);
                 }
             }
@@ -225,6 +365,8 @@ __global__ __launch_bounds__(256) void k_conv_dw(DwArgs d) {
             for (int e = 0; e < 8; ++e) sB[(ch + e) * PITCH + pix] = h[e];
         }
         __syncthreads();
+        if (bias && threadIdx.x < TCO)
+            for (int k = 0; k < KP; ++k) bsum += bf2f(sA[threadIdx.x * PITCH + k]);   // rows past the range are 0
 #pragma unroll
         for (int ks = 0; ks < KP / 32; ++ks) {
             bf16x8 av[MI], bv[NJ];
@@ -252,39 +394,27 @@ __global__ __launch_bounds__(256) void k_conv_dw(DwArgs d) {
                 const int ci = ci0 + wci * (TCI / 2) + j * 16 + r;
                 atomicAdd(&d.dw[((size_t)co * 9 + t) * d.Cin + ci], acc[i][j][e]);
             }
+    if (bias && threadIdx.x < TCO) atomicAdd(&d.db[co0 + threadIdx.x], bsum);
 }
 
 // ------------------------------------------------------------------ small kernels
-
-// Bias gradient: column sums of dZ [P][C] (C divides 256).
-__global__ __launch_bounds__(256) void k_colsum(const uint16_t* dz, long long P, int C, long long ppb, float* db) {
-    __shared__ float sh[256];
-    const int c = threadIdx.x % C, g = threadIdx.x / C, G = 256 / C;
-    const long long p0 = (long long)blockIdx.x * ppb, p1 = std::min(P, p0 + ppb);
-    float s = 0.f;
-    for (long long p = p0 + g; p < p1; p += G) s += bf2f(dz[p * C + c]);
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    if (g == 0) {
-        for (int k = 1; k < G; ++k) s += sh[k * C + c];
-        atomicAdd(&db[c], s);
-    }
-}
 
 // Data gradient through the 2x upsampling: sum the four fine pixels, add the
 // skip gradient, pass where the activation is positive, round to BF16.
 __global__ __launch_bounds__(256) void k_pool_mask(const float* dxu, int N, int H, int W, int C,
                                                    const uint16_t* add, const uint16_t* mask, uint16_t* out) {
-    const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
-    const long long total = (long long)N * H * W * C;
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    const int total = N * H * W * C;
     if (idx >= total) return;
-    const int c = (int)(idx % C);
-    const long long pix = idx / C;
-    const int x = (int)(pix % W), y = (int)((pix / W) % H);
-    const int n = (int)(pix / ((long long)W * H));
+    const unsigned pix = (unsigned)idx / (unsigned)C;
+    const int c = idx - (int)pix * C;
+    const unsigned row = pix / (unsigned)W;
+    const int x = (int)(pix - row * (unsigned)W);
+    const int n = (int)(row / (unsigned)H);
+    const int y = (int)row - n * H;
     const int W2 = 2 * W;
-    const long long b = (((long long)n * 2 * H + 2 * y) * W2 + 2 * x) * C + c;
-    float v = (dxu[b] + dxu[b + C]) + (dxu[b + (long long)W2 * C] + dxu[b + (long long)W2 * C + C]);
+    const int b = ((n * 2 * H + 2 * y) * W2 + 2 * x) * C + c;
+    float v = (dxu[b] + dxu[b + C]) + (dxu[b + W2 * C] + dxu[b + W2 * C + C]);
     if (add) v += bf2f(add[idx]);
     out[idx] = f2bf(bf2f(mask[idx]) > 0.f ? v : 0.f);
 }
@@ -292,10 +422,10 @@ __global__ __launch_bounds__(256) void k_pool_mask(const float* dxu, int N, int 
 // Network input: depth (mm, clipped to [-3, 3]), six pose-change values,
 // previous displacement (mm), zero padding to 32 channels; BF16.
 __global__ __launch_bounds__(256) void k_assemble(const float* depth, const float* pose, const float* prev,
-                                                  long long P, int HW, uint16_t* X) {
-    const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+                                                  int P, int HW, uint16_t* X) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
     if (p >= P) return;
-    const long long n = p / HW;
+    const int n = (int)((unsigned)p / (unsigned)HW);
     uint16_t v[32];
 #pragma unroll
     for (int k = 0; k < 32; ++k) v[k] = 0;
@@ -501,6 +631,19 @@ static unsigned blocks_for(long long n) { return (unsigned)((n + 255) / 256); }
 
 static void launch_conv(const ConvArgs& a, hipStream_t st) {
     const long long M = (long long)a.N * a.Hm * a.Wm;
+    const int tiles = ((a.Wm + LDS_TILE - 1) / LDS_TILE) * ((a.Hm + LDS_TILE - 1) / LDS_TILE) * a.N;
+    if (a.stride == 1 && !a.up) {
+        hipLaunchKernelGGL(k_conv_lds<0>, dim3((unsigned)tiles, a.Nn / 32), dim3(256), 0, st, a);
+        return;
+    }
+    if (a.up && !a.transpose && a.stride == 1) {
+        hipLaunchKernelGGL(k_conv_lds<1>, dim3((unsigned)tiles, a.Nn / 32), dim3(256), 0, st, a);
+        return;
+    }
+    if (a.transpose && a.stride == 2 && !a.up) {
+        hipLaunchKernelGGL(k_conv_lds<2>, dim3((unsigned)tiles, a.Nn / 32), dim3(256), 0, st, a);
+        return;
+    }
     if (a.Nn == 32) {
         hipLaunchKernelGGL((k_conv<4, 2, 4, 1>), dim3((unsigned)((M + 255) / 256), 1), dim3(256), 0, st, a);
     } else if (a.Nn == 64) {
@@ -519,17 +662,12 @@ static void launch_dw(const DwArgs& d, hipStream_t st) {
     ppb = std::max(64LL, (ppb + 63) / 64 * 64);
     splits = (P + ppb - 1) / ppb;
     DwArgs a = d;
-    a.ppb = ppb;
+    a.ppb = (int)ppb;
     const dim3 grid((unsigned)splits, (unsigned)tiles, 9);
     if (tco == 64 && tci == 64) hipLaunchKernelGGL((k_conv_dw<64, 64>), grid, dim3(256), 0, st, a);
     else if (tco == 64) hipLaunchKernelGGL((k_conv_dw<64, 32>), grid, dim3(256), 0, st, a);
     else if (tci == 64) hipLaunchKernelGGL((k_conv_dw<32, 64>), grid, dim3(256), 0, st, a);
     else hipLaunchKernelGGL((k_conv_dw<32, 32>), grid, dim3(256), 0, st, a);
-}
-
-static void launch_colsum(const uint16_t* dz, long long P, int C, float* db, hipStream_t st) {
-    const long long ppb = std::max(256LL, (P + 1023) / 1024);
-    hipLaunchKernelGGL(k_colsum, dim3((unsigned)((P + ppb - 1) / ppb)), dim3(256), 0, st, dz, P, C, ppb, db);
 }
 
 static void launch_head(sur_t* s, bool train, int n, const float* prev, const float* tgt, float* out) {
@@ -577,7 +715,8 @@ static void forward(sur_t* s, int n, const float* depth, const float* pose, cons
     const int H = s->P.H, W = s->P.W;
     s->n_last = n;
     const long long P = (long long)n * H * W;
-    hipLaunchKernelGGL(k_assemble, dim3(blocks_for(P)), dim3(256), 0, s->stream, depth, pose, prev, P, H * W, s->x0);
+    hipLaunchKernelGGL(k_assemble, dim3(blocks_for(P)), dim3(256), 0, s->stream, depth, pose, prev, (int)P, H * W,
+                       s->x0);
     for (int li = 0; li < 14; ++li) {
         const Layer& l = s->L[li];
         ConvArgs a{};
@@ -600,15 +739,14 @@ static void backward(sur_t* s, int n, const float* prev, const float* tgt) {
     launch_head(s, true, n, prev, tgt, nullptr);
     for (int li = 13; li >= 0; --li) {
         const Layer& l = s->L[li];
-        const long long P = (long long)n * l.hout * l.wout;
         DwArgs d{};
         d.dz = s->dz[li];
         d.src = li == 0 ? s->x0 : s->act[li - 1];
         d.N = n; d.Ho = l.hout; d.Wo = l.wout; d.Hs = l.hin; d.Ws = l.win;
         d.Cout = l.cout; d.Cin = l.cin_pad; d.stride = l.stride; d.up = l.up;
         d.dw = s->grad + l.w_off;
+        d.db = s->grad + l.b_off;
         launch_dw(d, s->stream);
-        launch_colsum(s->dz[li], P, l.cout, s->grad + l.b_off, s->stream);
         if (li == 0) break;
         const int prevl = li - 1;
         const uint16_t* sg = s->consumer_of[prevl] >= 0 ? s->dz[s->consumer_of[prevl]] : nullptr;
@@ -723,6 +861,11 @@ int sur_create(const sur_params* p, void* hip_stream, sur_t** out) {
     *out = nullptr;
     if (p->H < 8 || p->W < 8 || p->H % 8 || p->W % 8 || p->H > 4096 || p->W > 4096 || p->max_batch < 1) {
         std::fprintf(stderr, "sur_create: H, W must be multiples of 8 in [8, 4096], max_batch >= 1\n");
+        return SUR_EINVAL;
+    }
+    // the kernels index every tensor with 32-bit integers
+    if ((long long)p->max_batch * p->H * p->W * 256 >= (1LL << 31)) {
+        std::fprintf(stderr, "sur_create: max_batch * H * W * 256 must stay below 2^31\n");
         return SUR_EINVAL;
     }
     // the tile shapes of the convolution kernels cover 32, 64, 128 and 256 channels
