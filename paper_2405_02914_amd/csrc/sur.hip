@@ -441,88 +441,106 @@ __global__ __launch_bounds__(256) void k_assemble(const float* depth, const floa
 }
 
 // 1x1 head: next = prev + a13 Wh^T + bh.  Training also forms the loss
-// gradient 2 (next - target) / count, the head's weight and bias gradients,
-// and the BF16 pre-activation gradient of a13 (masked by a13 > 0).
+// gradient 2 (next - target) / count, the BF16 pre-activation gradient of a13
+// (masked by a13 > 0), the head's bias gradient and loss (wave sums), and its
+// weight gradient: per 256-pixel chunk the pixels' loss gradients go to LDS
+// and thread (k, group) accumulates dout[p][c] a13[p][k] over a share of them.
 template <int C0, bool TRAIN>
 __global__ __launch_bounds__(256) void k_head(const uint16_t* a13, const float* whf, const float* bh,
                                               const float* prev, const float* tgt, long long P, float two_over_count,
                                               float* out, uint16_t* dz13, float* gwh, float* gbh, float* loss) {
+    constexpr int G = 256 / C0;              // pixel groups of the weight-gradient phase
     __shared__ float sw[3 * C0 + 3];
-    __shared__ float red[4][3 * C0 + 4];
-    for (int k = threadIdx.x; k < 3 * C0; k += 256) sw[k] = whf[k];
-    if (threadIdx.x < 3) sw[3 * C0 + threadIdx.x] = bh[threadIdx.x];
+    __shared__ float sd[256 * 3];
+    __shared__ float red[256];
+    const int tid = threadIdx.x;
+    for (int k = tid; k < 3 * C0; k += 256) sw[k] = whf[k];
+    if (tid < 3) sw[3 * C0 + tid] = bh[tid];
     __syncthreads();
-    float gw[TRAIN ? 3 * C0 : 1], gb[3] = {0.f, 0.f, 0.f}, ls = 0.f;
-    if (TRAIN)
-        for (int k = 0; k < 3 * C0; ++k) gw[k] = 0.f;
-    for (long long p = (long long)blockIdx.x * 256 + threadIdx.x; p < P; p += (long long)gridDim.x * 256) {
-        float a[C0];
-        const uint4* s = reinterpret_cast<const uint4*>(a13 + p * C0);
+    const int kk = tid % C0, grp = tid / C0;
+    float gwa[3] = {0.f, 0.f, 0.f}, gb[3] = {0.f, 0.f, 0.f}, ls = 0.f;
+    for (long long base = (long long)blockIdx.x * 256; base < P; base += (long long)gridDim.x * 256) {
+        const long long p = base + tid;
+        float dout[3] = {0.f, 0.f, 0.f};
+        if (p < P) {
+            float a[C0];
+            const uint4* s = reinterpret_cast<const uint4*>(a13 + p * C0);
 #pragma unroll
-        for (int q = 0; q < C0 / 8; ++q) {
-            const uint4 v = s[q];
-            const uint16_t* h = reinterpret_cast<const uint16_t*>(&v);
+            for (int q = 0; q < C0 / 8; ++q) {
+                const uint4 v = s[q];
+                const uint16_t* h = reinterpret_cast<const uint16_t*>(&v);
 #pragma unroll
-            for (int e = 0; e < 8; ++e) a[q * 8 + e] = bf2f(h[e]);
-        }
-        float hd[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            float acc = 0.f;
-#pragma unroll
-            for (int k = 0; k < C0; ++k) acc += a[k] * sw[c * C0 + k];
-            hd[c] = prev[p * 3 + c] + (acc + sw[3 * C0 + c]);
-        }
-        if (!TRAIN) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) out[p * 3 + c] = hd[c];
-        } else {
-            float dout[3];
+                for (int e = 0; e < 8; ++e) a[q * 8 + e] = bf2f(h[e]);
+            }
+            float hd[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const float df = hd[c] - tgt[p * 3 + c];
-                ls += df * df;
-                dout[c] = two_over_count * df;
-                gb[c] += dout[c];
+                float acc = 0.f;
+#pragma unroll
+                for (int k = 0; k < C0; ++k) acc += a[k] * sw[c * C0 + k];
+                hd[c] = prev[p * 3 + c] + (acc + sw[3 * C0 + c]);
             }
-            uint16_t dz[C0];
+            if (!TRAIN) {
 #pragma unroll
-            for (int k = 0; k < C0; ++k) {
-                const float g = dout[0] * sw[k] + dout[1] * sw[C0 + k] + dout[2] * sw[2 * C0 + k];
-                dz[k] = f2bf(a[k] > 0.f ? g : 0.f);
+                for (int c = 0; c < 3; ++c) out[p * 3 + c] = hd[c];
+            } else {
 #pragma unroll
-                for (int c = 0; c < 3; ++c) gw[c * C0 + k] += dout[c] * a[k];
+                for (int c = 0; c < 3; ++c) {
+                    const float df = hd[c] - tgt[p * 3 + c];
+                    ls += df * df;
+                    dout[c] = two_over_count * df;
+                    gb[c] += dout[c];
+                }
+                uint16_t dz[C0];
+#pragma unroll
+                for (int k = 0; k < C0; ++k) {
+                    const float g = dout[0] * sw[k] + dout[1] * sw[C0 + k] + dout[2] * sw[2 * C0 + k];
+                    dz[k] = f2bf(a[k] > 0.f ? g : 0.f);
+                }
+                uint4* o = reinterpret_cast<uint4*>(dz13 + p * C0);
+#pragma unroll
+                for (int q = 0; q < C0 / 8; ++q) o[q] = reinterpret_cast<const uint4*>(dz)[q];
             }
-            uint4* o = reinterpret_cast<uint4*>(dz13 + p * C0);
-#pragma unroll
-            for (int q = 0; q < C0 / 8; ++q) o[q] = reinterpret_cast<const uint4*>(dz)[q];
         }
+        if (!TRAIN) continue;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sd[tid * 3 + c] = dout[c];
+        __syncthreads();
+        for (int q = grp; q < 256; q += G) {
+            const long long pq = base + q;
+            if (pq >= P) break;
+            const float av = bf2f(a13[pq * C0 + kk]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) gwa[c] += sd[q * 3 + c] * av;
+        }
+        __syncthreads();
     }
     if (!TRAIN) return;
-    // reduce the per-thread sums: wave shuffles, then the four waves through LDS
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    auto wsum = [&](float v) {
+    // weight gradient: sum the groups through LDS
+    for (int c = 0; c < 3; ++c) {
+        red[tid] = gwa[c];
+        __syncthreads();
+        if (tid < C0) {
+            float v = 0.f;
+            for (int g2 = 0; g2 < G; ++g2) v += red[g2 * C0 + tid];
+            atomicAdd(&gwh[c * C0 + tid], v);
+        }
+        __syncthreads();
+    }
+    // bias gradient and loss: wave shuffles, then the four waves
+    const int lane = tid & 63, wave = tid >> 6;
+    float vals[4] = {gb[0], gb[1], gb[2], ls};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        float v = vals[q];
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-        return v;
-    };
-    for (int k = 0; k < 3 * C0; ++k) {
-        const float v = wsum(gw[k]);
-        if (lane == 0) red[wave][k] = v;
-    }
-    for (int c = 0; c < 3; ++c) {
-        const float v = wsum(gb[c]);
-        if (lane == 0) red[wave][3 * C0 + c] = v;
-    }
-    {
-        const float v = wsum(ls);
-        if (lane == 0) red[wave][3 * C0 + 3] = v;
+        if (lane == 0) red[wave * 4 + q] = v;
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < 3 * C0 + 4; k += 256) {
-        const float v = (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]);
-        if (k < 3 * C0) atomicAdd(&gwh[k], v);
-        else if (k < 3 * C0 + 3) atomicAdd(&gbh[k - 3 * C0], v);
+    if (tid < 4) {
+        const float v = (red[tid] + red[4 + tid]) + (red[8 + tid] + red[12 + tid]);
+        if (tid < 3) atomicAdd(&gbh[tid], v);
         else atomicAdd(loss, v);
     }
 }
