@@ -1404,7 +1404,11 @@ int sim_batch_step(sim_batch_t* b, int32_t n_substeps) {
         L.n = (int)g.members.size();
         L.limit_slots = std::min(34, s0->P.rest_limit + 2);
         L.st = b->stream;
-        L.coop = !b->use_graph && coop_supported();                // eager launches only
+        // Per-pass launches for batches: their members usually do run passes after
+        // the first, and there the cooperative kernel's device-scope fences around
+        // each grid barrier cost more than the launches they save (an eager batch
+        // call took 2.6 times as long).
+        L.coop = false;
         sets.push_back(L);
     }
     if (!s0->pending) {

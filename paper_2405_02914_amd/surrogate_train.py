@@ -169,6 +169,34 @@ def inference_rate(net, data, stream, batch, reps=20):
     return batch * reps / dt, dt / reps
 
 
+def kernel_timing(batch=64, serve_batch=256, reps=20, stream=None):
+    """Training-step and inference times (ms) on seeded synthetic inputs of the
+    serving shape, without data generation: the short driver that kernel
+    profiles of the network run."""
+    import torch
+    st = stream or torch.cuda.Stream()
+    d, p, pv, tg = W.surrogate_batch(batch, RES, RES, seed=0)
+    d2, p2, pv2, _ = W.surrogate_batch(serve_batch, RES, RES, seed=1)
+    with torch.cuda.stream(st):
+        tr = [torch.from_numpy(a).cuda() for a in (d, p, pv, tg)]
+        inf = [torch.from_numpy(a).cuda() for a in (d2, p2, pv2)]
+        out = torch.empty_like(inf[2])
+    net = sur.Surrogate(RES, RES, max_batch=max(batch, serve_batch), stream=st.cuda_stream)
+    res = {}
+    for name, fn in (("train_ms", lambda: net.sur_train_step(*tr)), ("infer_ms", lambda: net.sur_infer(*inf, out=out))):
+        for _ in range(3):
+            fn()
+        st.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        st.synchronize()
+        res[name] = 1e3 * (time.perf_counter() - t0) / reps
+    net.close()
+    res.update(batch=batch, serve_batch=serve_batch, reps=reps)
+    return res
+
+
 def main():
     import torch
     ap = argparse.ArgumentParser()
@@ -181,8 +209,13 @@ def main():
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--out", default=None)
     ap.add_argument("--save", default=None)
+    ap.add_argument("--timing-only", action="store_true",
+                    help="time training steps and inference on synthetic inputs, no data generation")
     a = ap.parse_args()
     torch.cuda.set_device(0)
+    if a.timing_only:
+        print(json.dumps(kernel_timing(a.batch, a.serve_batch)), flush=True)
+        return
     st = torch.cuda.Stream()
     ptr, str_ = W.surrogate_trajectories(a.train, seed=1, n_substeps=a.substeps)
     pte, ste = W.surrogate_trajectories(a.test, seed=2, n_substeps=a.substeps)
