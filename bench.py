@@ -49,7 +49,7 @@ ALG_BYTES_PER_PARTICLE_PASS = 192.0 + 7.0
 # the counters' reading of a copy of known size (fetched bytes = 2.0 x
 # FETCH_SIZE, written = 1.0 x WRITE_SIZE); None whenever the kernel has changed
 # since the counters were taken.
-PMC_TRAFFIC_BYTES = (2.0 * 179372 + 320741) * 1024
+PMC_TRAFFIC_BYTES = (2.0 * 179396 + 320747) * 1024
 
 
 def parse():

@@ -47,6 +47,19 @@ struct DevState {
     float xe_f[2][3];
 };
 
+// Buffers reached through the argument table are generic pointers, and loads
+// and stores through them compile to flat instructions, which also count on the
+// LDS wait counter: every wait for an LDS read would then also wait for the
+// particle loads in flight.  The kernels cast them to the global address space.
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ gptr<T> glb(T* p) { return (gptr<T>)p; }
+// float4 is a class whose members take generic references, so its buffers are
+// reached as the plain 4-float vector type instead.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ gptr<f32x4> glb4(float4* p) { return (gptr<f32x4>)p; }
+
 struct KArgs {
     int nn[3];        // nodes per axis
     int T[3];         // tile size in cells
@@ -195,7 +208,9 @@ __device__ __forceinline__ void polar_rotation_minus_identity(const float G[9], 
         cof[8] = Q[0] * Q[4] - Q[1] * Q[3];
         const float d = tr + (cof[0] + cof[4] + cof[8]) +
                         (Q[0] * cof[0] + Q[1] * cof[1] + Q[2] * cof[2]);
-        const float inv = 1.0f / (1.0f + d);
+        // hardware reciprocal (about 1 ulp): 1 + d stays near 1, and the
+        // iteration is self-correcting, so its error does not accumulate
+        const float inv = __builtin_amdgcn_rcpf(1.0f + d);
         float K[9];
         K[0] = tr - Q[0] + cof[0] - d; K[1] = -Q[3] + cof[1];      K[2] = -Q[6] + cof[2];
         K[3] = -Q[1] + cof[3];      K[4] = tr - Q[4] + cof[4] - d; K[5] = -Q[7] + cof[5];

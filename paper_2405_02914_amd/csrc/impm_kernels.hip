@@ -28,10 +28,10 @@ __device__ __forceinline__ void tile_coords(const KArgs& a, int t, int tc[3]) {
 
 // Node sums in LDS are 64-bit fixed point with 2^-32 resolution.  A contribution
 // y (already scaled by 2^32, which is exact) becomes round(y) through one FP64
-// add of the constant 1.5 * 2^52: the sum holds the rounded integer in its low
-// mantissa bits, and the constant's own bits are a multiple of 2^51, so they drop
-// out of the low 51 bits of the accumulated sum, which are sign-extended at the
-// flush (valid for |sum| < 2^18).  Integer adds make the node sums exact and
+// add of the constant 1.5 * 2^52, or one FMA when y is a product of two floats:
+// the sum holds the rounded integer in its low mantissa bits, and the constant's
+// own bits are a multiple of 2^51, so they drop out of the low 51 bits of the
+// accumulated sum, which are sign-extended at the flush (valid for |sum| < 2^18).  Integer adds make the node sums exact and
 // independent of order, and LDS integer atomics are several times faster than
 // LDS float atomics on this chip.
 constexpr float kFixScaleF = 4294967296.0f;         // 2^32
@@ -40,6 +40,11 @@ constexpr double kFixMagic = 6755399441055744.0;    // 1.5 * 2^52
 
 __device__ __forceinline__ unsigned long long to_fixed_scaled(float y, double magic) {
     return (unsigned long long)__double_as_longlong((double)y + magic);
+}
+// round(w * y) for a scaled weight w already widened to FP64: the product of two
+// floats is exact in FP64, so one FMA forms and rounds it.
+__device__ __forceinline__ unsigned long long to_fixed_product(double w, float y, double magic) {
+    return (unsigned long long)__double_as_longlong(fma(w, (double)y, magic));
 }
 __device__ __forceinline__ float from_fixed(unsigned long long a) {
     const long long v = ((long long)(a << 13)) >> 13;
@@ -133,11 +138,11 @@ __device__ __forceinline__ int p2g_particle(unsigned long long* acc, const int o
             unsigned long long* nd = row0 + c * TL::SZ + b * TL::SY;
 #pragma unroll
             for (int aa = 0; aa < 3; ++aa) {
-                const float wt = wx[aa] * wbc;
-                atomicAdd(nd + aa, to_fixed_scaled(wt, magic));
-                atomicAdd(nd + aa + TL::AVOL, to_fixed_scaled(wt * (ax[aa][0] + sy0), magic));
-                atomicAdd(nd + aa + 2 * TL::AVOL, to_fixed_scaled(wt * (ax[aa][1] + sy1), magic));
-                atomicAdd(nd + aa + 3 * TL::AVOL, to_fixed_scaled(wt * (ax[aa][2] + sy2), magic));
+                const double wt = (double)(wx[aa] * wbc);
+                atomicAdd(nd + aa, (unsigned long long)__double_as_longlong(wt + magic));
+                atomicAdd(nd + aa + TL::AVOL, to_fixed_product(wt, ax[aa][0] + sy0, magic));
+                atomicAdd(nd + aa + 2 * TL::AVOL, to_fixed_product(wt, ax[aa][1] + sy1, magic));
+                atomicAdd(nd + aa + 3 * TL::AVOL, to_fixed_product(wt, ax[aa][2] + sy2, magic));
             }
         }
     }
@@ -146,20 +151,20 @@ __device__ __forceinline__ int p2g_particle(unsigned long long* acc, const int o
 
 // Write a tile's fixed-point node sums to its scratch record as floats.
 template <class TL>
-__device__ __forceinline__ void flush_tile(const unsigned long long* acc, float4* dst) {
+__device__ __forceinline__ void flush_tile(const unsigned long long* acc, gptr<f32x4> dst) {
     for (int k = threadIdx.x; k < TL::PVOL; k += TL::NT) {
         const int x = k % TL::PX, y = (k / TL::PX) % TL::PY, z = k / (TL::PX * TL::PY);
         const int o = z * TL::SZ + y * TL::SY + x;
-        dst[k] = make_float4(from_fixed(acc[o]), from_fixed(acc[TL::AVOL + o]),
-                             from_fixed(acc[2 * TL::AVOL + o]), from_fixed(acc[3 * TL::AVOL + o]));
+        dst[k] = f32x4{from_fixed(acc[o]), from_fixed(acc[TL::AVOL + o]), from_fixed(acc[2 * TL::AVOL + o]),
+                       from_fixed(acc[3 * TL::AVOL + o])};
     }
 }
 
 __device__ __forceinline__ void load_particle(const KArgs& a, long long id, int cell[3],
                                               float f[3]) {
-    unpack_cell(a.cell[id], cell);
+    unpack_cell(glb(a.cell)[id], cell);
 #pragma unroll
-    for (int q = 0; q < 3; ++q) f[q] = a.soa[(size_t)(F0 + q) * a.n + id];
+    for (int q = 0; q < 3; ++q) f[q] = glb(a.soa)[(size_t)(F0 + q) * a.n + id];
 }
 
 __global__ void k_fill(float* p, long long n, float val) {
@@ -180,8 +185,8 @@ __global__ __launch_bounds__(TL::NT) void k_p2g(BatchMap m, int cur) {
         t -= m.tile_base[s];
     }
     const KArgs& a = m.args[s];
-    const uint32_t* __restrict__ order = a.order[cur];
-    const uint32_t* __restrict__ bstart = a.bstart[cur];
+    const gptr<const uint32_t> __restrict__ order = glb<const uint32_t>(a.order[cur]);
+    const gptr<const uint32_t> __restrict__ bstart = glb<const uint32_t>(a.bstart[cur]);
     const uint32_t s0 = bstart[t], cnt = bstart[t + 1] - s0;
     if (cnt == 0) return;
     int tc[3];
@@ -195,14 +200,14 @@ __global__ __launch_bounds__(TL::NT) void k_p2g(BatchMap m, int cur) {
         int cell[3];
         float f[3], v[3], C[9], G[9];
         load_particle(a, id, cell, f);
-        for (int q = 0; q < 3; ++q) v[q] = a.soa[(size_t)(V0 + q) * a.n + id];
-        for (int q = 0; q < 9; ++q) C[q] = a.soa[(size_t)(C0 + q) * a.n + id];
-        for (int q = 0; q < 9; ++q) G[q] = a.soa[(size_t)(G0 + q) * a.n + id];
+        for (int q = 0; q < 3; ++q) v[q] = glb(a.soa)[(size_t)(V0 + q) * a.n + id];
+        for (int q = 0; q < 9; ++q) C[q] = glb(a.soa)[(size_t)(C0 + q) * a.n + id];
+        for (int q = 0; q < 9; ++q) G[q] = glb(a.soa)[(size_t)(G0 + q) * a.n + id];
         err |= p2g_particle<TL>(acc, org, cell, f, v, C, G, true, a);
     }
     if (err) atomicOr(&a.st->error, err);
     __syncthreads();
-    flush_tile<TL>(acc, a.scratch + (size_t)t * TL::PVOL);
+    flush_tile<TL>(acc, glb4(a.scratch) + (size_t)t * TL::PVOL);
 }
 
 // Node kernel: sum the partials of the tiles whose P2G block covers the node
@@ -219,7 +224,7 @@ __device__ __forceinline__ void grid_block(const BatchMap& m, int gnb, int sbin,
     }
     const KArgs& a = m.args[s];
     if (flag_load(&a.st->finished[pass])) return;
-    const uint32_t* __restrict__ bstart = a.bstart[sbin];
+    const gptr<const uint32_t> __restrict__ bstart = glb<const uint32_t>(a.bstart[sbin]);
     const long long nid = nb * (long long)kBlock + threadIdx.x;
     const long long n_nodes = (long long)a.nn[0] * a.nn[1] * a.nn[2];
     if (nid >= n_nodes) return;
@@ -242,7 +247,7 @@ __device__ __forceinline__ void grid_block(const BatchMap& m, int gnb, int sbin,
                 const int t = (tz * a.NT[1] + ty) * a.NT[0] + tx;
                 if (bstart[t + 1] == bstart[t]) continue;
                 const int l0 = i - (tx * TL::T0 - 1), l1 = j - (ty * TL::T1 - 1), l2 = k - (tz * TL::T2 - 1);
-                const float4 c = a.scratch[(size_t)t * TL::PVOL + (l2 * TL::PY + l1) * TL::PX + l0];
+                const f32x4 c = glb4(a.scratch)[(size_t)t * TL::PVOL + (l2 * TL::PY + l1) * TL::PX + l0];
                 W += c.x; P0 += c.y; P1 += c.z; P2 += c.w;
             }
     float V[3] = {0.f, 0.f, 0.f};
@@ -255,7 +260,7 @@ __device__ __forceinline__ void grid_block(const BatchMap& m, int gnb, int sbin,
                          j > a.nn[1] - 1 - a.band || k > a.nn[2] - 1 - a.band || k <= a.pad_b;
         if (bnd) V[0] = V[1] = V[2] = 0.f;
     }
-    a.gridV[nid] = make_float4(V[0], V[1], V[2], W);
+    glb4(a.gridV)[nid] = f32x4{V[0], V[1], V[2], W};
     if (a.dbgM) {
         a.dbgM[nid] = a.mp * W;
         a.dbgMG[3 * nid + 0] = a.mp * P0;
@@ -288,8 +293,8 @@ __device__ __forceinline__ void g2p2g_tile(const BatchMap& m, int gt, int cur, i
         if (t == 0 && threadIdx.x == 0) a.st->finished[pass + 1] = 1;
         return;
     }
-    const uint32_t* __restrict__ order = a.order[cur];
-    const uint32_t* __restrict__ bstart = a.bstart[cur];
+    const gptr<const uint32_t> __restrict__ order = glb<const uint32_t>(a.order[cur]);
+    const gptr<const uint32_t> __restrict__ bstart = glb<const uint32_t>(a.bstart[cur]);
     extern __shared__ unsigned long long lds_u64[];
     unsigned long long* acc = lds_u64;                                   // 4 * PVOL
     float* gv = reinterpret_cast<float*>(lds_u64 + 4 * TL::AVOL);        // GVOL x (vx, vy, vz)
@@ -311,7 +316,7 @@ __device__ __forceinline__ void g2p2g_tile(const BatchMap& m, int gt, int cur, i
         const int cx = tid % 3, cy = (tid / 3) % 3, cz = tid / 9;
         const long long nid = ((long long)(base[2] + cz) * a.nn[1] + (base[1] + cy)) * a.nn[0] +
                               (base[0] + cx);
-        const float4 V = a.gridV[nid];
+        const f32x4 V = glb4(a.gridV)[nid];
         const float wt = w[0][cx] * w[1][cy] * w[2][cz];
         ve_part[3 * tid + 0] = wt * V.x;
         ve_part[3 * tid + 1] = wt * V.y;
@@ -355,7 +360,7 @@ __device__ __forceinline__ void g2p2g_tile(const BatchMap& m, int gt, int cur, i
 
     const uint32_t s0 = bstart[t], cnt = bstart[t + 1] - s0;
     if (cnt == 0) {
-        if (fin && tid < kDirs) a.dircount[(size_t)t * kDirs + tid] = 0;
+        if (fin && tid < kDirs) glb(a.dircount)[(size_t)t * kDirs + tid] = 0;
         return;
     }
     int tc[3];
@@ -367,9 +372,9 @@ __device__ __forceinline__ void g2p2g_tile(const BatchMap& m, int gt, int cur, i
     for (int kk = tid; kk < TL::GVOL; kk += TL::NT) {
         const int lx = kk % TL::GX, ly = (kk / TL::GX) % TL::GY, lz = kk / (TL::GX * TL::GY);
         const int gx = orgG[0] + lx, gy = orgG[1] + ly, gz = orgG[2] + lz;
-        float4 V = make_float4(0.f, 0.f, 0.f, 0.f);
+        f32x4 V = {0.f, 0.f, 0.f, 0.f};
         if (gx >= 0 && gy >= 0 && gz >= 0 && gx < a.nn[0] && gy < a.nn[1] && gz < a.nn[2])
-            V = a.gridV[((long long)gz * a.nn[1] + gy) * a.nn[0] + gx];
+            V = glb4(a.gridV)[((long long)gz * a.nn[1] + gy) * a.nn[0] + gx];
         gv[3 * kk] = V.x; gv[3 * kk + 1] = V.y; gv[3 * kk + 2] = V.z;
     }
     for (int kk = tid; kk < 4 * TL::AVOL; kk += TL::NT) acc[kk] = 0ull;
@@ -395,8 +400,8 @@ __device__ __forceinline__ void g2p2g_tile(const BatchMap& m, int gt, int cur, i
             float G[9];
             uint8_t fl = 0;
             if constexpr (kEarly) {
-                for (int q = 0; q < 9; ++q) G[q] = a.soa[(size_t)(G0 + q) * a.n + id];
-                fl = a.flags[id];
+                for (int q = 0; q < 9; ++q) G[q] = glb(a.soa)[(size_t)(G0 + q) * a.n + id];
+                fl = glb(a.flags)[id];
             }
             // ---- 2. grid-to-particle (Eq. 6-7), separably: column sums S_a,
             // T_b, U_c of the weighted grid velocities along each axis give
@@ -450,8 +455,8 @@ __device__ __forceinline__ void g2p2g_tile(const BatchMap& m, int gt, int cur, i
                 err |= DEV_CFL;
             }
             if constexpr (!kEarly) {
-                for (int q = 0; q < 9; ++q) G[q] = a.soa[(size_t)(G0 + q) * a.n + id];
-                fl = a.flags[id];
+                for (int q = 0; q < 9; ++q) G[q] = glb(a.soa)[(size_t)(G0 + q) * a.n + id];
+                fl = glb(a.flags)[id];
             }
             if (a.bottom_rule && (fl & FLAG_BOTTOM)) v[2] = 0.f;
             if (fin) {
@@ -489,9 +494,9 @@ __device__ __forceinline__ void g2p2g_tile(const BatchMap& m, int gt, int cur, i
                 err |= perr;
                 if (perr == 0) {
                     for (int q = 0; q < 3; ++q) { cell[q] = moved[q]; f[q] = nfr[q]; }
-                    a.cell[id] = pack_cell(cell);
-                    for (int q = 0; q < 3; ++q) a.soa[(size_t)(F0 + q) * a.n + id] = f[q];
-                    for (int q = 0; q < 9; ++q) a.soa[(size_t)(G0 + q) * a.n + id] = G[q];
+                    glb(a.cell)[id] = pack_cell(cell);
+                    for (int q = 0; q < 3; ++q) glb(a.soa)[(size_t)(F0 + q) * a.n + id] = f[q];
+                    for (int q = 0; q < 9; ++q) glb(a.soa)[(size_t)(G0 + q) * a.n + id] = G[q];
                 }
                 if (id == a.e) {
                     a.st->xe_cell[par ^ 1] = pack_cell(cell);
@@ -509,8 +514,8 @@ __device__ __forceinline__ void g2p2g_tile(const BatchMap& m, int gt, int cur, i
                 }
             }
             if (store_vc && fin) {
-                for (int q = 0; q < 3; ++q) a.soa[(size_t)(V0 + q) * a.n + id] = v[q];
-                for (int q = 0; q < 9; ++q) a.soa[(size_t)(C0 + q) * a.n + id] = C[q];
+                for (int q = 0; q < 3; ++q) glb(a.soa)[(size_t)(V0 + q) * a.n + id] = v[q];
+                for (int q = 0; q < 9; ++q) glb(a.soa)[(size_t)(C0 + q) * a.n + id] = C[q];
             }
             // ---- transfer to the grid of the next exchange
             err |= p2g_particle<TL>(acc, orgP, cell, f, v, C, G, with_stress, a);
@@ -534,7 +539,7 @@ __device__ __forceinline__ void g2p2g_tile(const BatchMap& m, int gt, int cur, i
             if (dir >= 0) {
                 int base_r = running[dir];
                 for (int w2 = 0; w2 < wid; ++w2) base_r += wc[w2 * kDirs + dir];
-                a.dirrank[s0 + i] = ((uint32_t)(base_r + my_rank) << 5) | (uint32_t)dir;
+                glb(a.dirrank)[s0 + i] = ((uint32_t)(base_r + my_rank) << 5) | (uint32_t)dir;
             }
             __syncthreads();
             if (tid < kDirs) {
@@ -547,10 +552,10 @@ __device__ __forceinline__ void g2p2g_tile(const BatchMap& m, int gt, int cur, i
     }
     if (err) atomicOr(&a.st->error, err);
     __syncthreads();
-    flush_tile<TL>(acc, a.scratch + (size_t)t * TL::PVOL);
+    flush_tile<TL>(acc, glb4(a.scratch) + (size_t)t * TL::PVOL);
     if (fin && tid < kDirs) {
         const uint32_t c = running[tid];
-        a.dircount[(size_t)t * kDirs + tid] = c;
+        glb(a.dircount)[(size_t)t * kDirs + tid] = c;
         if (c) {
             const int dt[3] = {tid % 3 - 1, (tid / 3) % 3 - 1, tid / 9 - 1};
             int u[3];
@@ -624,36 +629,51 @@ __global__ __launch_bounds__(TL::NT) void k_extra_passes(BatchMap m, int tiles, 
 }
 
 // Counting sort, scan part: exclusive prefix sum of the next step's tile sizes
-// (accumulated by the fused kernel), one block; clears the counts and the
-// per-step loop flags for the next step.
+// (accumulated by the fused kernel), one block of 16 waves per sensor; clears the
+// counts and the per-step loop flags for the next step.  Each thread takes four
+// consecutive counts of a 4096-entry chunk; the waves scan their thread totals
+// with cross-lane shifts, so a chunk costs two block barriers.
 __global__ __launch_bounds__(1024) void k_scan(BatchMap m, int next, int limit_slots) {
     const KArgs& a = m.args[blockIdx.x];
-    uint32_t* __restrict__ bstart_next = a.bstart[next];
-    __shared__ uint32_t part[1024];
-    __shared__ uint32_t carry;
-    const int tid = threadIdx.x;
-    if (tid == 0) carry = 0;
+    const gptr<uint32_t> __restrict__ bstart_next = glb(a.bstart[next]);
+    __shared__ uint32_t wsum[16];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     if (tid < limit_slots) a.st->finished[tid] = 0;
-    __syncthreads();
-    for (int t0 = 0; t0 < a.n_tiles; t0 += 1024) {
-        const int u = t0 + tid;
-        uint32_t cnt = 0;
-        if (u < a.n_tiles) {
-            cnt = a.newcnt[u];
-            a.newcnt[u] = 0;
+    uint32_t carry = 0;   // the same in every thread
+    for (int t0 = 0; t0 < a.n_tiles; t0 += 4096) {
+        const int u0 = t0 + 4 * tid;
+        uint32_t c[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            c[q] = 0;
+            if (u0 + q < a.n_tiles) {
+                c[q] = glb(a.newcnt)[u0 + q];
+                glb(a.newcnt)[u0 + q] = 0;
+            }
         }
-        part[tid] = cnt;
-        __syncthreads();
-        for (int off = 1; off < 1024; off <<= 1) {
-            const uint32_t x = tid >= off ? part[tid - off] : 0;
-            __syncthreads();
-            part[tid] += x;
-            __syncthreads();
+        const uint32_t tot = c[0] + c[1] + c[2] + c[3];
+        uint32_t incl = tot;   // inclusive scan of the thread totals over the wave
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(incl, off);
+            if (lane >= off) incl += y;
         }
-        if (u < a.n_tiles) bstart_next[u] = carry + part[tid] - cnt;
+        if (lane == 63) wsum[wid] = incl;
         __syncthreads();
-        if (tid == 1023) carry += part[1023];
-        __syncthreads();
+        uint32_t run = carry + incl - tot, chunk = 0;
+#pragma unroll
+        for (int w = 0; w < 16; ++w) {
+            const uint32_t ws = wsum[w];
+            if (w < wid) run += ws;
+            chunk += ws;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (u0 + q < a.n_tiles) bstart_next[u0 + q] = run;
+            run += c[q];
+        }
+        carry += chunk;
+        __syncthreads();   // the next chunk rewrites wsum
     }
     if (tid == 0) bstart_next[a.n_tiles] = carry;
 }
@@ -669,13 +689,23 @@ __global__ __launch_bounds__(kBlock) void k_scatter(BatchMap m, int cur) {
         t -= m.tile_base[s];
     }
     const KArgs& a = m.args[s];
-    const uint32_t* __restrict__ order = a.order[cur];
-    const uint32_t* __restrict__ bstart = a.bstart[cur];
-    const uint32_t* __restrict__ bstart_next = a.bstart[cur ^ 1];
-    uint32_t* __restrict__ order_next = a.order[cur ^ 1];
+    const gptr<const uint32_t> __restrict__ order = glb<const uint32_t>(a.order[cur]);
+    const gptr<const uint32_t> __restrict__ bstart = glb<const uint32_t>(a.bstart[cur]);
+    const gptr<const uint32_t> __restrict__ bstart_next = glb<const uint32_t>(a.bstart[cur ^ 1]);
+    const gptr<uint32_t> __restrict__ order_next = glb(a.order[cur ^ 1]);
     const uint32_t s0 = bstart[t], cnt = bstart[t + 1] - s0;
     if (cnt == 0) return;
     const int tid = threadIdx.x;
+    // The first kPre rounds of (direction rank, id) pairs are loaded before the
+    // destination offsets are summed, so the two memory round trips overlap.
+    constexpr int kPre = 6;
+    uint32_t pre_dr[kPre], pre_id[kPre];
+#pragma unroll
+    for (int k = 0; k < kPre; ++k) {
+        const uint32_t i = tid + k * kBlock;
+        pre_dr[k] = i < cnt ? glb(a.dirrank)[s0 + i] : 0u;
+        pre_id[k] = i < cnt ? order[s0 + i] : 0u;
+    }
     if (tid < kDirs) {
         int tc[3], u[3];
         tile_coords(a, t, tc);
@@ -699,7 +729,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(BatchMap m, int cur) {
                     sc[q] = u[q] - e2[q];
                     ok2 = ok2 && sc[q] >= 0 && sc[q] < a.NT[q];
                 }
-                cnts[d2] = ok2 ? a.dircount[(size_t)tile_linear(a, sc) * kDirs + d2] : 0u;
+                cnts[d2] = ok2 ? glb(a.dircount)[(size_t)tile_linear(a, sc) * kDirs + d2] : 0u;
             }
 #pragma unroll
             for (int d2 = 0; d2 < kDirs; ++d2) o += cnts[d2];
@@ -707,8 +737,16 @@ __global__ __launch_bounds__(kBlock) void k_scatter(BatchMap m, int cur) {
         off[tid] = o;
     }
     __syncthreads();
-    for (uint32_t i = tid; i < cnt; i += kBlock) {
-        const uint32_t dr = a.dirrank[s0 + i];
+#pragma unroll
+    for (int k = 0; k < kPre; ++k) {
+        if (tid + k * kBlock < cnt) {
+            const uint32_t dst = off[pre_dr[k] & 31u] + (pre_dr[k] >> 5);
+            if (dst < (uint32_t)a.n) order_next[dst] = pre_id[k];
+            else atomicOr(&a.st->error, DEV_CFL);
+        }
+    }
+    for (uint32_t i = tid + kPre * kBlock; i < cnt; i += kBlock) {
+        const uint32_t dr = glb(a.dirrank)[s0 + i];
         const uint32_t dst = off[dr & 31u] + (dr >> 5);
         if (dst < (uint32_t)a.n) order_next[dst] = order[s0 + i];
         else atomicOr(&a.st->error, DEV_CFL);
@@ -722,7 +760,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(BatchMap m, int cur) {
 __global__ void k_surface_accum(KArgs a, SurfArgs s) {
     const long long slot = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (slot >= a.n) return;
-    if (!(a.flags[slot] & FLAG_SURFACE)) return;
+    if (!(glb(a.flags)[slot] & FLAG_SURFACE)) return;
     const long long id = s.id_of[slot];
     const int ppc = s.m * s.m * s.m;
     const long long cell_id = id / ppc;
