@@ -47,9 +47,10 @@ ALG_BYTES_PER_PARTICLE_PASS = 192.0 + 7.0
 # HBM bytes per launch of the fused kernel for this workload, from two
 # rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) scaled by
 # the counters' reading of a copy of known size (fetched bytes = 2.0 x
-# FETCH_SIZE, written = 1.0 x WRITE_SIZE); None whenever the kernel has changed
-# since the counters were taken.
-PMC_TRAFFIC_BYTES = (2.0 * 179396 + 320747) * 1024
+# FETCH_SIZE, written = 1.0 x WRITE_SIZE), with the default storage compaction
+# once per frame; None whenever the kernel has changed since the counters were
+# taken.
+PMC_TRAFFIC_BYTES = (2.0 * 158167 + 308179) * 1024
 
 
 def parse():
@@ -63,6 +64,8 @@ def parse():
     ap.add_argument("--tile", default=None, help="tile cells tx,ty,tz[,threads] of the binned order")
     ap.add_argument("--workload", choices=("sensor", "batch", "surrogate"), default="sensor")
     ap.add_argument("--graph", type=int, default=None, help="1/0: replay step sequences as HIP graphs")
+    ap.add_argument("--compact-every", type=int, default=200,
+                    help="executed steps between storage compactions of the sensor (0: never)")
     return ap.parse_args()
 
 
@@ -304,6 +307,7 @@ def main():
     # warm-up on a throw-away sensor (allocation, code load, caches)
     if args.warmup:
         w = impm.Sim(p)
+        w.sim_set_compaction(args.compact_every)
         if args.tile:
             w.sim_set_tile(*[int(v) for v in args.tile.split(",")])
         run_frames(w, segs, 0, args.warmup, hm)
@@ -312,6 +316,7 @@ def main():
         del w
 
     sim = impm.Sim(p)
+    sim.sim_set_compaction(args.compact_every)
     if args.tile:
         sim.sim_set_tile(*[int(v) for v in args.tile.split(",")])
     if args.graph:
@@ -334,7 +339,9 @@ def main():
     achieved = ALG_BYTES_PER_PARTICLE_PASS * n / (avg_ms * 1e-3) / 1e9   # nan when not profiled
     roofline = {"bound": "hbm", "kernel": "k_g2p2g<false>", "achieved": round(achieved, 1),
                 "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                "traffic": PMC_TRAFFIC_BYTES, "traffic_unit": "bytes/launch",
+                # the counters were read on the default layout and tile only
+                "traffic": PMC_TRAFFIC_BYTES if args.compact_every == 200 and not args.tile else None,
+                "traffic_unit": "bytes/launch",
                 "avg_kernel_ms": round(avg_ms, 5),
                 "alg_bytes_per_launch": ALG_BYTES_PER_PARTICLE_PASS * n}
     out = {
@@ -353,7 +360,8 @@ def main():
         "config": {"workload": "IMPM sensor 128x128x32 cells dx 0.25 mm, 4194304 particles, capsule "
                                "press 1.5 mm then slip 2 mm + rotate 30 deg, 256x256 height map "
                                "every 50 substeps",
-                   "particles": n, "subcycle": SUBCYCLE, "tile": args.tile or "8,4,4", "executed_steps": steps_exec,
+                   "particles": n, "subcycle": SUBCYCLE, "tile": args.tile or "8,4,4",
+                   "compact_every": args.compact_every, "executed_steps": steps_exec,
                    "passes": st["passes"], "limit_hits": st["limit_hits"],
                    "particle_substeps_per_s": n * args.steps / wall,
                    "particle_passes_per_s": n * st["passes"] / wall},

@@ -19,6 +19,8 @@ namespace impm {
 __global__ void k_fill(float* p, long long n, float val);
 __global__ void k_scan(BatchMap m, int next, int limit_slots);
 __global__ void k_scatter(BatchMap m, int cur);
+__global__ void k_compact(KArgs a, int cur, float* soa_dst, uint32_t* cell_dst, uint8_t* flags_dst,
+                          const uint32_t* id_src, uint32_t* id_dst, long long* e_out);
 __global__ void k_surface_accum(KArgs a, SurfArgs s);
 __global__ void k_depthmap(KArgs a, DepthArgs g, float* out);
 __global__ void k_surface_finish(const unsigned long long* acc, int npix, float top, float dx, int mode,
@@ -79,6 +81,19 @@ struct sim_s {
     // whole cache lines of every plane.  The ABI addresses particles by id.
     std::vector<uint32_t> slot_of, id_of;
     uint32_t* d_id_of = nullptr;
+    // Storage compaction: every `compact_every` executed steps the state moves
+    // into the current binned order (the device id map moves with it), so that
+    // a tile's loads stay on its own cache lines while particles migrate.  The
+    // host slot maps are then refreshed from the device only when a host call
+    // needs them; until then `e_slot` holds the calibration particle's slot.
+    long long compact_every = 0, since_compact = 0;
+    float* soa_alt = nullptr;
+    uint32_t* cell_alt = nullptr;
+    uint8_t* flags_alt = nullptr;
+    uint32_t* id_of_alt = nullptr;
+    long long* d_e_slot = nullptr;
+    bool slots_stale = false;
+    long long e_slot = 0;
     bool use_graph = false;       // replay step sequences as HIP graphs
     GraphCache graphs;
     std::vector<double> hf_host;  // height-field table (P.hf points here)
@@ -314,7 +329,7 @@ static KArgs kargs(const sim_t* s) {
     a.hf_half = P.hf_half;
     a.mp = (float)s->mp;
     a.n = s->n;
-    a.e = s->slot_of[s->e];
+    a.e = s->slots_stale ? s->e_slot : (long long)s->slot_of[s->e];
     a.soa = s->soa;
     a.cell = s->cell;
     a.flags = s->flags;
@@ -432,7 +447,18 @@ static int read_cells(sim_t* s, std::vector<uint32_t>& cells, std::vector<float>
     return SIM_OK;
 }
 
+// Bring the host slot maps up to date after storage compactions.
+static int ensure_slots(sim_t* s) {
+    if (!s->slots_stale) return SIM_OK;
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    HIPCHK(s, hipMemcpy(s->id_of.data(), s->d_id_of, (size_t)s->n * 4, hipMemcpyDeviceToHost));
+    for (long long k = 0; k < s->n; ++k) s->slot_of[s->id_of[k]] = (uint32_t)k;
+    s->slots_stale = false;
+    return SIM_OK;
+}
+
 static int refresh_binning(sim_t* s) {
+    if (int rc0 = ensure_slots(s)) return rc0;
     std::vector<uint32_t> cells;
     std::vector<float> offs;
     int rc = read_cells(s, cells, offs);
@@ -572,6 +598,44 @@ static void finish_call(sim_t* s, int32_t n_substeps, long long N) {
         s->cur ^= 1;
         s->gstep += 1;
     }
+}
+
+// Move the state into the binned order of the next step (see sim_s).  The
+// order must be a permutation, so a latched device error is reported first.
+static int compact_storage(sim_t* s) {
+    const size_t n = (size_t)s->n;
+    if (!s->soa_alt) {
+        HIPCHK(s, hipMalloc(&s->soa_alt, (size_t)NPLANES * n * sizeof(float)));
+        HIPCHK(s, hipMalloc(&s->cell_alt, n * 4));
+        HIPCHK(s, hipMalloc(&s->flags_alt, n));
+        HIPCHK(s, hipMalloc(&s->id_of_alt, n * 4));
+        HIPCHK(s, hipMalloc(&s->d_e_slot, sizeof(long long)));
+    }
+    if (int rc = check_device_error(s)) return rc;
+    const KArgs a = kargs(s);
+    long long e_new = a.e;   // kept if the kernel does not report a slot
+    HIPCHK(s, hipMemcpyAsync(s->d_e_slot, &e_new, sizeof(long long), hipMemcpyHostToDevice, s->stream));
+    const int blocks = (int)std::min<long long>((s->n + kBlock - 1) / kBlock, 8192);
+    hipLaunchKernelGGL(k_compact, dim3(blocks), dim3(kBlock), 0, s->stream, a, s->cur, s->soa_alt, s->cell_alt,
+                       s->flags_alt, s->d_id_of, s->id_of_alt, s->d_e_slot);
+    HIPCHK(s, hipGetLastError());
+    HIPCHK(s, hipMemcpyAsync(&e_new, s->d_e_slot, sizeof(long long), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    if (int rc = check_device_error(s)) return rc;
+    std::swap(s->soa, s->soa_alt);
+    std::swap(s->cell, s->cell_alt);
+    std::swap(s->flags, s->flags_alt);
+    std::swap(s->d_id_of, s->id_of_alt);
+    s->e_slot = e_new;
+    s->slots_stale = true;
+    s->since_compact = 0;
+    return sync_args(s);
+}
+
+static int after_call(sim_t* s, long long N) {
+    s->since_compact += N;
+    if (s->compact_every > 0 && s->since_compact >= s->compact_every) return compact_storage(s);
+    return SIM_OK;
 }
 
 // ------------------------------------------------------------------ C ABI
@@ -795,7 +859,7 @@ void sim_destroy(sim_t* s) {
     void* bufs[] = {s->soa, s->cell, s->flags, s->order[0], s->order[1], s->bstart[0], s->bstart[1],
                     s->dirrank, s->dircount, s->newcnt, s->scratch, s->gridV, s->dbgM, s->dbgMG,
                     s->st, s->poses, s->surf_rest, s->surf_acc, s->out_tmp, s->d_args, s->d_hf,
-                    s->d_id_of};
+                    s->d_id_of, s->soa_alt, s->cell_alt, s->flags_alt, s->id_of_alt, s->d_e_slot};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     for (int k = 0; k < 2; ++k) {
@@ -885,7 +949,7 @@ int sim_step(sim_t* s, int32_t n_substeps) {
         if (le != hipSuccess) return fail(s, SIM_EHIP, std::string("step launch: ") + hipGetErrorString(le));
         if (e != hipSuccess) return fail(s, SIM_EHIP, std::string("step graph: ") + hipGetErrorString(e));
         finish_call(s, n_substeps, N);
-        return SIM_OK;
+        return after_call(s, N);
     }
     for (long long j = 0; j < N; ++j) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -905,7 +969,7 @@ int sim_step(sim_t* s, int32_t n_substeps) {
         g += 1;
     }
     finish_call(s, n_substeps, N);
-    return SIM_OK;
+    return after_call(s, N);
 }
 
 int sim_synchronize(sim_t* s) {
@@ -1035,6 +1099,7 @@ int sim_grid_dims(const sim_t* s, int32_t nodes[3]) {
 
 int sim_read_particles(sim_t* s, double* x, float* v, float* C, float* G) {
     if (!s) return SIM_EINVAL;
+    if (int rc0 = ensure_slots(s)) return rc0;
     HIPCHK(s, hipStreamSynchronize(s->stream));
     const size_t n = (size_t)s->n;
     if (x) {
@@ -1069,6 +1134,7 @@ int sim_read_particles(sim_t* s, double* x, float* v, float* C, float* G) {
 
 int sim_write_particles(sim_t* s, const double* x, const float* v, const float* C, const float* G) {
     if (!s) return SIM_EINVAL;
+    if (int rc0 = ensure_slots(s)) return rc0;
     HIPCHK(s, hipStreamSynchronize(s->stream));
     const size_t n = (size_t)s->n;
     if (x) {
@@ -1124,6 +1190,7 @@ int sim_read_rest(sim_t* s, double* X, uint8_t* flags) {
         }
     }
     if (flags) {
+        if (int rc0 = ensure_slots(s)) return rc0;
         std::vector<uint8_t> fs(s->n);
         HIPCHK(s, hipMemcpy(fs.data(), s->flags, s->n, hipMemcpyDeviceToHost));
         for (long long id = 0; id < s->n; ++id) flags[id] = fs[s->slot_of[id]];
@@ -1178,6 +1245,14 @@ int sim_set_graph(sim_t* s, int32_t on) {
 int sim_profile(sim_t* s, int32_t on) {
     if (!s) return SIM_EINVAL;
     s->prof = on != 0;
+    return SIM_OK;
+}
+
+int sim_set_compaction(sim_t* s, int32_t every_steps) {
+    if (!s) return SIM_EINVAL;
+    if (every_steps < 0) return fail(s, SIM_EINVAL, "every_steps must be >= 0");
+    s->compact_every = every_steps;
+    s->since_compact = 0;
     return SIM_OK;
 }
 

@@ -753,6 +753,36 @@ __global__ __launch_bounds__(kBlock) void k_scatter(BatchMap m, int cur) {
     }
 }
 
+// Storage compaction: the particle at binned position q moves to slot q, so that
+// a tile's particles fill consecutive slots again, and the order becomes the
+// identity.  Every state plane, the packed cell, the flags and the id map move
+// together; the calibration particle's new slot goes to e_out.  The order is a
+// permutation of [0, n) (the host checks the error word first); an entry out of
+// range latches DEV_CFL and is skipped.
+__global__ __launch_bounds__(kBlock) void k_compact(KArgs a, int cur, float* __restrict__ soa_dst,
+                                                    uint32_t* __restrict__ cell_dst,
+                                                    uint8_t* __restrict__ flags_dst,
+                                                    const uint32_t* __restrict__ id_src,
+                                                    uint32_t* __restrict__ id_dst, long long* __restrict__ e_out) {
+    const gptr<uint32_t> order = glb(a.order[cur]);
+    const gptr<const float> soa = glb<const float>(a.soa);
+    const size_t n = (size_t)a.n;
+    for (size_t q = blockIdx.x * (size_t)kBlock + threadIdx.x; q < n; q += (size_t)gridDim.x * kBlock) {
+        const uint32_t src = order[q];
+        if (src >= n) {
+            atomicOr(&a.st->error, DEV_CFL);
+            continue;
+        }
+        cell_dst[q] = glb(a.cell)[src];
+        flags_dst[q] = glb(a.flags)[src];
+        id_dst[q] = id_src[src];
+#pragma unroll
+        for (int p = 0; p < NPLANES; ++p) soa_dst[(size_t)p * n + q] = soa[(size_t)p * n + src];
+        order[q] = (uint32_t)q;
+        if ((long long)src == a.e) *e_out = (long long)q;
+    }
+}
+
 // Surface raster: every surface particle adds its quadratic B-spline weights
 // (pitch = pixel size) and weighted displacement (in cells) to a W x H
 // accumulator of 64-bit fixed-point sums (2^-32), so the maps are exact and

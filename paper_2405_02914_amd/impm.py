@@ -58,8 +58,8 @@ EXPORTS = ("sim_params_default", "sim_create", "sim_destroy", "sim_set_indenter_
            "sim_batch_create", "sim_batch_destroy", "sim_batch_size", "sim_batch_get",
            "sim_batch_set_indenter_poses", "sim_batch_step", "sim_batch_synchronize",
            "sim_batch_heightmaps", "sim_batch_displacements", "sim_batch_last_error",
-           "sim_autotune_tile", "sim_set_graph", "sim_batch_set_graph", "sim_indenter_depthmap",
-           "sim_batch_depthmaps")
+           "sim_autotune_tile", "sim_set_graph", "sim_set_compaction", "sim_batch_set_graph",
+           "sim_indenter_depthmap", "sim_batch_depthmaps")
 
 _lib = None
 
@@ -96,6 +96,7 @@ def lib():
     L.sim_set_tile_threads.argtypes = [vp, i32, i32, i32, i32]
     L.sim_profile.argtypes = [vp, i32]
     L.sim_set_graph.argtypes = [vp, i32]
+    L.sim_set_compaction.argtypes = [vp, i32]
     L.sim_indenter_depthmap.argtypes = [vp, fp, i32, i32, C.c_double, i32]
     L.sim_batch_depthmaps.argtypes = [vp, fp, i32, i32, C.c_double, i32]
     L.sim_batch_set_graph.argtypes = [vp, i32]
@@ -269,6 +270,9 @@ class Sim:
 
     def sim_set_graph(self, on=True):
         self._chk(lib().sim_set_graph(self.h, int(on)))
+
+    def sim_set_compaction(self, every_steps):
+        self._chk(lib().sim_set_compaction(self.h, int(every_steps)))
 
     def sim_profile(self, on=True):
         self._chk(lib().sim_profile(self.h, int(on)))
