@@ -50,7 +50,7 @@ ALG_BYTES_PER_PARTICLE_PASS = 192.0 + 7.0
 # FETCH_SIZE, written = 1.0 x WRITE_SIZE), with the default storage compaction
 # once per frame; None whenever the kernel has changed since the counters were
 # taken.
-PMC_TRAFFIC_BYTES = (2.0 * 158167 + 308179) * 1024
+PMC_TRAFFIC_BYTES = (2.0 * 159035 + 308822) * 1024
 
 
 def parse():

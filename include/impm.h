@@ -190,12 +190,14 @@ int sim_set_graph(sim_t* s, int32_t on);
 /* Storage compaction (a layout choice; the method is unchanged).  every_steps > 0:
  * after a sim_step call in which at least every_steps executed steps have
  * accumulated, the particle state (all planes, cells, flags, id map) is moved
- * on the device into the binned order of the next step.  Particles that cross
- * tiles otherwise leave a tile's data spread over other tiles' cache lines.
- * The results are bitwise those of a run without compaction (the node sums are
- * exact and order-independent).  Each compaction synchronises the stream once,
- * copies the state once (about 2 x 105 B per particle), and reports a latched
- * device error (SIM_ENUMERIC) at that point.  The first use allocates a second
+ * on the device into the binned order of the next step, round-robin over the
+ * stencil base nodes inside each tile.  Without it, particles that cross tiles
+ * leave a tile's data spread over other tiles' cache lines, and neighbouring
+ * lanes come to share base nodes.  The results are bitwise those of a run
+ * without compaction: the node sums are exact and order-independent.  The
+ * storage order itself may differ between runs.  Each compaction synchronises
+ * the stream once, copies the state once (about 2 x 105 B per particle), and
+ * reports a latched device error (SIM_ENUMERIC) at that point.  The first use allocates a second
  * copy of the state, owned by the handle (SIM_EHIP if that fails).
  * every_steps = 0 (the default) turns it off; negative values are SIM_EINVAL. */
 int sim_set_compaction(sim_t* s, int32_t every_steps);

@@ -615,8 +615,7 @@ static int compact_storage(sim_t* s) {
     const KArgs a = kargs(s);
     long long e_new = a.e;   // kept if the kernel does not report a slot
     HIPCHK(s, hipMemcpyAsync(s->d_e_slot, &e_new, sizeof(long long), hipMemcpyHostToDevice, s->stream));
-    const int blocks = (int)std::min<long long>((s->n + kBlock - 1) / kBlock, 8192);
-    hipLaunchKernelGGL(k_compact, dim3(blocks), dim3(kBlock), 0, s->stream, a, s->cur, s->soa_alt, s->cell_alt,
+    hipLaunchKernelGGL(k_compact, dim3(s->n_tiles), dim3(kBlock), 0, s->stream, a, s->cur, s->soa_alt, s->cell_alt,
                        s->flags_alt, s->d_id_of, s->id_of_alt, s->d_e_slot);
     HIPCHK(s, hipGetLastError());
     HIPCHK(s, hipMemcpyAsync(&e_new, s->d_e_slot, sizeof(long long), hipMemcpyDeviceToHost, s->stream));

@@ -753,34 +753,79 @@ __global__ __launch_bounds__(kBlock) void k_scatter(BatchMap m, int cur) {
     }
 }
 
-// Storage compaction: the particle at binned position q moves to slot q, so that
-// a tile's particles fill consecutive slots again, and the order becomes the
-// identity.  Every state plane, the packed cell, the flags and the id map move
-// together; the calibration particle's new slot goes to e_out.  The order is a
-// permutation of [0, n) (the host checks the error word first); an entry out of
-// range latches DEV_CFL and is skipped.
+// Storage compaction, one block per tile: the tile's particles move to the
+// slots of its binned range, so that its loads fill consecutive cache lines
+// again, and the order over the range becomes the identity.  Inside the range
+// they go round-robin over the stencil base nodes (the first particle of every
+// base node, then the second, ...), so that adjacent lanes of the next fused
+// kernels add to different LDS nodes.  With r the rank of a particle among those
+// of its base node l and c[.] the base-node counts, the new position is
+// sum_l' min(c[l'], r) + #{l' < l : c[l'] > r}, a bijection onto the range.
+// Every state plane, the packed cell, the flags and the id map move together;
+// the calibration particle's new slot goes to e_out.  The rank is taken with LDS
+// atomics, so the storage order may differ between runs; no result depends on
+// it (the node sums are exact).  dirrank, which the next fused kernel rewrites,
+// holds (rank, base node) between the two passes.  Out-of-range entries latch
+// DEV_CFL and are clamped, which keeps every access in bounds.
+constexpr int kMaxTileNodes = 512;
+
 __global__ __launch_bounds__(kBlock) void k_compact(KArgs a, int cur, float* __restrict__ soa_dst,
                                                     uint32_t* __restrict__ cell_dst,
                                                     uint8_t* __restrict__ flags_dst,
                                                     const uint32_t* __restrict__ id_src,
                                                     uint32_t* __restrict__ id_dst, long long* __restrict__ e_out) {
+    __shared__ uint32_t cnt[kMaxTileNodes];
+    const int t = blockIdx.x, tid = threadIdx.x;
     const gptr<uint32_t> order = glb(a.order[cur]);
+    const gptr<const uint32_t> bstart = glb<const uint32_t>(a.bstart[cur]);
+    const gptr<uint32_t> keys = glb(a.dirrank);
     const gptr<const float> soa = glb<const float>(a.soa);
     const size_t n = (size_t)a.n;
-    for (size_t q = blockIdx.x * (size_t)kBlock + threadIdx.x; q < n; q += (size_t)gridDim.x * kBlock) {
-        const uint32_t src = order[q];
-        if (src >= n) {
-            atomicOr(&a.st->error, DEV_CFL);
-            continue;
-        }
-        cell_dst[q] = glb(a.cell)[src];
-        flags_dst[q] = glb(a.flags)[src];
-        id_dst[q] = id_src[src];
+    const uint32_t s0 = bstart[t], c = bstart[t + 1] - s0;
+    if (c == 0) return;
+    const int nl = a.T[0] * a.T[1] * a.T[2];
+    for (int k = tid; k < nl; k += kBlock) cnt[k] = 0;
+    __syncthreads();
+    int tc[3];
+    tile_coords(a, t, tc);
+    int err = 0;
+    for (uint32_t i = tid; i < c; i += kBlock) {
+        uint32_t src = order[s0 + i];
+        if (src >= n) { err |= DEV_CFL; src = 0; }
+        int cell[3];
+        float f[3];
+        load_particle(a, src, cell, f);
+        int l[3];
 #pragma unroll
-        for (int p = 0; p < NPLANES; ++p) soa_dst[(size_t)p * n + q] = soa[(size_t)p * n + src];
-        order[q] = (uint32_t)q;
-        if ((long long)src == a.e) *e_out = (long long)q;
+        for (int q = 0; q < 3; ++q) {
+            l[q] = cell[q] - 1 + (f[q] >= 0.5f ? 1 : 0) - tc[q] * a.T[q];
+            if (l[q] < 0 || l[q] >= a.T[q]) { err |= DEV_CFL; l[q] = l[q] < 0 ? 0 : a.T[q] - 1; }
+        }
+        const uint32_t local = (uint32_t)((l[2] * a.T[1] + l[1]) * a.T[0] + l[0]);
+        const uint32_t r = atomicAdd(&cnt[local], 1u);
+        keys[s0 + i] = (r << 9) | local;
     }
+    __syncthreads();
+    for (uint32_t i = tid; i < c; i += kBlock) {
+        const uint32_t key = keys[s0 + i], r = key >> 9, local = key & 511u;
+        uint32_t pos = 0;
+        for (int k = 0; k < nl; ++k) {
+            const uint32_t ck = cnt[k];
+            pos += min(ck, r) + (((uint32_t)k < local && ck > r) ? 1u : 0u);
+        }
+        const size_t dst = s0 + min(pos, c - 1);
+        uint32_t src = order[s0 + i];
+        if (src >= n) src = 0;
+        cell_dst[dst] = glb(a.cell)[src];
+        flags_dst[dst] = glb(a.flags)[src];
+        id_dst[dst] = id_src[src];
+#pragma unroll
+        for (int p = 0; p < NPLANES; ++p) soa_dst[(size_t)p * n + dst] = soa[(size_t)p * n + src];
+        if ((long long)src == a.e) *e_out = (long long)dst;
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < c; i += kBlock) order[s0 + i] = s0 + i;
+    if (err) atomicOr(&a.st->error, err);
 }
 
 // Surface raster: every surface particle adds its quadratic B-spline weights
