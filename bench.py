@@ -154,12 +154,16 @@ def bench_batch(args):
     if args.warmup:
         w = impm.Batch(params, tiles=tiles)
         w.sim_batch_set_graph(graph)
+        for m in w.sensors:
+            m.sim_set_compaction(args.compact_every)
         run_batch_segments(w, scheds, min(args.warmup, total))
         w.sim_batch_synchronize()
         w.close()
         del w
     b = impm.Batch(params, tiles=tiles)
     b.sim_batch_set_graph(graph)
+    for m in b.sensors:
+        m.sim_set_compaction(args.compact_every)
     hm = torch.empty(len(params) * 128 * 128, device="cuda", dtype=torch.float32)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -186,6 +190,7 @@ def bench_batch(args):
                                f"{sum(ns)} particles, mixed sphere/capsule/box/height-field indenters, "
                                f"press-slip-rotate over {total} substeps",
                    "particles": sum(ns), "subcycle": params[0].subcycle, "graph": graph,
+                   "compact_every": args.compact_every,
                    "passes_per_step": round(ppass / max(upd, 1), 3),
                    "tiles": {f"{c[0]}x{c[1]}x{c[2]}": list(t) for c, (t, _) in sorted(tuned.items())},
                    "particle_passes_per_s": ppass / wall},

@@ -199,6 +199,8 @@ int sim_set_graph(sim_t* s, int32_t on);
  * the stream once, copies the state once (about 2 x 105 B per particle), and
  * reports a latched device error (SIM_ENUMERIC) at that point.  The first use allocates a second
  * copy of the state, owned by the handle (SIM_EHIP if that fails).
+ * A batch member (sim_batch_get) with compaction set compacts the same way after
+ * sim_batch_step calls, on its own stream once the batch's launches are done.
  * every_steps = 0 (the default) turns it off; negative values are SIM_EINVAL. */
 int sim_set_compaction(sim_t* s, int32_t every_steps);
 

@@ -1518,6 +1518,22 @@ int sim_batch_step(sim_batch_t* b, int32_t n_substeps) {
     if (le != hipSuccess) return bfail(b, SIM_EHIP, std::string("batch step launch: ") + hipGetErrorString(le));
     BHIPCHK(b, hipGetLastError());
     for (sim_t* s : b->sims) finish_call(s, n_substeps, N);
+    // Members with storage compaction (sim_set_compaction on a member handle)
+    // compact on their own streams once the batch's launches have completed;
+    // the next call's argument sync picks up their new buffers.
+    bool synced = false;
+    for (int i = 0; i < n; ++i) {
+        sim_t* s = b->sims[i];
+        s->since_compact += N;
+        if (s->compact_every > 0 && s->since_compact >= s->compact_every) {
+            if (!synced) {
+                BHIPCHK(b, hipStreamSynchronize(b->stream));
+                synced = true;
+            }
+            const int rc2 = compact_storage(s);
+            if (rc2) return bfail(b, rc2, "sensor " + std::to_string(i) + ": " + s->err);
+        }
+    }
     return SIM_OK;
 }
 

@@ -98,3 +98,33 @@ def test_write_after_compaction(gpu):
     assert _stats_equal(a, b)
     for s in (a, b):
         s.close()
+
+
+def test_batch_members_with_compaction(gpu):
+    """Batch members that compact (on their own streams, after the batch's
+    launches) stay bitwise equal to the members of a batch that does not."""
+    params, scheds = W.config3(n_sensors=3, seed=7, k_range=(2, 3), n_substeps=60)
+    a, b = gpu.Batch(params), gpu.Batch(params)
+    for s in b.sensors:
+        s.sim_set_compaction(3)
+    print(f"batch compaction test: {[p.cells for p in params]}", flush=True)
+    for k in range(len(scheds[0])):
+        pos = np.array([s[k][1] for s in scheds])
+        quat = np.array([s[k][2] for s in scheds])
+        n = scheds[0][k][0]
+        for x in (a, b):
+            x.sim_batch_set_indenter_poses(pos, quat)
+        done = 0
+        while done < n:
+            m = min(5, n - done)
+            for x in (a, b):
+                x.sim_batch_step(m)
+            done += m
+    for x in (a, b):
+        x.sim_batch_synchronize()
+    for i in range(len(params)):
+        assert _same_state(a.sensors[i], b.sensors[i]), i
+        assert _stats_equal(a.sensors[i], b.sensors[i]), i
+    assert np.array_equal(a.sim_batch_heightmaps(16, 16), b.sim_batch_heightmaps(16, 16))
+    for x in (a, b):
+        x.close()
