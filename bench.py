@@ -48,9 +48,9 @@ ALG_BYTES_PER_PARTICLE_PASS = 192.0 + 7.0
 # rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) scaled by
 # the counters' reading of a copy of known size (fetched bytes = 2.0 x
 # FETCH_SIZE, written = 1.0 x WRITE_SIZE), with the default storage compaction
-# once per frame; None whenever the kernel has changed since the counters were
-# taken.
-PMC_TRAFFIC_BYTES = (2.0 * 159035 + 308822) * 1024
+# every 100 executed steps; None whenever the kernel has changed since the
+# counters were taken.
+PMC_TRAFFIC_BYTES = (2.0 * 152514 + 305138) * 1024
 
 
 def parse():
@@ -64,7 +64,7 @@ def parse():
     ap.add_argument("--tile", default=None, help="tile cells tx,ty,tz[,threads] of the binned order")
     ap.add_argument("--workload", choices=("sensor", "batch", "surrogate"), default="sensor")
     ap.add_argument("--graph", type=int, default=None, help="1/0: replay step sequences as HIP graphs")
-    ap.add_argument("--compact-every", type=int, default=200,
+    ap.add_argument("--compact-every", type=int, default=100,
                     help="executed steps between storage compactions of the sensor (0: never)")
     return ap.parse_args()
 
@@ -345,7 +345,7 @@ def main():
     roofline = {"bound": "hbm", "kernel": "k_g2p2g<false>", "achieved": round(achieved, 1),
                 "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                 # the counters were read on the default layout and tile only
-                "traffic": PMC_TRAFFIC_BYTES if args.compact_every == 200 and not args.tile else None,
+                "traffic": PMC_TRAFFIC_BYTES if args.compact_every == 100 and not args.tile else None,
                 "traffic_unit": "bytes/launch",
                 "avg_kernel_ms": round(avg_ms, 5),
                 "alg_bytes_per_launch": ALG_BYTES_PER_PARTICLE_PASS * n}

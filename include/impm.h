@@ -188,8 +188,9 @@ int sim_set_tile_threads(sim_t* s, int32_t tx, int32_t ty, int32_t tz, int32_t t
 int sim_set_graph(sim_t* s, int32_t on);
 
 /* Storage compaction (a layout choice; the method is unchanged).  every_steps > 0:
- * after a sim_step call in which at least every_steps executed steps have
- * accumulated, the particle state (all planes, cells, flags, id map) is moved
+ * once every_steps executed steps have accumulated (between the steps of an
+ * eager sim_step call, at the end of a graph-replayed or batched call), the
+ * particle state (all planes, cells, flags, id map) is moved
  * on the device into the binned order of the next step, round-robin over the
  * stencil base nodes inside each tile.  Without it, particles that cross tiles
  * leave a tile's data spread over other tiles' cache lines, and neighbouring

@@ -600,9 +600,10 @@ static void finish_call(sim_t* s, int32_t n_substeps, long long N) {
     }
 }
 
-// Move the state into the binned order of the next step (see sim_s).  The
-// order must be a permutation, so a latched device error is reported first.
-static int compact_storage(sim_t* s) {
+// Move the state into binned order `cur`, the order of the next step (see
+// sim_s).  The order must be a permutation, so a latched device error is
+// reported first.
+static int compact_storage(sim_t* s, int cur) {
     const size_t n = (size_t)s->n;
     if (!s->soa_alt) {
         HIPCHK(s, hipMalloc(&s->soa_alt, (size_t)NPLANES * n * sizeof(float)));
@@ -615,7 +616,7 @@ static int compact_storage(sim_t* s) {
     const KArgs a = kargs(s);
     long long e_new = a.e;   // kept if the kernel does not report a slot
     HIPCHK(s, hipMemcpyAsync(s->d_e_slot, &e_new, sizeof(long long), hipMemcpyHostToDevice, s->stream));
-    hipLaunchKernelGGL(k_compact, dim3(s->n_tiles), dim3(kBlock), 0, s->stream, a, s->cur, s->soa_alt, s->cell_alt,
+    hipLaunchKernelGGL(k_compact, dim3(s->n_tiles), dim3(kBlock), 0, s->stream, a, cur, s->soa_alt, s->cell_alt,
                        s->flags_alt, s->d_id_of, s->id_of_alt, s->d_e_slot);
     HIPCHK(s, hipGetLastError());
     HIPCHK(s, hipMemcpyAsync(&e_new, s->d_e_slot, sizeof(long long), hipMemcpyDeviceToHost, s->stream));
@@ -633,7 +634,7 @@ static int compact_storage(sim_t* s) {
 
 static int after_call(sim_t* s, long long N) {
     s->since_compact += N;
-    if (s->compact_every > 0 && s->since_compact >= s->compact_every) return compact_storage(s);
+    if (s->compact_every > 0 && s->since_compact >= s->compact_every) return compact_storage(s, s->cur);
     return SIM_OK;
 }
 
@@ -966,9 +967,15 @@ int sim_step(sim_t* s, int32_t n_substeps) {
         sbin = cur;
         cur ^= 1;
         g += 1;
+        // eager calls compact between their steps as well; the launches of
+        // the next step read the moved state through the refreshed record
+        s->since_compact += 1;
+        if (j + 1 < N && s->compact_every > 0 && s->since_compact >= s->compact_every) {
+            if (int rc2 = compact_storage(s, cur)) return rc2;
+        }
     }
     finish_call(s, n_substeps, N);
-    return after_call(s, N);
+    return after_call(s, 0);
 }
 
 int sim_synchronize(sim_t* s) {
@@ -1530,7 +1537,7 @@ int sim_batch_step(sim_batch_t* b, int32_t n_substeps) {
                 BHIPCHK(b, hipStreamSynchronize(b->stream));
                 synced = true;
             }
-            const int rc2 = compact_storage(s);
+            const int rc2 = compact_storage(s, s->cur);
             if (rc2) return bfail(b, rc2, "sensor " + std::to_string(i) + ": " + s->err);
         }
     }
