@@ -605,13 +605,13 @@ static void finish_call(sim_t* s, int32_t n_substeps, long long N) {
 // reported first.
 static int compact_storage(sim_t* s, int cur) {
     const size_t n = (size_t)s->n;
-    if (!s->soa_alt) {
-        HIPCHK(s, hipMalloc(&s->soa_alt, (size_t)NPLANES * n * sizeof(float)));
-        HIPCHK(s, hipMalloc(&s->cell_alt, n * 4));
-        HIPCHK(s, hipMalloc(&s->flags_alt, n));
-        HIPCHK(s, hipMalloc(&s->id_of_alt, n * 4));
-        HIPCHK(s, hipMalloc(&s->d_e_slot, sizeof(long long)));
-    }
+    // each buffer on its own, so that a call after a failed allocation retries
+    // exactly the missing ones
+    if (!s->soa_alt) HIPCHK(s, hipMalloc(&s->soa_alt, (size_t)NPLANES * n * sizeof(float)));
+    if (!s->cell_alt) HIPCHK(s, hipMalloc(&s->cell_alt, n * 4));
+    if (!s->flags_alt) HIPCHK(s, hipMalloc(&s->flags_alt, n));
+    if (!s->id_of_alt) HIPCHK(s, hipMalloc(&s->id_of_alt, n * 4));
+    if (!s->d_e_slot) HIPCHK(s, hipMalloc(&s->d_e_slot, sizeof(long long)));
     if (int rc = check_device_error(s)) return rc;
     const KArgs a = kargs(s);
     long long e_new = a.e;   // kept if the kernel does not report a slot
