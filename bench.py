@@ -9,12 +9,16 @@ normal over the remaining 1500 substeps (dt = 2e-5 s per configured substep,
 4 executed steps each for stability), sticking contact; a 256 x 256 surface
 height map every 50 substeps.
 
-A benchmark "step" is one configured substep of that schedule (all executed
-steps, every pass of the relative-rest loop, the commit and the binning),
-with the height map of each 50-substep frame included.  The reported value is
-particle-updates per second: particles x executed steps / wall time.
+A benchmark "step" is one height-map frame of that schedule: 50 configured
+substeps (200 executed steps, every pass of the relative-rest loop, the commit
+and the binning of each) followed by the 256 x 256 height map.  The schedule
+has 40 frames (10 of press, 30 of slip and rotation); `--steps K` times frames
+0..K-1 from the initial state, and frames past the 40th hold the final pose.
+Warm-up frames run on a throw-away sensor from the same initial state.  The
+reported value is particle-updates per second: particles x executed steps /
+wall time.
 
-    python bench.py [--gpus 1] [--steps 2000] [--warmup 50]
+    python bench.py [--gpus 1] [--steps 40] [--warmup 2]
     python bench.py --workload batch       # 64 batched sensors, 500 substeps
     python bench.py --workload surrogate   # surrogate training and serving vs IMPM
     python bench.py --copy-calibration     # 1 GiB device copy for counter scaling
@@ -24,7 +28,8 @@ The batch workload: 64 independent sensors of 32x32x8 to 96x96x24 cells (dx
 capsule, rounded-box and Perlin height-field indenters pressed 0.3-1.5 mm, then
 slipped 0-3 mm and rotated up to 45 degrees over 500 substeps (2 executed steps
 each); tile shapes from the autotuner per sensor size; every call of the batch
-is one HIP graph launch.  A step is one configured substep of all 64 sensors.
+is one HIP graph launch.  A step is one segment of the schedule (its poses
+change at segment ends) for all 64 sensors.
 """
 import argparse
 import json
@@ -48,16 +53,29 @@ ALG_BYTES_PER_PARTICLE_PASS = 192.0 + 7.0
 # rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) scaled by
 # the counters' reading of a copy of known size (fetched bytes = 2.0 x
 # FETCH_SIZE, written = 1.0 x WRITE_SIZE), with the default storage compaction
-# every 100 executed steps; None whenever the kernel has changed since the
-# counters were taken.
+# every 100 executed steps.  PMC_SOURCE_SHA is the SHA-256 (first 16 hex digits)
+# of the kernel sources the counters were read on; the figure is reported only
+# while the sources still hash to it.
 PMC_TRAFFIC_BYTES = (2.0 * 152514 + 305138) * 1024
+PMC_SOURCE_SHA = None
+KERNEL_SOURCES = ("paper_2405_02914_amd/csrc/impm_kernels.hip", "paper_2405_02914_amd/csrc/impm_device.h")
 
 
-def parse():
+def kernel_source_sha():
+    """SHA-256 (first 16 hex digits) of the IMPM kernel sources."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def parse(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=40, help="height-map frames timed (50 substeps each)")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed frames on a throw-away sensor")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=4, help="oracle executed steps timed")
     ap.add_argument("--copy-calibration", action="store_true")
@@ -66,7 +84,7 @@ def parse():
     ap.add_argument("--graph", type=int, default=None, help="1/0: replay step sequences as HIP graphs")
     ap.add_argument("--compact-every", type=int, default=100,
                     help="executed steps between storage compactions of the sensor (0: never)")
-    return ap.parse_args()
+    return ap.parse_args(argv)
 
 
 def copy_calibration():
@@ -85,53 +103,40 @@ def copy_calibration():
     print(json.dumps({"bytes_read_per_kernel": 4 * n, "bytes_written_per_kernel": 4 * n}))
 
 
-def run_frames(sim, segs, first, count, hm_out):
-    """Advance `count` configured substeps starting at substep `first` of the
-    schedule; a height map at every frame boundary."""
+def frame_plan(segs, count):
+    """The first `count` height-map frames of the schedule `segs` (a list of
+    (n_substeps, target_pos, target_quat), one entry per frame); frames past its
+    end hold the final pose for FRAME substeps each."""
+    if count < 0:
+        raise ValueError("the frame count must be >= 0")
+    plan = list(segs[:count])
+    while len(plan) < count:
+        plan.append((FRAME, segs[-1][1], segs[-1][2]))
+    return plan
+
+
+def run_plan(sim, plan, hm_out):
+    """Advance the sensor through `plan`, taking the height map after each frame.
+    Returns the configured substeps advanced."""
     done = 0
-    k = first
-    # locate the segment containing substep `first`
-    bounds = []
-    s0 = 0
-    for n, pos, q in segs:
-        bounds.append((s0, s0 + n, pos, q))
-        s0 += n
-    total = s0
-    while done < count:
-        if k >= total:                      # past the schedule: hold the final pose
-            n = min(FRAME, count - done)
-            sim.sim_set_indenter_pose(bounds[-1][2], bounds[-1][3])
-            sim.sim_step(n)
-            sim.sim_surface_heightmap(HM, HM, out=hm_out)
-            done += n
-            k += n
-            continue
-        for a, b, pos, q in bounds:
-            if a <= k < b:
-                n = b - k
-                if k != a or n > count - done:
-                    raise ValueError("steps must cover whole frames of the schedule")
-                sim.sim_set_indenter_pose(pos, q)
-                sim.sim_step(n)
-                sim.sim_surface_heightmap(HM, HM, out=hm_out)
-                done += n
-                k += n
-                break
+    for n, pos, q in plan:
+        sim.sim_set_indenter_pose(pos, q)
+        sim.sim_step(n)
+        sim.sim_surface_heightmap(HM, HM, out=hm_out)
+        done += n
     return done
 
 
 def run_batch_segments(b, scheds, count):
-    """Advance every sensor of the batch `count` substeps along its schedule (the
-    schedules share their segment boundaries)."""
-    done, k = 0, 0
-    while done < count and k < len(scheds[0]):
+    """Advance every sensor of the batch through the first `count` segments of its
+    schedule (the schedules share their segment boundaries).  Returns the
+    configured substeps advanced."""
+    done = 0
+    for k in range(min(count, len(scheds[0]))):
         n = scheds[0][k][0]
-        if n > count - done:
-            raise ValueError("steps must cover whole segments of the schedule")
         b.sim_batch_set_indenter_poses([s[k][1] for s in scheds], [s[k][2] for s in scheds])
         b.sim_batch_step(n)
         done += n
-        k += 1
     return done
 
 
@@ -142,7 +147,7 @@ def bench_batch(args):
     torch.cuda.set_device(0)
     params, scheds = W.config3()
     total = sum(s[0] for s in scheds[0])
-    steps = min(args.steps, total)
+    steps = min(args.steps, len(scheds[0]))      # schedule segments timed
     # autotuned tile shape per sensor size class
     tiles, tuned = [], {}
     for p in params:
@@ -156,7 +161,7 @@ def bench_batch(args):
         w.sim_batch_set_graph(graph)
         for m in w.sensors:
             m.sim_set_compaction(args.compact_every)
-        run_batch_segments(w, scheds, min(args.warmup, total))
+        run_batch_segments(w, scheds, args.warmup)
         w.sim_batch_synchronize()
         w.close()
         del w
@@ -182,13 +187,13 @@ def bench_batch(args):
         "metric": "IMPM particle-updates/s",
         "value": upd / wall,
         "unit": "particle-updates/s",
-        "n_gpus": 1, "steps": done, "warmup": args.warmup,
-        "ms_per_step": 1e3 * wall / done,
+        "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / max(steps, 1),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{len(params)} batched IMPM sensors, 32x32x8 to 96x96x24 cells, dx 0.5 mm, "
                                f"{sum(ns)} particles, mixed sphere/capsule/box/height-field indenters, "
-                               f"press-slip-rotate over {total} substeps",
+                               f"press-slip-rotate over {total} substeps; timed substeps 0-{done - 1}",
                    "particles": sum(ns), "subcycle": params[0].subcycle, "graph": graph,
                    "compact_every": args.compact_every,
                    "passes_per_step": round(ppass / max(upd, 1), 3),
@@ -285,6 +290,8 @@ def bench_surrogate(args):
 
 def main():
     args = parse()
+    if args.steps < 1 or args.warmup < 0:
+        sys.exit("--steps must be >= 1 and --warmup >= 0")
     if args.copy_calibration:
         copy_calibration()
         return
@@ -302,20 +309,19 @@ def main():
     import torch
     from paper_2405_02914_amd import impm, workloads as W
 
-    if args.steps % FRAME or args.warmup % FRAME:
-        sys.exit("--steps and --warmup must be multiples of 50 (whole height-map frames)")
     torch.cuda.set_device(0)
     p = W.config2(subcycle=SUBCYCLE)
     segs = W.config2_schedule()
+    timed, warm = frame_plan(segs, args.steps), frame_plan(segs, args.warmup)
     hm = torch.empty(HM * HM, device="cuda", dtype=torch.float32)
 
     # warm-up on a throw-away sensor (allocation, code load, caches)
-    if args.warmup:
+    if warm:
         w = impm.Sim(p)
         w.sim_set_compaction(args.compact_every)
         if args.tile:
             w.sim_set_tile(*[int(v) for v in args.tile.split(",")])
-        run_frames(w, segs, 0, args.warmup, hm)
+        run_plan(w, warm, hm)
         w.sim_synchronize()
         w.close()
         del w
@@ -330,7 +336,7 @@ def main():
         sim.sim_profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    run_frames(sim, segs, 0, args.steps, hm)
+    substeps = run_plan(sim, timed, hm)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     sim.sim_synchronize()
@@ -344,8 +350,10 @@ def main():
     achieved = ALG_BYTES_PER_PARTICLE_PASS * n / (avg_ms * 1e-3) / 1e9   # nan when not profiled
     roofline = {"bound": "hbm", "kernel": "k_g2p2g<false>", "achieved": round(achieved, 1),
                 "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                # the counters were read on the default layout and tile only
-                "traffic": PMC_TRAFFIC_BYTES if args.compact_every == 100 and not args.tile else None,
+                # the counters were read on the default layout and tile only, and
+                # hold only for the kernel sources they were taken on
+                "traffic": (PMC_TRAFFIC_BYTES if args.compact_every == 100 and not args.tile
+                            and PMC_SOURCE_SHA == kernel_source_sha() else None),
                 "traffic_unit": "bytes/launch",
                 "avg_kernel_ms": round(avg_ms, 5),
                 "alg_bytes_per_launch": ALG_BYTES_PER_PARTICLE_PASS * n}
@@ -356,19 +364,21 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * wall / args.steps,
+        "ms_per_step": 1e3 * wall / max(args.steps, 1),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "IMPM sensor 128x128x32 cells dx 0.25 mm, 4194304 particles, capsule "
-                               "press 1.5 mm then slip 2 mm + rotate 30 deg, 256x256 height map "
-                               "every 50 substeps",
+                               "press 1.5 mm over substeps 0-499 then slip 2 mm + rotate 30 deg over "
+                               "500-1999, 256x256 height map every 50 substeps; a step is one "
+                               f"50-substep frame; timed substeps 0-{substeps - 1}",
+                   "timed_substeps": substeps,
                    "particles": n, "subcycle": SUBCYCLE, "tile": args.tile or "8,4,4",
                    "compact_every": args.compact_every, "executed_steps": steps_exec,
                    "passes": st["passes"], "limit_hits": st["limit_hits"],
-                   "particle_substeps_per_s": n * args.steps / wall,
+                   "particle_substeps_per_s": n * substeps / wall,
                    "particle_passes_per_s": n * st["passes"] / wall},
         "roofline": roofline,
     }
@@ -384,6 +394,7 @@ def main():
         o.step(subs)
         c1 = time.perf_counter()
         ex = o.counters()["steps"]
+        o.close()
         out["cpu_baseline"] = {"value": o.n * ex / (c1 - c0), "unit": "particle-updates/s",
                                "cores": 1, "kind": "oracle",
                                "sample": f"first {ex} executed steps of the same workload "

@@ -122,9 +122,17 @@ int sim_create(const sim_params* p, void* hip_stream, sim_t** out);
 /* Free every device buffer of the handle (NULL is ignored). */
 void sim_destroy(sim_t* s);
 
-/* Target pose reached at the end of the next sim_step: the indenter moves from
- * its current pose at constant linear and angular velocity (linear position
- * interpolation, rotation about one fixed axis). */
+/* Target pose reached at the end of the next sim_step (Fig. 2(B) and Sec. III:
+ * the motions -- press, slide, rotate -- are simulated step by step until the
+ * object reaches its target pose; Sec. IV-B: the object starts centred over
+ * the elastomer, and the distance and angle it has moved are measured at its
+ * calibration point x_o).  The indenter moves from its current pose at
+ * constant linear and angular velocity (linear position interpolation,
+ * rotation about one fixed axis); each executed step's pose is the object
+ * velocity that Algorithm 1 prescribes.  pos: 3 doubles (m, slab frame);
+ * quat_wxyz: 4 doubles, normalised by the call.  Host memory, read during the
+ * call only.  SIM_EINVAL on a NULL handle or pointer or a non-finite value;
+ * the pose is not changed then. */
 int sim_set_indenter_pose(sim_t* s, const double pos[3], const double quat_wxyz[4]);
 
 /* Enqueue n_substeps configured substeps (n_substeps * subcycle executed steps
@@ -134,11 +142,18 @@ int sim_step(sim_t* s, int32_t n_substeps);
 /* Wait for enqueued work; return SIM_ENUMERIC if a device error was latched. */
 int sim_synchronize(sim_t* s);
 
-/* Surface height map, H rows x W columns, row v and column u at the pixel
- * centre ((u+1/2) Lx/W, (v+1/2) Ly/H): slab height + the Shepard-normalised
- * 2-D quadratic B-spline average (pitch = pixel size) of the top surface
+/* Surface height map (Sec. IV-B: after the deformation the elastomer surface
+ * particles are read out and interpolated into a depth image; Fig. 2(C):
+ * interpolating the surface particles' depths gives the 3-D elastomer model).
+ * H rows x W columns, row v and column u at the pixel centre
+ * ((u+1/2) Lx/W, (v+1/2) Ly/H): slab height + the Shepard-normalised 2-D
+ * quadratic B-spline average (pitch = pixel size) of the top surface
  * particles' z displacement; pixels with no particle weight get the slab
- * height.  out: W*H floats, host or device memory. */
+ * height.  The paper's small depth perturbation, a meshing workaround, is not
+ * applied.  out: W*H floats (row-major by v), caller memory on the host
+ * (out_on_device = 0: the call synchronises the stream and reports latched
+ * device errors) or on the handle's device (enqueued only).  SIM_EINVAL on a
+ * NULL pointer or W, H < 1; out is written only on success. */
 int sim_surface_heightmap(sim_t* s, float* out, int32_t W, int32_t H, int32_t out_on_device);
 
 /* The same interpolation of the full displacement x - X_rest: H*W*3 floats. */

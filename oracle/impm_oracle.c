@@ -709,6 +709,13 @@ void orc_get_grid(const orc_sim *s, double *M, double *MG, double *V) {
     if (V) memcpy(V, s->V, s->n_nodes * 3 * sizeof(double));
 }
 
+/* Overwrite the grid mass and momentum (test hook: the boundary and contact
+ * rules of the grid update are then exercised on a chosen grid). */
+void orc_set_grid(orc_sim *s, const double *M, const double *MG) {
+    if (M) memcpy(s->M, M, s->n_nodes * sizeof(double));
+    if (MG) memcpy(s->MG, MG, s->n_nodes * 3 * sizeof(double));
+}
+
 void orc_get_counters(const orc_sim *s, int64_t *out4, double *last_r) {
     out4[0] = s->substeps; out4[1] = s->steps; out4[2] = s->passes; out4[3] = s->limit_hits;
     if (last_r) *last_r = s->last_r;

@@ -74,6 +74,7 @@ def lib():
             getattr(L, f).argtypes = [P, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_get_rest.argtypes = [P, C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_get_grid.argtypes = [P, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_set_grid.argtypes = [P, C.c_void_p, C.c_void_p]
         L.orc_get_counters.argtypes = [P, i64, C.POINTER(C.c_double)]
         L.orc_get_pose.argtypes = [P, dp]
         L.orc_get_xo.argtypes = [P, dp]
@@ -141,11 +142,14 @@ class OracleSim:
         self.nodes = tuple(int(v) for v in nn)
         self.n_nodes = int(np.prod(self.nodes))
 
-    def __del__(self):
+    def close(self):
         h = getattr(self, "h", None)
         if h:
             lib().orc_destroy(h)
             self.h = None
+
+    def __del__(self):
+        self.close()
 
     # -- driving
     def set_target_pose(self, pos, quat):
@@ -195,6 +199,10 @@ class OracleSim:
         M = np.zeros(self.n_nodes); MG = np.zeros((self.n_nodes, 3)); V = np.zeros((self.n_nodes, 3))
         lib().orc_get_grid(self.h, _ptr(M), _ptr(MG), _ptr(V))
         return M, MG, V
+
+    def set_grid(self, M=None, MG=None):
+        arrs = [None if a is None else np.ascontiguousarray(a, np.float64) for a in (M, MG)]
+        lib().orc_set_grid(self.h, *[_ptr(a) for a in arrs])
 
     def counters(self):
         c = np.zeros(4, np.int64); r = C.c_double()

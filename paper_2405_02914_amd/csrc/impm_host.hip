@@ -875,7 +875,8 @@ int sim_set_indenter_pose(sim_t* s, const double pos[3], const double quat_wxyz[
     if (!s || !pos || !quat_wxyz) return fail(s, SIM_EINVAL, "null argument");
     double q[4] = {quat_wxyz[0], quat_wxyz[1], quat_wxyz[2], quat_wxyz[3]};
     const double qn = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
-    if (!(qn > 0) || !std::isfinite(pos[0] + pos[1] + pos[2])) return fail(s, SIM_EINVAL, "bad pose");
+    if (!(qn > 0) || !std::isfinite(qn) || !std::isfinite(pos[0] + pos[1] + pos[2]))
+        return fail(s, SIM_EINVAL, "bad pose");
     quat_normalise(q);
     std::memcpy(s->tpos, pos, sizeof(s->tpos));
     std::memcpy(s->tquat, q, sizeof(s->tquat));
