@@ -96,6 +96,7 @@ typedef struct {
     int64_t e;                 /* calibration particle id */
     int64_t substeps, steps, passes, limit_hits;
     double last_r;
+    double min_margin;         /* min |r - threshold| / threshold over every test taken */
     int32_t *forced;           /* forced pass counts (parity replay), may be NULL */
     int64_t n_forced, forced_pos;
     int32_t *pass_log;         /* passes of each executed step, capacity log_cap */
@@ -449,6 +450,7 @@ orc_sim *orc_create(const orc_params *P) {
     quat_normalize(s->quat);
     memcpy(s->tpos, s->pos, sizeof(s->pos));
     memcpy(s->tquat, s->quat, sizeof(s->quat));
+    s->min_margin = INFINITY;
 
     /* calibration points: x_o the body-fixed lowest point, x_e the nearest particle */
     body_lowest_point(P, s->po_body);
@@ -642,6 +644,10 @@ static void impm_step(orc_sim *s, int64_t j, int64_t N, double h) {
             double dvx = ve[0] - vo_at[0], dvy = ve[1] - vo_at[1];
             double r = sqrt(dvx * dvx + dvy * dvy) / gnorm;
             s->last_r = r;
+            if (s->P.rest_threshold > 0.0) {
+                double m = fabs(r - s->P.rest_threshold) / s->P.rest_threshold;
+                if (m < s->min_margin) s->min_margin = m;
+            }
             stop = r <= s->P.rest_threshold;
             if (!stop && cnt >= s->P.rest_limit) { stop = 1; s->limit_hits += 1; }
         }
@@ -719,6 +725,21 @@ void orc_set_grid(orc_sim *s, const double *M, const double *MG) {
 void orc_get_counters(const orc_sim *s, int64_t *out4, double *last_r) {
     out4[0] = s->substeps; out4[1] = s->steps; out4[2] = s->passes; out4[3] = s->limit_hits;
     if (last_r) *last_r = s->last_r;
+}
+
+/* Closest approach of the relative-rest ratio to the threshold so far, as
+ * |r - threshold| / threshold (infinity before any test): near the threshold a
+ * single-precision evaluation may take the other branch. */
+double orc_min_margin(const orc_sim *s) { return s->min_margin; }
+
+/* Place the indenter at a pose (current and target) without stepping: a test
+ * hook that lets a state taken elsewhere continue from its pose. */
+void orc_set_pose(orc_sim *s, const double *pos, const double *quat) {
+    memcpy(s->pos, pos, 3 * sizeof(double));
+    memcpy(s->quat, quat, 4 * sizeof(double));
+    quat_normalize(s->quat);
+    memcpy(s->tpos, s->pos, sizeof(s->pos));
+    memcpy(s->tquat, s->quat, sizeof(s->quat));
 }
 
 void orc_get_pose(const orc_sim *s, double *pose7) {

@@ -75,6 +75,9 @@ def lib():
         L.orc_get_rest.argtypes = [P, C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_get_grid.argtypes = [P, C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_set_grid.argtypes = [P, C.c_void_p, C.c_void_p]
+        L.orc_min_margin.restype = C.c_double
+        L.orc_min_margin.argtypes = [P]
+        L.orc_set_pose.argtypes = [P, dp, dp]
         L.orc_get_counters.argtypes = [P, i64, C.POINTER(C.c_double)]
         L.orc_get_pose.argtypes = [P, dp]
         L.orc_get_xo.argtypes = [P, dp]
@@ -209,6 +212,13 @@ class OracleSim:
         lib().orc_get_counters(self.h, c, C.byref(r))
         return dict(substeps=int(c[0]), steps=int(c[1]), passes=int(c[2]),
                     limit_hits=int(c[3]), last_r=r.value)
+
+    def min_margin(self):
+        """min |r - threshold| / threshold over every relative-rest test so far."""
+        return float(lib().orc_min_margin(self.h))
+
+    def set_pose(self, pos, quat):
+        lib().orc_set_pose(self.h, np.asarray(pos, np.float64), np.asarray(quat, np.float64))
 
     def pose(self):
         o = np.zeros(7); lib().orc_get_pose(self.h, o); return o

@@ -17,6 +17,20 @@ __device__ __forceinline__ int flag_load(const int* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Each block copies its kernel record into registers before its first store:
+// loads taken then are free of clobbering stores, so their uniform addresses
+// go to the scalar unit once, instead of being re-fetched through vector memory
+// for every particle (the particle loop's stores might alias the record).  The
+// copy is only ever indexed with constants (pick() selects a buffer of a
+// double-buffered pair), so it stays in registers.
+__device__ __forceinline__ KArgs load_args(const BatchMap& m, int s) {
+    return m.args[__builtin_amdgcn_readfirstlane(s)];
+}
+template <class T>
+__device__ __forceinline__ T pick(const T (&pair)[2], int i) {
+    return i ? pair[1] : pair[0];
+}
+
 __device__ __forceinline__ int tile_linear(const KArgs& a, const int tc[3]) {
     return (tc[2] * a.NT[1] + tc[1]) * a.NT[0] + tc[0];
 }
@@ -184,9 +198,9 @@ __global__ __launch_bounds__(TL::NT) void k_p2g(BatchMap m, int cur) {
         s = batch_find(m.tile_base, m.n, t);
         t -= m.tile_base[s];
     }
-    const KArgs& a = m.args[s];
-    const gptr<const uint32_t> __restrict__ order = glb<const uint32_t>(a.order[cur]);
-    const gptr<const uint32_t> __restrict__ bstart = glb<const uint32_t>(a.bstart[cur]);
+    const KArgs a = load_args(m, s);
+    const gptr<const uint32_t> __restrict__ order = glb<const uint32_t>(pick(a.order, cur));
+    const gptr<const uint32_t> __restrict__ bstart = glb<const uint32_t>(pick(a.bstart, cur));
     const uint32_t s0 = bstart[t], cnt = bstart[t + 1] - s0;
     if (cnt == 0) return;
     int tc[3];
@@ -222,9 +236,9 @@ __device__ __forceinline__ void grid_block(const BatchMap& m, int gnb, int sbin,
         s = batch_find(m.node_base, m.n, nb);
         nb -= m.node_base[s];
     }
-    const KArgs& a = m.args[s];
+    const KArgs a = load_args(m, s);
     if (flag_load(&a.st->finished[pass])) return;
-    const gptr<const uint32_t> __restrict__ bstart = glb<const uint32_t>(a.bstart[sbin]);
+    const gptr<const uint32_t> __restrict__ bstart = glb<const uint32_t>(pick(a.bstart, sbin));
     const long long nid = nb * (long long)kBlock + threadIdx.x;
     const long long n_nodes = (long long)a.nn[0] * a.nn[1] * a.nn[2];
     if (nid >= n_nodes) return;
@@ -286,15 +300,15 @@ __device__ __forceinline__ void g2p2g_tile(const BatchMap& m, int gt, int cur, i
         s = batch_find(m.tile_base, m.n, t);
         t -= m.tile_base[s];
     }
-    const KArgs& a = m.args[s];
+    const KArgs a = load_args(m, s);
     if (flag_load(&a.st->finished[pass])) {
         // carry the flag to the next pass slot so that every later pass of the
         // step is skipped as well
         if (t == 0 && threadIdx.x == 0) a.st->finished[pass + 1] = 1;
         return;
     }
-    const gptr<const uint32_t> __restrict__ order = glb<const uint32_t>(a.order[cur]);
-    const gptr<const uint32_t> __restrict__ bstart = glb<const uint32_t>(a.bstart[cur]);
+    const gptr<const uint32_t> __restrict__ order = glb<const uint32_t>(pick(a.order, cur));
+    const gptr<const uint32_t> __restrict__ bstart = glb<const uint32_t>(pick(a.bstart, cur));
     extern __shared__ unsigned long long lds_u64[];
     unsigned long long* acc = lds_u64;                                   // 4 * PVOL
     float* gv = reinterpret_cast<float*>(lds_u64 + 4 * TL::AVOL);        // GVOL x (vx, vy, vz)
@@ -635,7 +649,7 @@ __global__ __launch_bounds__(TL::NT) void k_extra_passes(BatchMap m, int tiles, 
 // with cross-lane shifts, so a chunk costs two block barriers.
 __global__ __launch_bounds__(1024) void k_scan(BatchMap m, int next, int limit_slots) {
     const KArgs& a = m.args[blockIdx.x];
-    const gptr<uint32_t> __restrict__ bstart_next = glb(a.bstart[next]);
+    const gptr<uint32_t> __restrict__ bstart_next = glb(pick(a.bstart, next));
     __shared__ uint32_t wsum[16];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     if (tid < limit_slots) a.st->finished[tid] = 0;
@@ -688,11 +702,11 @@ __global__ __launch_bounds__(kBlock) void k_scatter(BatchMap m, int cur) {
         s = batch_find(m.tile_base, m.n, t);
         t -= m.tile_base[s];
     }
-    const KArgs& a = m.args[s];
-    const gptr<const uint32_t> __restrict__ order = glb<const uint32_t>(a.order[cur]);
-    const gptr<const uint32_t> __restrict__ bstart = glb<const uint32_t>(a.bstart[cur]);
-    const gptr<const uint32_t> __restrict__ bstart_next = glb<const uint32_t>(a.bstart[cur ^ 1]);
-    const gptr<uint32_t> __restrict__ order_next = glb(a.order[cur ^ 1]);
+    const KArgs a = load_args(m, s);
+    const gptr<const uint32_t> __restrict__ order = glb<const uint32_t>(pick(a.order, cur));
+    const gptr<const uint32_t> __restrict__ bstart = glb<const uint32_t>(pick(a.bstart, cur));
+    const gptr<const uint32_t> __restrict__ bstart_next = glb<const uint32_t>(pick(a.bstart, cur ^ 1));
+    const gptr<uint32_t> __restrict__ order_next = glb(pick(a.order, cur ^ 1));
     const uint32_t s0 = bstart[t], cnt = bstart[t + 1] - s0;
     if (cnt == 0) return;
     const int tid = threadIdx.x;
@@ -776,8 +790,8 @@ __global__ __launch_bounds__(kBlock) void k_compact(KArgs a, int cur, float* __r
                                                     uint32_t* __restrict__ id_dst, long long* __restrict__ e_out) {
     __shared__ uint32_t cnt[kMaxTileNodes];
     const int t = blockIdx.x, tid = threadIdx.x;
-    const gptr<uint32_t> order = glb(a.order[cur]);
-    const gptr<const uint32_t> bstart = glb<const uint32_t>(a.bstart[cur]);
+    const gptr<uint32_t> order = glb(pick(a.order, cur));
+    const gptr<const uint32_t> bstart = glb<const uint32_t>(pick(a.bstart, cur));
     const gptr<uint32_t> keys = glb(a.dirrank);
     const gptr<const float> soa = glb<const float>(a.soa);
     const size_t n = (size_t)a.n;

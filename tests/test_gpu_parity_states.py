@@ -1,0 +1,239 @@
+"""Parity with the FP64 oracle from deformed, in-contact states, with the
+device taking its own relative-rest decisions (Algorithm 1's repeat-until test
+and LIMIT), and of the literal every-pass variant of the loop.
+
+Each test hands one state to both sides (positions on the device's lattice,
+velocities, C and F - I rounded to FP32, the same indenter pose) and compares
+what each computes from it:
+  - one configured substep: normwise relative error <= 1e-5 per field;
+  - the pass count of every compared step, and the last relative-rest ratio
+    r at <= 1e-5 relative, wherever the oracle's r stayed at least 1e-4
+    (relative) away from the threshold (closer than that, FP32 and FP64 may
+    legitimately take different branches; the device then replays the
+    oracle's pass schedule instead);
+  - positions after many substeps within 1e-3 dx.
+"""
+import numpy as np
+import pytest
+
+from paper_2405_02914_amd import workloads as W
+from tests.test_gpu_parity import TOL_STEP, compare_states, rel
+
+pytestmark = pytest.mark.gpu
+
+MARGIN = 1e-4      # relative distance of r from the threshold below which branches may differ
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2405_02914_amd import impm
+    impm.lib()
+    return impm
+
+
+@pytest.fixture(scope="module")
+def ref(oracle_lib):
+    return oracle_lib
+
+
+def handoff(p, x, v, Cm, F):
+    """The state both sides start from: FP64 positions on the device lattice and
+    FP32-rounded v, C, G = F - I (exact in FP64 again)."""
+    xs = W.representable_positions(p, x)
+    v32, C32 = v.astype(np.float32), Cm.astype(np.float32)
+    G32 = (F - np.eye(3)[None]).astype(np.float32)
+    return xs, v32, C32, G32, np.eye(3)[None] + G32.astype(np.float64)
+
+
+@pytest.mark.parametrize("at", [50, 99])
+def test_single_substep_from_config1_oracle_state(gpu, ref, at):
+    """Config 1 (sphere pressed 1 mm over 100 substeps): the oracle's state at
+    substep `at` (deformed, in contact), then one substep on both sides."""
+    p = W.config1(subcycle=2)
+    x0, y0, z0 = p.pose0[:3]
+    depth = 1.0e-3
+    o = ref.OracleSim(p)
+    o.run_schedule([(at, (x0, y0, z0 - depth * at / 100), (1, 0, 0, 0))])
+    xs, v32, C32, G32, F = handoff(p, *o.state())
+    o.set_state(x=xs, v=v32, Cm=C32, F=F)
+    pose = (x0, y0, z0 - depth * at / 100)
+    print(f"[parity] config1 state at substep {at}: max |G| {np.abs(G32).max():.3e}", flush=True)
+    assert np.abs(G32).max() > 1e-3, "the state should be deformed"
+    g = gpu.Sim(p.replace(pose0=pose + (1.0, 0.0, 0.0, 0.0)))
+    g.sim_write_particles(xs, v32, C32, G32)
+    tgt = (x0, y0, z0 - depth * (at + 1) / 100)
+    g.sim_set_indenter_pose(tgt, (1, 0, 0, 0))
+    o.set_target_pose(tgt, (1, 0, 0, 0))
+    g.sim_step(1)
+    o.step(1)
+    compare_states(g, o, xs, f"config1 substep {at} -> {at + 1}", dx=p.dx)
+    assert g.sim_get_stats()["passes"] == 2 == o.counters()["passes"] - 2 * at
+
+
+def _slip_sensor():
+    p = W.small_sensor(cells=(16, 16, 6), radius=1.5e-3, subcycle=2)
+    c = np.array(p.pose0[:3])
+    press = (20, tuple(c + [0, 0, -0.4e-3]), (1, 0, 0, 0))
+    return p, c, press
+
+
+@pytest.mark.parametrize("k", [0, 2, 4])
+def test_device_pass_decision_from_oracle_state(gpu, ref, k):
+    """After a 0.4 mm press, the k-th substep of a slip with rotation (the loop
+    iterates, up to LIMIT passes).  Both sides start each compared substep from
+    the oracle's state; the device decides its passes itself."""
+    p, c, press = _slip_sensor()
+    o = ref.OracleSim(p)
+    g = gpu.Sim(p)                      # same initial pose: same calibration particle
+    o.enable_pass_log(1000)
+    o.run_schedule([press])
+
+    def tgt(j):
+        return tuple(c + [0.4e-3 * (j + 1) / 30, 0, -0.4e-3]), W.quat_about_z(20 * (j + 1) / 30)
+
+    for j in range(k):
+        o.set_target_pose(*tgt(j))
+        o.step(1)
+    pose = o.pose()
+    xs, v32, C32, G32, F = handoff(p, *o.state())
+    o.set_state(x=xs, v=v32, Cm=C32, F=F)
+    # the device's indenter: walk it to the same pose with the oracle's schedule
+    g.sim_debug_force_passes(o.pass_log())
+    g.run_schedule([press] + [(1,) + tgt(j) for j in range(k)])
+    st0 = g.sim_get_stats()
+    assert np.allclose(st0["pose"], pose, rtol=0, atol=1e-15)
+    g.sim_write_particles(xs, v32, C32, G32)
+    n_log = len(o.pass_log())
+    oc0 = o.counters()
+    o.set_target_pose(*tgt(k))
+    o.step(1)
+    g.sim_set_indenter_pose(*tgt(k))
+    g.sim_step(1)
+    oc, st = o.counters(), g.sim_get_stats()
+    passes_o = o.pass_log()[n_log:]
+    print(f"[parity] slip substep {k}: oracle passes {passes_o.tolist()} r {oc['last_r']:.6f}; "
+          f"device passes {st['passes'] - st0['passes']} r {st['last_r']:.6f}", flush=True)
+    assert passes_o.max() > 1 or k > 0
+    # the margin of the compared substep's tests alone
+    margin = _step_margin(ref, p, xs, v32, C32, F, pose, tgt(k))
+    if margin >= MARGIN:
+        assert st["passes"] - st0["passes"] == int(passes_o.sum())
+        assert st["limit_hits"] - st0["limit_hits"] == oc["limit_hits"] - oc0["limit_hits"]
+        assert abs(st["last_r"] - oc["last_r"]) <= 1e-5 * oc["last_r"]
+        compare_states(g, o, xs, f"slip substep {k}", dx=p.dx)
+    else:
+        pytest.skip(f"r came within {margin:.1e} of the threshold: branches may differ")
+
+
+def _step_margin(ref, p, xs, v32, C32, F, pose, tgt):
+    """Closest relative approach of r to the threshold during one substep from
+    the given state (a fresh oracle run of the same substep)."""
+    o = ref.OracleSim(p)
+    o.set_state(x=xs, v=v32, Cm=C32, F=F)
+    o.set_pose(pose[:3], pose[3:])
+    o.set_target_pose(*tgt)
+    o.step(1)
+    return o.min_margin()
+
+
+def test_free_running_loop_matches_oracle_away_from_threshold(gpu, ref):
+    """The whole press + slip + rotation schedule with the device deciding every
+    pass itself.  Where the oracle's r never came within 1e-4 (relative) of the
+    threshold, both must take the same passes; whenever they did, positions
+    must agree within 1e-3 dx and the last ratio within 1e-5."""
+    p, c, press = _slip_sensor()
+    segs = [press, (30, tuple(c + [0.4e-3, 0, -0.4e-3]), W.quat_about_z(20))]
+    o = ref.OracleSim(p)
+    o.enable_pass_log(10000)
+    o.run_schedule(segs)
+    g = gpu.Sim(p)
+    g.run_schedule(segs)
+    st, oc = g.sim_get_stats(), o.counters()
+    err = np.abs(g.sim_read_particles()[0] - o.state()[0]).max() / p.dx
+    print(f"[parity] free-running: margin {o.min_margin():.2e}, passes dev {st['passes']} "
+          f"oracle {oc['passes']}, limit hits dev {st['limit_hits']} oracle {oc['limit_hits']}, "
+          f"max|dx| {err:.2e} dx", flush=True)
+    assert st["steps"] == oc["steps"]
+    same = st["passes"] == oc["passes"] and st["limit_hits"] == oc["limit_hits"]
+    if o.min_margin() >= MARGIN:
+        assert same
+    if not same:
+        pytest.skip(f"r came within {o.min_margin():.1e} of the threshold and the pass counts differ")
+    assert abs(st["last_r"] - oc["last_r"]) <= 1e-5 * oc["last_r"]
+    assert err <= 1e-3
+
+
+def test_literal_every_pass_stress_variant(gpu, ref):
+    """stress_each_pass = 1: every pass of Algorithm 1 re-adds the elastic
+    impulse (the loop read literally).  On a short, gentle slip where it stays
+    valid: the device on the oracle's pass schedule within 1e-3 dx, and, away
+    from the threshold, the same passes when it decides itself."""
+    p, c, press = _slip_sensor()
+    p = p.replace(stress_each_pass=1)
+    segs = [press, (10, tuple(c + [0.05e-3, 0, -0.4e-3]), W.quat_about_z(3))]
+    o = ref.OracleSim(p)
+    o.enable_pass_log(10000)
+    o.run_schedule(segs)
+    sched = o.pass_log()
+    assert sched.max() > 1
+    g = gpu.Sim(p)
+    g.sim_debug_force_passes(sched)
+    g.run_schedule(segs)
+    xo = o.state()[0]
+    err = np.abs(g.sim_read_particles()[0] - xo).max() / p.dx
+    print(f"[parity] literal variant: passes {sched.sum()} (max {sched.max()}), max|dx| {err:.2e} dx, "
+          f"margin {o.min_margin():.2e}", flush=True)
+    assert err <= 1e-3
+    g2 = gpu.Sim(p)
+    g2.run_schedule(segs)
+    if o.min_margin() >= MARGIN:
+        assert g2.sim_get_stats()["passes"] == o.counters()["passes"]
+        assert np.abs(g2.sim_read_particles()[0] - xo).max() <= 1e-3 * p.dx
+
+
+@pytest.mark.slow
+def test_config2_full_size_first_slip_substep(gpu, ref):
+    """Config 2 at full size (4,194,304 particles) in the benchmark's launch
+    configuration (8 x 4 x 4 tiles, storage compaction every 100 executed
+    steps, the cooperative kernel for the passes after the first): the device
+    presses 1.5 mm over substeps 0-499, its state goes to the oracle, and both
+    run substep 500, the first of the slip and rotation, the device deciding
+    its passes itself (or replaying the oracle's where r came within 1e-4 of
+    the threshold)."""
+    p = W.config2(subcycle=4)
+    segs = W.config2_schedule()
+    g = gpu.Sim(p)
+    g.sim_set_compaction(100)
+    g.run_schedule(segs[:10])
+    g.sim_synchronize()
+    st0 = g.sim_get_stats()
+    assert st0["substeps"] == 500
+    x, v, Cm, G = g.sim_read_particles()
+    o = ref.OracleSim(p)
+    o.set_state(x=x, v=v, Cm=Cm, F=np.eye(3)[None] + G.astype(np.float64))
+    pose = st0["pose"]
+    o.set_pose(pose[:3], pose[3:])
+    n, pos, q = segs[10]
+    x0 = p.pose0[0]
+    tgt = ((pos[0] - x0) / n + x0, pos[1], pos[2]), W.quat_about_z(30.0 / 1500)
+    o.enable_pass_log(100)
+    o.set_target_pose(*tgt)
+    print(f"[parity] config2 substep 500 on the oracle ({o.n} particles)", flush=True)
+    o.step(1)
+    sched = o.pass_log()
+    margin = o.min_margin()
+    forced = margin < MARGIN
+    if forced:
+        g.sim_debug_force_passes(sched)
+    g.sim_set_indenter_pose(*tgt)
+    g.sim_step(1)
+    st, oc = g.sim_get_stats(), o.counters()
+    print(f"[parity] config2 substep 500: oracle passes {sched.tolist()} r {oc['last_r']:.6f} margin "
+          f"{margin:.2e}; device passes {st['passes'] - st0['passes']} r {st['last_r']:.6f}", flush=True)
+    assert st["passes"] - st0["passes"] == int(sched.sum())
+    if not forced:
+        assert abs(st["last_r"] - oc["last_r"]) <= 1e-5 * oc["last_r"]
+    compare_states(g, o, x, "config2 substep 500", dx=p.dx)
