@@ -156,6 +156,20 @@ int sim_synchronize(sim_t* s);
  * NULL pointer or W, H < 1; out is written only on success. */
 int sim_surface_heightmap(sim_t* s, float* out, int32_t W, int32_t H, int32_t out_on_device);
 
+/* The height map of sim_surface_heightmap without any device allocation, for
+ * callers that cannot allocate: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  The pixel accumulators live in a
+ * fixed library workspace of 512 * 512 pixels (8 MiB per device, held until
+ * the process ends) instead of the handle's own buffer; W * H above that is
+ * SIM_EINVAL with a message, before any work is enqueued.  out_device: W*H
+ * floats of device memory on the handle's device, written by kernels enqueued
+ * on the handle's stream (the call does not synchronise; latched device
+ * errors surface at the next synchronising call).  Results are bitwise those
+ * of sim_surface_heightmap.  Every call on one GPU shares that workspace and
+ * clears it first: calls that overlap on one GPU (two streams, or two host
+ * threads) race and give undefined maps; serialise them. */
+int sim_surface_heightmap_noalloc(sim_t* s, float* out_device, int32_t W, int32_t H);
+
 /* The same interpolation of the full displacement x - X_rest: H*W*3 floats. */
 int sim_surface_displacement(sim_t* s, float* out, int32_t W, int32_t H, int32_t out_on_device);
 

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -638,6 +639,39 @@ static int after_call(sim_t* s, long long N) {
     return SIM_OK;
 }
 
+// Workspace of sim_surface_heightmap_noalloc: the raster's fixed-point pixel
+// accumulators (4 per pixel), a fixed device array instead of the handle's
+// lazily allocated buffer.  Every device the library runs on holds its own
+// copy until the process ends.  In host code `scratch` names a host-side
+// stand-in, not device memory: the kernels only ever receive the per-device
+// address that hipGetSymbolAddress returns for it.
+constexpr long long kNoAllocMaxPixels = 512LL * 512LL;
+static __device__ __align__(256) unsigned long long scratch[kNoAllocMaxPixels * 4];   // 8 MiB
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static unsigned long long* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on `dev` (looked up once per device, with
+// that device current).
+static hipError_t scratch_address(int dev, unsigned long long** out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int prev = 0;
+        hipError_t e = hipGetDevice(&prev);
+        if (e != hipSuccess) return e;
+        if (prev != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (prev != dev) (void)hipSetDevice(prev);
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = static_cast<unsigned long long*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
 // ------------------------------------------------------------------ C ABI
 
 extern "C" {
@@ -1065,6 +1099,45 @@ int sim_indenter_depthmap(sim_t* s, float* out, int32_t W, int32_t H, double sca
 
 int sim_surface_heightmap(sim_t* s, float* out, int32_t W, int32_t H, int32_t out_on_device) {
     return surface_raster(s, out, W, H, out_on_device, 0);
+}
+
+// Allocation-free height map: the raster of sim_surface_heightmap with its
+// accumulators in the fixed workspace `scratch` (through its per-device address).
+int sim_surface_heightmap_noalloc(sim_t* s, float* out_device, int32_t W, int32_t H) {
+    if (!s || !out_device || W < 1 || H < 1) return fail(s, SIM_EINVAL, "bad raster arguments");
+    const long long npix = (long long)W * H;
+    if (npix > kNoAllocMaxPixels)
+        return fail(s, SIM_EINVAL, "sim_surface_heightmap_noalloc: W*H = " + std::to_string(npix) +
+                                       " exceeds its fixed workspace of " + std::to_string(kNoAllocMaxPixels) +
+                                       " pixels");
+    if (s->device < 0 || s->device >= kMaxDevices) return fail(s, SIM_EINVAL, "device ordinal out of range");
+    unsigned long long* acc = nullptr;
+    HIPCHK(s, scratch_address(s->device, &acc));
+    int prev = 0;
+    HIPCHK(s, hipGetDevice(&prev));
+    if (prev != s->device) HIPCHK(s, hipSetDevice(s->device));
+    KArgs a = kargs(s);
+    SurfArgs sa;
+    sa.W = W; sa.H = H; sa.Nx = s->P.cells[0]; sa.Ny = s->P.cells[1]; sa.m = s->m;
+    sa.pad_l = s->P.pad_lateral; sa.pad_b = s->P.pad_bottom;
+    sa.pitch_x = (double)s->P.cells[0] / (double)W;
+    sa.pitch_y = (double)s->P.cells[1] / (double)H;
+    sa.dx = (float)s->P.dx;
+    sa.n = s->n;
+    sa.rest_r = s->surf_rest;
+    sa.id_of = s->d_id_of;
+    sa.acc = acc;
+    // the accumulators keep the previous call's sums: clear them with a kernel
+    // (no memset node, so a captured graph of these launches replays correctly)
+    hipLaunchKernelGGL(k_fill, dim3(std::min<long long>((npix * 8 + 255) / 256, 4096)), dim3(256), 0, s->stream,
+                       reinterpret_cast<float*>(acc), npix * 8, 0.0f);
+    hipLaunchKernelGGL(k_surface_accum, dim3((unsigned)((s->n + 255) / 256)), dim3(256), 0, s->stream, a, sa);
+    hipLaunchKernelGGL(k_surface_finish, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, s->stream, acc,
+                       (int)npix, (float)(s->P.cells[2] * s->P.dx), (float)s->P.dx, 0, out_device);
+    const hipError_t e = hipGetLastError();
+    if (prev != s->device) (void)hipSetDevice(prev);
+    HIPCHK(s, e);
+    return SIM_OK;
 }
 
 int sim_surface_displacement(sim_t* s, float* out, int32_t W, int32_t H, int32_t out_on_device) {

@@ -59,7 +59,7 @@ EXPORTS = ("sim_params_default", "sim_create", "sim_destroy", "sim_set_indenter_
            "sim_batch_set_indenter_poses", "sim_batch_step", "sim_batch_synchronize",
            "sim_batch_heightmaps", "sim_batch_displacements", "sim_batch_last_error",
            "sim_autotune_tile", "sim_set_graph", "sim_set_compaction", "sim_batch_set_graph",
-           "sim_indenter_depthmap", "sim_batch_depthmaps")
+           "sim_indenter_depthmap", "sim_batch_depthmaps", "sim_surface_heightmap_noalloc")
 
 _lib = None
 
@@ -83,6 +83,7 @@ def lib():
     L.sim_synchronize.argtypes = [vp]
     L.sim_surface_heightmap.argtypes = [vp, fp, i32, i32, i32]
     L.sim_surface_displacement.argtypes = [vp, fp, i32, i32, i32]
+    L.sim_surface_heightmap_noalloc.argtypes = [vp, fp, i32, i32]
     L.sim_get_stats.argtypes = [vp, C.POINTER(sim_stats)]
     L.sim_num_particles.argtypes = [vp, C.POINTER(C.c_int64)]
     L.sim_grid_dims.argtypes = [vp, C.POINTER(C.c_int32)]
@@ -212,6 +213,12 @@ class Sim:
         o = np.zeros((H, W), np.float32)
         self._chk(lib().sim_indenter_depthmap(self.h, _p(o), W, H, float(scale), 0))
         return o
+
+    def sim_surface_heightmap_noalloc(self, W, H, out):
+        """Height map into the device tensor `out` (H*W floats) without a device
+        allocation (fixed library workspace of 512*512 pixels)."""
+        self._chk(lib().sim_surface_heightmap_noalloc(self.h, C.c_void_p(out.data_ptr()), W, H))
+        return out
 
     def sim_surface_heightmap(self, W, H, out=None):
         """Host numpy (H, W) unless `out` is a device tensor of H*W floats."""
