@@ -21,6 +21,8 @@ wall time.
     python bench.py [--gpus 1] [--steps 40] [--warmup 2]
     python bench.py --workload batch       # 64 batched sensors, 500 substeps
     python bench.py --workload surrogate   # surrogate training and serving vs IMPM
+    python bench.py --workload protocol    # the paper's slip / rotation protocol, IMPM vs normal MPM
+    python bench.py --workload object      # object particles against the grid collider, same trajectory
     python bench.py --copy-calibration     # 1 GiB device copy for counter scaling
 
 The batch workload: 64 independent sensors of 32x32x8 to 96x96x24 cells (dx
@@ -77,10 +79,10 @@ def parse(argv=None):
     ap.add_argument("--steps", type=int, default=40, help="height-map frames timed (50 substeps each)")
     ap.add_argument("--warmup", type=int, default=2, help="untimed frames on a throw-away sensor")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=4, help="oracle executed steps timed")
+    ap.add_argument("--cpu-steps", type=int, default=8, help="oracle executed steps timed on all threads")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--tile", default=None, help="tile cells tx,ty,tz[,threads] of the binned order")
-    ap.add_argument("--workload", choices=("sensor", "batch", "surrogate"), default="sensor")
+    ap.add_argument("--workload", choices=("sensor", "batch", "surrogate", "protocol", "object"), default="sensor")
     ap.add_argument("--graph", type=int, default=None, help="1/0: replay step sequences as HIP graphs")
     ap.add_argument("--compact-every", type=int, default=100,
                     help="executed steps between storage compactions of the sensor (0: never)")
@@ -288,6 +290,149 @@ def bench_surrogate(args):
     print(json.dumps(out), flush=True)
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(p, segs, exec_steps):
+    """The FP64 oracle timed on the host cores over the first executed steps of
+    the same workload: once with all the threads the host grants (OMP_NUM_THREADS,
+    else every core) and once on one thread."""
+    from oracle import impm_ref
+    cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+
+    def timed(threads, steps):
+        o = impm_ref.OracleSim(p)
+        o.set_threads(threads)
+        n0, pos, q = segs[0]
+        subs = max(1, steps // SUBCYCLE)
+        a = subs / n0
+        o.set_target_pose(tuple(p0 + (p1 - p0) * a for p0, p1 in zip(p.pose0[:3], pos)), q)
+        c0 = time.perf_counter()
+        o.step(subs)
+        sec = time.perf_counter() - c0
+        ex = o.counters()["steps"]
+        n = o.n
+        o.close()
+        return n * ex / sec, ex, sec
+
+    v_all, ex_all, s_all = timed(cores, max(exec_steps, SUBCYCLE))
+    v_one, ex_one, s_one = timed(1, SUBCYCLE)
+    return {"value": v_all, "unit": "particle-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {ex_all} executed steps of the same workload (4194304 particles), FP64, "
+                      f"{cores} OpenMP threads, {s_all:.1f} s; one thread: {ex_one} steps in {s_one:.1f} s",
+            "value_1_thread": v_one, "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+
+
+def bench_object(args):
+    """The full-resolution trajectory with the object represented by particles
+    (the paper's description) against the rigid grid collider: the height maps
+    of every frame compared, for object particles as dense as the elastomer and
+    100 times denser, and the particle-updates/s of each."""
+    import numpy as np
+    import torch
+    from paper_2405_02914_amd import impm, workloads as W
+    torch.cuda.set_device(0)
+    base = W.config2(subcycle=SUBCYCLE)
+    plan = frame_plan(W.config2_schedule(), min(args.steps, 40))
+    hm = torch.empty(HM * HM, device="cuda", dtype=torch.float32)
+    runs = {}
+    for name, p in (("collider", base),
+                    ("particles_rho1", base.replace(object_mode=1, object_density=base.rho)),
+                    ("particles_rho100", base.replace(object_mode=1, object_density=100 * base.rho))):
+        s = impm.Sim(p)
+        s.sim_set_compaction(args.compact_every)
+        maps = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for n, pos, q in plan:
+            s.sim_set_indenter_pose(pos, q)
+            s.sim_step(n)
+            s.sim_surface_heightmap(HM, HM, out=hm)
+            maps.append(hm.clone())
+        s.sim_synchronize()
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        st = s.sim_get_stats()
+        s.close()
+        depth = np.stack([(p.height - m.cpu().numpy()) * 1e3 for m in maps])      # mm into the slab
+        runs[name] = {"depth": depth, "updates_per_s": p.n_particles * st["steps"] / sec,
+                      "passes_per_step": st["passes"] / st["steps"], "limit_hits": st["limit_hits"]}
+    ref = runs["collider"]["depth"]
+    table = {}
+    for name, r in runs.items():
+        d = r["depth"] - ref
+        table[name] = {"max_depth_mm": [round(float(x), 4) for x in r["depth"].reshape(len(plan), -1).max(1)],
+                       "rms_vs_collider_mm": round(float(np.sqrt((d ** 2).mean())), 5),
+                       "max_vs_collider_mm": round(float(np.abs(d).max()), 5),
+                       "particle_updates_per_s": r["updates_per_s"],
+                       "passes_per_step": round(r["passes_per_step"], 4), "limit_hits": r["limit_hits"]}
+    out = {
+        "metric": "IMPM particle-updates/s",
+        "value": runs["particles_rho100"]["updates_per_s"],
+        "unit": "particle-updates/s",
+        "n_gpus": 1, "steps": len(plan), "warmup": 0, "ms_per_step": None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "IMPM sensor 128x128x32 cells dx 0.25 mm, capsule press 1.5 mm then slip 2 mm + "
+                               f"rotate 30 deg, frames 0-{len(plan) - 1}: object particles (density 1x and 100x "
+                               "the elastomer's, 8 per cell, 2.5 mm cap) against the grid collider",
+                   "runs": table},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_protocol(args):
+    """The paper's slip and rotation protocol on the full-resolution slab with the
+    holed-disc indenter: press 0.5 mm, then slide leftward 1-5 mm or rotate
+    clockwise 5-45 degrees, IMPM against the plain method; a height map after
+    every increment.  Reports the hole and trace depths of each map."""
+    import torch
+    from paper_2405_02914_amd import protocol as P
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    slip = P.protocol("slip", sign=-1.0)
+    rot = P.protocol("rotate", sign=-1.0, increments=9)
+    wall = time.perf_counter() - t0
+    runs = [slip["impm"], slip["normal"], rot["impm"], rot["normal"]]
+    upd = sum(r["particle_updates_per_s"] * r["seconds"] for r in runs)
+    gpu_s = sum(r["seconds"] for r in runs)
+
+    def table(res, key):
+        return {m: [round(row[key], 4) if key in row else None for row in res[m]["metrics"]]
+                for m in ("impm", "normal")}
+
+    out = {
+        "metric": "IMPM particle-updates/s",
+        "value": upd / gpu_s,
+        "unit": "particle-updates/s",
+        "n_gpus": 1, "steps": 4, "warmup": 0, "ms_per_step": 1e3 * gpu_s / 4,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "paper slip/rotation protocol: 128x128x32 cells dx 0.25 mm, holed-disc indenter "
+                               "(r 4 mm, hole r 1.5 mm), press 0.5 mm, slide leftward 0-5 mm in 1 mm steps / "
+                               "rotate clockwise 0-45 deg in 5 deg steps, IMPM and normal MPM",
+                   "wall_s": round(wall, 2),
+                   "slip_hole_contrast_mm": table(slip, "hole_contrast_mm"),
+                   "slip_trace_mm": table(slip, "trace_mm"),
+                   "slip_face_mm": table(slip, "face_mm"),
+                   "rotate_hole_mm": table(rot, "hole_mm"),
+                   "rotate_face_mm": table(rot, "face_mm"),
+                   "passes_per_step": {"slip_impm": slip["impm"]["passes_per_step"],
+                                       "rotate_impm": rot["impm"]["passes_per_step"]},
+                   "limit_hits": {"slip_impm": slip["impm"]["limit_hits"],
+                                  "rotate_impm": rot["impm"]["limit_hits"]}},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.steps < 1 or args.warmup < 0:
@@ -304,6 +449,12 @@ def main():
         return
     if args.workload == "surrogate":
         bench_surrogate(args)
+        return
+    if args.workload == "protocol":
+        bench_protocol(args)
+        return
+    if args.workload == "object":
+        bench_object(args)
         return
     import numpy as np
     import torch
@@ -384,21 +535,7 @@ def main():
     }
     sim.close()
     if not args.no_cpu_baseline:
-        from oracle import impm_ref
-        o = impm_ref.OracleSim(p)
-        n_, pos, q = segs[0]
-        subs = max(1, args.cpu_steps // SUBCYCLE)
-        a = subs / n_
-        o.set_target_pose(tuple(p0 + (p1 - p0) * a for p0, p1 in zip(p.pose0[:3], pos)), q)
-        c0 = time.perf_counter()
-        o.step(subs)
-        c1 = time.perf_counter()
-        ex = o.counters()["steps"]
-        o.close()
-        out["cpu_baseline"] = {"value": o.n * ex / (c1 - c0), "unit": "particle-updates/s",
-                               "cores": 1, "kind": "oracle",
-                               "sample": f"first {ex} executed steps of the same workload "
-                                         f"({o.n} particles), FP64, one thread, {c1 - c0:.1f} s"}
+        out["cpu_baseline"] = cpu_baseline(p, segs, args.cpu_steps)
     print(json.dumps(out), flush=True)
 
 

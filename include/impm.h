@@ -54,6 +54,7 @@ enum {
 enum { SIM_SHAPE_NONE = 0, SIM_SHAPE_SPHERE = 1, SIM_SHAPE_CAPSULE = 2, SIM_SHAPE_BOX = 3,
        SIM_SHAPE_HEIGHTFIELD = 4 };
 enum { SIM_MODE_IMPM = 0, SIM_MODE_PLAIN = 1 };
+enum { SIM_OBJECT_COLLIDER = 0, SIM_OBJECT_PARTICLES = 1 };
 
 /* Device error bits reported by sim_get_stats (SIM_ENUMERIC when non-zero). */
 enum { SIM_DEV_CFL = 1, SIM_DEV_NONFINITE = 2, SIM_DEV_DETF = 4 };
@@ -93,6 +94,23 @@ typedef struct {
     int32_t _pad2;
     double hf_half;            /* footprint radius and table half-width (m) */
     const double* hf;          /* hf_n * hf_n heights (m), row-major by y */
+    /* How the object acts on the elastomer (Sec. III-A):
+     *   SIM_OBJECT_COLLIDER: a rigid collider at the grid -- every node inside the
+     *     indenter takes its rigid velocity;
+     *   SIM_OBJECT_PARTICLES: the object is represented by particles, as the
+     *     paper describes it -- the body-fixed lattice points of spacing dx / m
+     *     (m^3 = ppc) inside the indenter, at most object_cap above its lowest
+     *     point and (at the initial pose) inside the grid; Algorithm 1 sets their
+     *     velocity to the object's motion before every exchange, they join the
+     *     particle-to-grid transfer with density object_density and no stress,
+     *     they move rigidly with the pose, and x_o is the object's bottom
+     *     particle (ties to the one farthest from the body z axis, then the
+     *     smallest body (x, y)).  They are internal: the particle calls below
+     *     address the elastomer particles only. */
+    int32_t object_mode;
+    int32_t _pad3;
+    double object_density;     /* kg/m^3, > 0 with SIM_OBJECT_PARTICLES */
+    double object_cap;         /* m, > 0 with SIM_OBJECT_PARTICLES */
 } sim_params;
 
 typedef struct {

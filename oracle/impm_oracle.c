@@ -22,10 +22,13 @@
  *   - X_g in Eq. (3)/(4) is the position of the summed node i; Eq. (7) sums V_g;
  *   - S_p is the fixed-corotated Kirchhoff stress tau = 2mu (F-R) F^T + lambda J (J-1) I,
  *     R the rotation of the polar decomposition of F (Newton iteration of Higham 1986);
- *   - the object is a rigid kinematic collider: every grid node inside the indenter
- *     at the start of the substep takes the rigid velocity (relative rest); its
- *     shape is a sphere, a capsule rod, a rounded box or a sampled height field
- *     (the solid above a bilinear surface, over a disc footprint);
+ *   - the object is either a rigid kinematic collider (every grid node inside the
+ *     indenter at the start of the substep takes the rigid velocity, relative
+ *     rest), or, as the paper describes it, a set of object particles whose
+ *     velocity is set to the object's prescribed motion before every exchange
+ *     (Algorithm 1) and which join the particle-to-grid transfer with their own
+ *     mass; its shape is a sphere, a capsule rod, a rounded box or a sampled
+ *     height field (the solid above a bilinear surface, over a disc footprint);
  *   - the relative-rest test uses the tangential (x,y) velocity 2-vectors,
  *     |v_e,t - v_o,t| <= threshold |v_o,t|, converged at once if |v_o,t| <= 1e-9 m/s;
  *   - F and x are committed once per substep with the final pass's C and v;
@@ -44,6 +47,13 @@
  * Coordinates: slab-local metres, origin at the slab's (-x,-y) bottom corner, z up.
  * Grid node (i,j,k) sits at ((i-pl) dx, (j-pl) dx, (k-pb) dx).
  * Compiled with -ffp-contract=off so every expression rounds as written.
+ *
+ * With one thread (the default) every loop is the plain serial loop above.
+ * orc_set_threads(s, T > 1) runs the same steps with OpenMP for timing on many
+ * cores: particle loops split into T contiguous ranges, the particle-to-grid
+ * sums taken per thread and added node by node in thread order (a fixed
+ * order, so a run is reproducible, but it rounds differently from the serial
+ * sums at the level of FP64 round-off).
  */
 #include <math.h>
 #include <stdint.h>
@@ -78,6 +88,13 @@ typedef struct {
     int32_t _pad2;
     double hf_half;
     const double *hf;
+    /* object representation: 0 = rigid collider at the grid, 1 = object particles
+     * on a body-fixed lattice of spacing dx / m (m^3 = ppc) filling the body up to
+     * object_cap above its lowest point, density object_density */
+    int32_t object_mode;
+    int32_t _pad3;
+    double object_density;
+    double object_cap;
 } orc_params;
 
 typedef struct {
@@ -103,6 +120,11 @@ typedef struct {
     int64_t log_cap, log_len;
     int32_t error;             /* 1: a stencil left the grid, 2: non-finite state, 3: det F <= 0 */
     double *hf_copy;           /* the height-field table (shape 4) */
+    int32_t threads;           /* OpenMP threads of the timing leg (1: the plain serial loops) */
+    double *Mt, *MGt;          /* per-thread node sums of the parallel particle-to-grid */
+    int64_t n_obj;             /* object particles (object_mode 1) */
+    double *obj_body, *obj_x;  /* n_obj*3 body-frame and world positions */
+    double m_obj;              /* mass of one object particle */
 } orc_sim;
 
 /* ---------------------------------------------------------------- SplitMix64 */
@@ -376,12 +398,87 @@ static int cube_root_ppc(int ppc) {
     return -1;
 }
 
+/* Body-frame bounding box of the indenter (half-extents about the body axis in
+ * x and y; z from the lowest point up to that plus `cap`). */
+static void body_box(const orc_params *P, double z_low, double cap, double lo[3], double hi[3]) {
+    double hx = 0.0, hy = 0.0;
+    if (P->shape == 1) { hx = P->radius; hy = P->radius; }
+    else if (P->shape == 2) { hx = P->half_length + P->radius; hy = P->radius; }
+    else if (P->shape == 3) { hx = P->half_extent[0]; hy = P->half_extent[1]; }
+    else if (P->shape == 4) { hx = P->hf_half; hy = P->hf_half; }
+    lo[0] = -hx; hi[0] = hx; lo[1] = -hy; hi[1] = hy;
+    lo[2] = z_low; hi[2] = z_low + cap;
+}
+
+/* Object particles (object_mode 1): the body-fixed lattice points
+ * ((i + 1/2) h, (j + 1/2) h, z_low + (k + 1/2) h), h = dx / m, that lie inside
+ * the indenter, at most object_cap above its lowest point, and (at the initial
+ * pose) with their whole stencil at least one node inside the grid.  Ordered
+ * by k, then j, then i.  Also sets x_o: the lowest object particle, ties to the
+ * one farthest from the body z axis, then to the smallest (x, y). */
+static void make_object_particles(orc_sim *s, int m) {
+    const orc_params *P = &s->P;
+    double low[3];
+    body_lowest_point(P, low);
+    double h = P->dx / (double)m;
+    double lo[3], hi[3];
+    body_box(P, low[2], P->object_cap, lo, hi);
+    int64_t ni = (int64_t)ceil(hi[0] / h), nj = (int64_t)ceil(hi[1] / h);
+    int64_t nk = (int64_t)ceil(P->object_cap / h);
+    double R[9];
+    quat_to_matrix(s->quat, R);
+    double off[3] = {(double)P->pad_lateral, (double)P->pad_lateral, (double)P->pad_bottom};
+    int64_t cap_n = 0, n = 0;
+    double *body = NULL;
+    for (int64_t k = 0; k < nk; ++k)
+        for (int64_t j = -nj; j < nj; ++j)
+            for (int64_t i = -ni; i < ni; ++i) {
+                double p[3] = {((double)i + 0.5) * h, ((double)j + 0.5) * h, low[2] + ((double)k + 0.5) * h};
+                if (body_phi(P, p) > 0.0) continue;
+                double w[3];
+                int ok = 1;
+                for (int a = 0; a < 3; ++a) {
+                    w[a] = s->pos[a] + R[3 * a] * p[0] + R[3 * a + 1] * p[1] + R[3 * a + 2] * p[2];
+                    double b = floor(w[a] / P->dx + off[a] - 0.5);
+                    if (b < 1.0 || b > (double)(s->nn[a] - 4)) ok = 0;
+                }
+                if (!ok) continue;
+                if (n == cap_n) {
+                    cap_n = cap_n ? 2 * cap_n : 4096;
+                    body = (double *)realloc(body, (size_t)cap_n * 3 * sizeof(double));
+                }
+                memcpy(body + 3 * n, p, sizeof(p));
+                ++n;
+            }
+    s->n_obj = n;
+    s->obj_body = body;
+    s->obj_x = (double *)malloc((size_t)(n > 0 ? n : 1) * 3 * sizeof(double));
+    for (int64_t q = 0; q < n; ++q)
+        for (int a = 0; a < 3; ++a)
+            s->obj_x[3 * q + a] = s->pos[a] + R[3 * a] * body[3 * q] + R[3 * a + 1] * body[3 * q + 1] +
+                                  R[3 * a + 2] * body[3 * q + 2];
+    s->m_obj = P->object_density * s->Vp;
+    /* x_o: the bottom particle of the object */
+    int found = 0;
+    double bz = 0.0, br2 = 0.0;
+    for (int64_t q = 0; q < n; ++q) {
+        const double *p = body + 3 * q;
+        double r2 = p[0] * p[0] + p[1] * p[1];
+        int better = !found || p[2] < bz ||
+                     (p[2] == bz && (r2 > br2 ||
+                                     (r2 == br2 && (p[0] < s->po_body[0] || (p[0] == s->po_body[0] && p[1] < s->po_body[1])))));
+        if (better) { found = 1; bz = p[2]; br2 = r2; memcpy(s->po_body, p, 3 * sizeof(double)); }
+    }
+}
+
 void orc_destroy(orc_sim *s) {
     if (!s) return;
     free(s->x); free(s->v); free(s->C); free(s->F); free(s->Xrest);
     free(s->bottom); free(s->surface); free(s->M); free(s->MG); free(s->V);
     free(s->forced); free(s->pass_log);
     free((void *)s->hf_copy);
+    free(s->obj_body); free(s->obj_x);
+    free(s->Mt); free(s->MGt);
     free(s);
 }
 
@@ -451,9 +548,12 @@ orc_sim *orc_create(const orc_params *P) {
     memcpy(s->tpos, s->pos, sizeof(s->pos));
     memcpy(s->tquat, s->quat, sizeof(s->quat));
     s->min_margin = INFINITY;
+    s->threads = 1;
 
-    /* calibration points: x_o the body-fixed lowest point, x_e the nearest particle */
+    /* calibration points: x_o the body-fixed lowest point (with object particles:
+     * the object's bottom particle), x_e the nearest elastomer particle */
     body_lowest_point(P, s->po_body);
+    if (P->object_mode == 1 && P->shape != 0) make_object_particles(s, m);
     double Rq[9], xo[3];
     quat_to_matrix(s->quat, Rq);
     for (int a = 0; a < 3; ++a)
@@ -472,12 +572,13 @@ orc_sim *orc_create(const orc_params *P) {
 
 /* Particle-to-grid, Eq. (1)-(4). h is the executed step length; with_stress = 0
  * drops the elastic momentum ME_i (Eq. 4) and transfers MM_i alone. */
-static void p2g_ex(orc_sim *s, double h, int with_stress) {
-    memset(s->M, 0, s->n_nodes * sizeof(double));
-    memset(s->MG, 0, s->n_nodes * 3 * sizeof(double));
+/* Particle-to-grid of elastomer particles [p0, p1) and object particles
+ * [q0, q1) into the node arrays M, MG (added to). */
+static void p2g_range(const orc_sim *s, double h, int with_stress, const step_pose *sp, int64_t p0, int64_t p1,
+                      int64_t q0, int64_t q1, double *M, double *MG) {
     const double dx = s->P.dx;
     const double coef = -4.0 * h / (dx * dx);
-    for (int64_t p = 0; p < s->n; ++p) {
+    for (int64_t p = p0; p < p1; ++p) {
         const double *xp = s->x + 3 * p, *vp = s->v + 3 * p, *Cp = s->C + 9 * p, *Fp = s->F + 9 * p;
         int base[3];
         double w[3][3];
@@ -494,18 +595,79 @@ static void p2g_ex(orc_sim *s, double h, int with_stress) {
                     double d[3] = {X[0] - xp[0], X[1] - xp[1], X[2] - xp[2]};
                     double wt = w[0][a] * w[1][b] * w[2][c];
                     int64_t ni = node_index(s, i, j, k);
-                    s->M[ni] += wt * s->mp;
+                    M[ni] += wt * s->mp;
                     for (int r = 0; r < 3; ++r)
-                        s->MG[3 * ni + r] += wt * (s->mp * vp[r] + (A[3 * r] * d[0] + A[3 * r + 1] * d[1] + A[3 * r + 2] * d[2]));
+                        MG[3 * ni + r] += wt * (s->mp * vp[r] + (A[3 * r] * d[0] + A[3 * r + 1] * d[1] + A[3 * r + 2] * d[2]));
                 }
+    }
+    /* Object particles (Algorithm 1: their velocities are set to the object's
+     * prescribed motion before the exchange): velocity v_o + w x (x_p - c) and
+     * affine matrix C = [w]x of the rigid motion, mass m_obj, no stress. */
+    if (sp && q1 > q0) {
+        const double *w = sp->w;
+        double Cr[9] = {0.0, -w[2], w[1], w[2], 0.0, -w[0], -w[1], w[0], 0.0};
+        for (int64_t q = q0; q < q1; ++q) {
+            const double *xp = s->obj_x + 3 * q;
+            double vq[3];
+            rigid_velocity(sp, xp, vq);
+            int base[3];
+            double wgt[3][3];
+            stencil(s, xp, base, wgt);
+            for (int c = 0; c < 3; ++c)
+                for (int b = 0; b < 3; ++b)
+                    for (int a = 0; a < 3; ++a) {
+                        int i = base[0] + a, j = base[1] + b, k = base[2] + c;
+                        double X[3];
+                        node_pos(s, i, j, k, X);
+                        double d[3] = {X[0] - xp[0], X[1] - xp[1], X[2] - xp[2]};
+                        double wt = wgt[0][a] * wgt[1][b] * wgt[2][c];
+                        int64_t ni = node_index(s, i, j, k);
+                        M[ni] += wt * s->m_obj;
+                        for (int r = 0; r < 3; ++r)
+                            MG[3 * ni + r] += wt * (s->m_obj * vq[r] +
+                                                    s->m_obj * (Cr[3 * r] * d[0] + Cr[3 * r + 1] * d[1] + Cr[3 * r + 2] * d[2]));
+                    }
+        }
     }
 }
 
-void orc_p2g(orc_sim *s, double h) { p2g_ex(s, h, 1); }
+/* Particle-to-grid, Eq. (1)-(4). h is the executed step length; with_stress = 0
+ * drops the elastic momentum ME_i (Eq. 4) and transfers MM_i alone; sp (may be
+ * NULL) is the step's pose, which the object particles' velocities follow. */
+static void p2g_ex(orc_sim *s, double h, int with_stress, const step_pose *sp) {
+    memset(s->M, 0, s->n_nodes * sizeof(double));
+    memset(s->MG, 0, s->n_nodes * 3 * sizeof(double));
+    const int T = s->threads;
+    if (T <= 1) {
+        p2g_range(s, h, with_stress, sp, 0, s->n, 0, sp ? s->n_obj : 0, s->M, s->MG);
+        return;
+    }
+    if (!s->Mt) {
+        s->Mt = (double *)malloc((size_t)T * s->n_nodes * sizeof(double));
+        s->MGt = (double *)malloc((size_t)T * s->n_nodes * 3 * sizeof(double));
+    }
+    const int64_t nq = sp ? s->n_obj : 0;
+#pragma omp parallel for num_threads(T) schedule(static, 1)
+    for (int t = 0; t < T; ++t) {
+        double *M = s->Mt + (size_t)t * s->n_nodes, *MG = s->MGt + (size_t)t * s->n_nodes * 3;
+        memset(M, 0, s->n_nodes * sizeof(double));
+        memset(MG, 0, s->n_nodes * 3 * sizeof(double));
+        p2g_range(s, h, with_stress, sp, s->n * t / T, s->n * (t + 1) / T, nq * t / T, nq * (t + 1) / T, M, MG);
+    }
+#pragma omp parallel for num_threads(T) schedule(static)
+    for (int64_t i = 0; i < s->n_nodes; ++i)
+        for (int t = 0; t < T; ++t) {
+            s->M[i] += s->Mt[(size_t)t * s->n_nodes + i];
+            for (int r = 0; r < 3; ++r) s->MG[3 * i + r] += s->MGt[((size_t)t * s->n_nodes + i) * 3 + r];
+        }
+}
+
+void orc_p2g(orc_sim *s, double h) { p2g_ex(s, h, 1, NULL); }
 
 /* Grid velocity, Eq. (5); relative-rest contact with the rigid indenter; zero
  * velocity on boundary nodes.  Flags let the invariant tests switch parts off. */
 void orc_grid_update_ex(orc_sim *s, const step_pose *sp, int use_contact, int use_bc) {
+#pragma omp parallel for num_threads(s->threads) schedule(static) if (s->threads > 1)
     for (int k = 0; k < s->nn[2]; ++k)
         for (int j = 0; j < s->nn[1]; ++j)
             for (int i = 0; i < s->nn[0]; ++i) {
@@ -529,6 +691,7 @@ void orc_grid_update_ex(orc_sim *s, const step_pose *sp, int use_contact, int us
 void orc_g2p_ex(orc_sim *s, int bottom_rule) {
     const double dx = s->P.dx;
     const double cc = 4.0 / (dx * dx);
+#pragma omp parallel for num_threads(s->threads) schedule(static) if (s->threads > 1)
     for (int64_t p = 0; p < s->n; ++p) {
         const double *xp = s->x + 3 * p;
         int base[3];
@@ -555,8 +718,19 @@ void orc_g2p_ex(orc_sim *s, int bottom_rule) {
     }
 }
 
+/* Object particles follow the rigid motion exactly: body point p at the pose
+ * `sp` (its centre and rotation). */
+static void place_object(orc_sim *s, const step_pose *sp) {
+    for (int64_t q = 0; q < s->n_obj; ++q) {
+        const double *p = s->obj_body + 3 * q;
+        for (int a = 0; a < 3; ++a)
+            s->obj_x[3 * q + a] = sp->c[a] + sp->R[3 * a] * p[0] + sp->R[3 * a + 1] * p[1] + sp->R[3 * a + 2] * p[2];
+    }
+}
+
 /* Particle movement, Eq. (8)-(9). */
 void orc_commit(orc_sim *s, double h) {
+#pragma omp parallel for num_threads(s->threads) schedule(static) if (s->threads > 1)
     for (int64_t p = 0; p < s->n; ++p) {
         double *Fp = s->F + 9 * p, *Cp = s->C + 9 * p;
         double Fn[9];
@@ -589,8 +763,35 @@ static void gather_velocity(const orc_sim *s, const double *xp, double *out) {
 /* ---------------------------------------------------------------- Algorithm 1 */
 
 /* Every particle's stencil inside the grid, its state finite and det F > 0. */
+static int check_particle(const orc_sim *s, int64_t p, const double *off) {
+    for (int a = 0; a < 3; ++a) {
+        double xg = s->x[3 * p + a] / s->P.dx + off[a];
+        if (!isfinite(xg) || !isfinite(s->v[3 * p + a])) return 2;
+        double b = floor(xg - 0.5);
+        if (b < 0.0 || b + 2.0 > (double)(s->nn[a] - 1)) return 1;
+    }
+    for (int k = 0; k < 9; ++k)
+        if (!isfinite(s->C[9 * p + k]) || !isfinite(s->F[9 * p + k])) return 2;
+    if (!(det3(s->F + 9 * p) > 0.0)) return 3;
+    return 0;
+}
+
 static int check_state(orc_sim *s) {
     double off[3] = {(double)s->P.pad_lateral, (double)s->P.pad_lateral, (double)s->P.pad_bottom};
+    if (s->threads > 1) {
+        /* the code of the first failing particle, as the serial scan finds it */
+        int64_t first = s->n;
+#pragma omp parallel for num_threads(s->threads) schedule(static) reduction(min : first)
+        for (int64_t p = 0; p < s->n; ++p)
+            if (p < first && check_particle(s, p, off)) first = p;
+        if (first < s->n) return check_particle(s, first, off);
+        for (int64_t q = 0; q < s->n_obj; ++q)
+            for (int a = 0; a < 3; ++a) {
+                double b = floor(s->obj_x[3 * q + a] / s->P.dx + off[a] - 0.5);
+                if (b < 0.0 || b + 2.0 > (double)(s->nn[a] - 1)) return 1;
+            }
+        return 0;
+    }
     for (int64_t p = 0; p < s->n; ++p) {
         for (int a = 0; a < 3; ++a) {
             double xg = s->x[3 * p + a] / s->P.dx + off[a];
@@ -602,6 +803,11 @@ static int check_state(orc_sim *s) {
             if (!isfinite(s->C[9 * p + k]) || !isfinite(s->F[9 * p + k])) return 2;
         if (!(det3(s->F + 9 * p) > 0.0)) return 3;
     }
+    for (int64_t q = 0; q < s->n_obj; ++q)
+        for (int a = 0; a < 3; ++a) {
+            double b = floor(s->obj_x[3 * q + a] / s->P.dx + off[a] - 0.5);
+            if (b < 0.0 || b + 2.0 > (double)(s->nn[a] - 1)) return 1;
+        }
     return 0;
 }
 
@@ -625,8 +831,8 @@ static void impm_step(orc_sim *s, int64_t j, int64_t N, double h) {
         /* The elastic impulse of the step enters the first exchange; later passes
          * only re-exchange momentum so that the velocity field relaxes towards the
          * object's (unless the literal every-pass variant is asked for). */
-        p2g_ex(s, h, cnt == 0 || s->P.stress_each_pass);
-        orc_grid_update_ex(s, &sp, 1, 1);
+        p2g_ex(s, h, cnt == 0 || s->P.stress_each_pass, &sp);
+        orc_grid_update_ex(s, &sp, s->P.object_mode != 1, 1);
         /* relative-rest test on the calibration particle, before its G2P */
         double ve[3];
         gather_velocity(s, s->x + 3 * s->e, ve);
@@ -656,6 +862,11 @@ static void impm_step(orc_sim *s, int64_t j, int64_t N, double h) {
     s->passes += cnt;
     if (s->pass_log && s->log_len < s->log_cap) s->pass_log[s->log_len++] = cnt;
     orc_commit(s, h);
+    if (s->n_obj > 0) {
+        step_pose end;
+        make_step_pose(s, j + 1, N, h, &end);
+        place_object(s, &end);
+    }
     s->steps += 1;
 }
 
@@ -727,6 +938,31 @@ void orc_get_counters(const orc_sim *s, int64_t *out4, double *last_r) {
     if (last_r) *last_r = s->last_r;
 }
 
+int64_t orc_num_object(const orc_sim *s) { return s->n_obj; }
+
+/* Threads of the timing leg (1 = serial; returns the value taken). */
+int32_t orc_set_threads(orc_sim *s, int32_t threads) {
+    s->threads = threads > 1 ? threads : 1;
+    free(s->Mt); free(s->MGt);
+    s->Mt = s->MGt = NULL;
+    return s->threads;
+}
+
+/* Object particles: world positions (n_obj * 3) and body-frame positions. */
+void orc_get_object(const orc_sim *s, double *x, double *body) {
+    if (x && s->n_obj) memcpy(x, s->obj_x, s->n_obj * 3 * sizeof(double));
+    if (body && s->n_obj) memcpy(body, s->obj_body, s->n_obj * 3 * sizeof(double));
+}
+
+/* Object particle mass, and the P2G of one exchange with the object particles
+ * at the start pose of a one-step move to the target (test hook). */
+double orc_object_mass(const orc_sim *s) { return s->m_obj; }
+void orc_phase_p2g_object(orc_sim *s, double h) {
+    step_pose sp;
+    make_step_pose(s, 0, 1, h, &sp);
+    p2g_ex(s, h, 1, &sp);
+}
+
 /* Closest approach of the relative-rest ratio to the threshold so far, as
  * |r - threshold| / threshold (infinity before any test): near the threshold a
  * single-precision evaluation may take the other branch. */
@@ -780,7 +1016,7 @@ int64_t orc_get_pass_log(const orc_sim *s, int32_t *out, int64_t cap) {
 /* Phase entry points for the invariant tests: one exchange with optional parts.
  * A NULL pose disables the contact rule. */
 void orc_phase_p2g(orc_sim *s, double h) { orc_p2g(s, h); }
-void orc_phase_p2g_momentum(orc_sim *s) { p2g_ex(s, 0.0, 0); }
+void orc_phase_p2g_momentum(orc_sim *s) { p2g_ex(s, 0.0, 0, NULL); }
 void orc_phase_grid(orc_sim *s, int use_contact, int use_bc) {
     step_pose sp;
     make_step_pose(s, 0, 1, s->P.dt, &sp);

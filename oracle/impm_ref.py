@@ -22,7 +22,7 @@ def build(force: bool = False) -> str:
     """Compile the oracle with gcc (no fused multiply-add contraction)."""
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
                                "-o", tmp, SRC, "-lm"])
         os.replace(tmp, LIB)
     return LIB
@@ -42,6 +42,8 @@ class _Params(C.Structure):
         ("stress_each_pass", C.c_int32), ("_pad1", C.c_int32),
         ("hf_n", C.c_int32), ("_pad2", C.c_int32), ("hf_half", C.c_double),
         ("hf", C.POINTER(C.c_double)),
+        ("object_mode", C.c_int32), ("_pad3", C.c_int32), ("object_density", C.c_double),
+        ("object_cap", C.c_double),
     ]
 
 
@@ -78,6 +80,14 @@ def lib():
         L.orc_min_margin.restype = C.c_double
         L.orc_min_margin.argtypes = [P]
         L.orc_set_pose.argtypes = [P, dp, dp]
+        L.orc_set_threads.restype = C.c_int32
+        L.orc_set_threads.argtypes = [P, C.c_int32]
+        L.orc_num_object.restype = C.c_int64
+        L.orc_num_object.argtypes = [P]
+        L.orc_get_object.argtypes = [P, C.c_void_p, C.c_void_p]
+        L.orc_object_mass.restype = C.c_double
+        L.orc_object_mass.argtypes = [P]
+        L.orc_phase_p2g_object.argtypes = [P, C.c_double]
         L.orc_get_counters.argtypes = [P, i64, C.POINTER(C.c_double)]
         L.orc_get_pose.argtypes = [P, dp]
         L.orc_get_xo.argtypes = [P, dp]
@@ -122,6 +132,7 @@ def to_params(p) -> _Params:
     q.fillet = p.fillet
     q.pose0[:] = list(p.pose0)
     q.stress_each_pass = p.stress_each_pass
+    q.object_mode, q.object_density, q.object_cap = p.object_mode, p.object_density, p.object_cap
     if getattr(p, "hf", None) is not None:
         t = np.ascontiguousarray(p.hf, np.float64)
         q.hf_n, q.hf_half = t.shape[0], p.hf_half
@@ -212,6 +223,23 @@ class OracleSim:
         lib().orc_get_counters(self.h, c, C.byref(r))
         return dict(substeps=int(c[0]), steps=int(c[1]), passes=int(c[2]),
                     limit_hits=int(c[3]), last_r=r.value)
+
+    def set_threads(self, n):
+        """OpenMP threads of the timing leg (1: the plain serial loops)."""
+        return int(lib().orc_set_threads(self.h, int(n)))
+
+    def objects(self):
+        """Object particles: (world positions, body-frame positions), each (n_obj, 3)."""
+        n = int(lib().orc_num_object(self.h))
+        x = np.zeros((n, 3)); b = np.zeros((n, 3))
+        lib().orc_get_object(self.h, _ptr(x), _ptr(b))
+        return x, b
+
+    def object_mass(self):
+        return float(lib().orc_object_mass(self.h))
+
+    def p2g_with_object(self, h=None):
+        lib().orc_phase_p2g_object(self.h, self.params.dt if h is None else h)
 
     def min_margin(self):
         """min |r - threshold| / threshold over every relative-rest test so far."""

@@ -7,9 +7,12 @@
 //   v0..2          velocity (m/s)
 //   C0..8          affine velocity matrix C (1/s), row-major
 //   G0..8          F - I, the deformation gradient minus identity, row-major
-//   flags  uint8   bit 0: lower layer (v_z = 0 under IMPM), bit 1: surface particle
+//   flags  uint8   bit 0: lower layer (v_z = 0 under IMPM), bit 1: surface particle,
+//                  bit 2: object particle (the object represented by particles)
 // Holding x as cell + offset and F as I + G keeps FP32 relative precision in the
-// B-spline weights and in F - R, which the stress depends on.
+// B-spline weights and in F - R, which the stress depends on.  Object particles
+// hold no v, C or G: their G0..G2 planes carry their body-fixed lattice indices
+// (i, j, k), exact in FP32, from which every commit places them rigidly.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -21,7 +24,7 @@ constexpr int kWaves = kBlock / 64;  // wave64
 constexpr int kDirs = 27;            // neighbour tiles a particle can move to in one step
 
 enum : int { F0 = 0, V0 = 3, C0 = 6, G0 = 15, NPLANES = 24 };
-enum : uint8_t { FLAG_BOTTOM = 1, FLAG_SURFACE = 2 };
+enum : uint8_t { FLAG_BOTTOM = 1, FLAG_SURFACE = 2, FLAG_OBJECT = 4 };
 enum : int { DEV_CFL = 1, DEV_NONFINITE = 2, DEV_DETF = 4 };
 
 // Pose of the indenter for one executed step (host FP64 table).
@@ -32,6 +35,8 @@ struct StepPose {
     double w[3];       // angular velocity over the step
     double vot[2];     // tangential (x, y) velocity of the object point x_o
     double gnorm;      // |vot|
+    double c_end[3];   // body origin and rotation at the end of the step, where
+    double R_end[9];   // the commit places the object particles
     int32_t forced;    // forced pass count, 0 = decide by the relative-rest test
     int32_t _pad;
 };
@@ -74,6 +79,13 @@ struct KArgs {
     int hf_n;
     double hf_half;
     float mp;         // particle mass (kg), for the debug grid copy
+    // object particles (object_mode 1): mass ratio to an elastomer particle, the
+    // body lattice (spacing obj_h, lowest layer centre obj_z0) and the node
+    // accumulators of their fixed-point mass weights (null without them)
+    int object_mode;
+    float kappa;
+    double obj_h, obj_z0;
+    unsigned long long* objW;
     long long n;      // particles
     long long e;      // calibration particle id
     // buffers

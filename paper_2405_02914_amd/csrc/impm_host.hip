@@ -102,7 +102,11 @@ struct sim_s {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int device = 0;
-    long long n = 0;
+    long long n = 0;             // particles in the device arrays: elastomer, then object
+    long long n_el = 0;          // elastomer particles (the ones the ABI addresses)
+    long long n_obj = 0;         // object particles (object_mode SIM_OBJECT_PARTICLES)
+    unsigned long long* objW = nullptr;   // node accumulators of the object particles' weights
+    double obj_h = 0.0, obj_z0 = 0.0;     // their body lattice: spacing, lowest layer centre
     int m = 0;
     int nn[3] = {0, 0, 0};
     long long n_nodes = 0;
@@ -257,6 +261,82 @@ static void lowest_point(const sim_params& P, double* p) {
     }
 }
 
+// Inside measure of the indenter in its body frame (<= 0 inside): the same
+// FP64 expressions, in the same order, as the reference's, so that both sample
+// the same object particles.
+static double body_phi(const sim_params& P, const double* p) {
+#pragma clang fp contract(off)
+    if (P.shape == SIM_SHAPE_SPHERE) {
+        return p[0] * p[0] + p[1] * p[1] + p[2] * p[2] - P.radius * P.radius;
+    } else if (P.shape == SIM_SHAPE_CAPSULE) {
+        const double hl = P.half_length;
+        const double t = p[0] < -hl ? -hl : (p[0] > hl ? hl : p[0]);
+        const double qx = p[0] - t;
+        return qx * qx + p[1] * p[1] + p[2] * p[2] - P.radius * P.radius;
+    } else if (P.shape == SIM_SHAPE_BOX) {
+        double out2 = 0.0, inmax = -1e300;
+        for (int a = 0; a < 3; ++a) {
+            const double q = std::fabs(p[a]) - (P.half_extent[a] - P.fillet);
+            const double qp = q > 0.0 ? q : 0.0;
+            out2 += qp * qp;
+            if (q > inmax) inmax = q;
+        }
+        const double inside_part = inmax < 0.0 ? inmax : 0.0;
+        return std::sqrt(out2) + inside_part - P.fillet;
+    } else if (P.shape == SIM_SHAPE_HEIGHTFIELD) {
+        if (p[0] * p[0] + p[1] * p[1] > P.hf_half * P.hf_half) return 1.0;
+        const int n = P.hf_n;
+        const double step = 2.0 * P.hf_half / (double)(n - 1);
+        const double u = (p[0] + P.hf_half) / step, v = (p[1] + P.hf_half) / step;
+        int i0 = (int)std::floor(u), j0 = (int)std::floor(v);
+        i0 = std::min(std::max(i0, 0), n - 2);
+        j0 = std::min(std::max(j0, 0), n - 2);
+        const double fu = u - (double)i0, fv = v - (double)j0;
+        const double* t = P.hf;
+        const double z0 = (1.0 - fu) * t[j0 * n + i0] + fu * t[j0 * n + i0 + 1];
+        const double z1 = (1.0 - fu) * t[(j0 + 1) * n + i0] + fu * t[(j0 + 1) * n + i0 + 1];
+        return ((1.0 - fv) * z0 + fv * z1) - p[2];
+    }
+    return 1.0;
+}
+
+// Object particles (SIM_OBJECT_PARTICLES): the body lattice points
+// ((i + 1/2) h, (j + 1/2) h, z_low + (k + 1/2) h), h = dx / m, inside the
+// indenter, at most object_cap above its lowest point and with their whole
+// stencil at least one node inside the grid at the initial pose (pos, R);
+// ordered by k, then j, then i.  lat receives (i, j, k), world the positions.
+static void sample_object(const sim_params& P, int m, const int nn[3], const double* pos, const double* R,
+                          double z_low, std::vector<int32_t>& lat, std::vector<double>& world) {
+#pragma clang fp contract(off)
+    const double h = P.dx / (double)m;
+    double hx = 0.0, hy = 0.0;
+    if (P.shape == SIM_SHAPE_SPHERE) { hx = P.radius; hy = P.radius; }
+    else if (P.shape == SIM_SHAPE_CAPSULE) { hx = P.half_length + P.radius; hy = P.radius; }
+    else if (P.shape == SIM_SHAPE_BOX) { hx = P.half_extent[0]; hy = P.half_extent[1]; }
+    else if (P.shape == SIM_SHAPE_HEIGHTFIELD) { hx = P.hf_half; hy = P.hf_half; }
+    const long long ni = (long long)std::ceil(hx / h), nj = (long long)std::ceil(hy / h);
+    const long long nk = (long long)std::ceil(P.object_cap / h);
+    const double off[3] = {(double)P.pad_lateral, (double)P.pad_lateral, (double)P.pad_bottom};
+    lat.clear();
+    world.clear();
+    for (long long k = 0; k < nk; ++k)
+        for (long long j = -nj; j < nj; ++j)
+            for (long long i = -ni; i < ni; ++i) {
+                const double p[3] = {((double)i + 0.5) * h, ((double)j + 0.5) * h, z_low + ((double)k + 0.5) * h};
+                if (body_phi(P, p) > 0.0) continue;
+                double w[3];
+                bool ok = true;
+                for (int a = 0; a < 3; ++a) {
+                    w[a] = pos[a] + R[3 * a] * p[0] + R[3 * a + 1] * p[1] + R[3 * a + 2] * p[2];
+                    const double b = std::floor(w[a] / P.dx + off[a] - 0.5);
+                    if (b < 1.0 || b > (double)(nn[a] - 4)) ok = false;
+                }
+                if (!ok) continue;
+                lat.push_back((int32_t)i); lat.push_back((int32_t)j); lat.push_back((int32_t)k);
+                world.insert(world.end(), w, w + 3);
+            }
+}
+
 static void body_to_world(const double* c, const double* R, const double* pb, double* out) {
     for (int a = 0; a < 3; ++a) out[a] = c[a] + R[3 * a] * pb[0] + R[3 * a + 1] * pb[1] + R[3 * a + 2] * pb[2];
 }
@@ -264,8 +344,21 @@ static void body_to_world(const double* c, const double* R, const double* pb, do
 // Pose table of one sim_step call: N executed steps of length h moving the
 // body from (pos, quat) to (tpos, tquat) at constant velocity (Sec. IV-B:
 // press, slide and rotate step by step until the target pose).
+static void pose_at(const sim_t* s, double frac, double* c, double* R) {
+    for (int a = 0; a < 3; ++a) c[a] = s->pos[a] + (s->tpos[a] - s->pos[a]) * frac;
+    double axis[3], ang;
+    rel_axis_angle(s->quat, s->tquat, axis, &ang);
+    const double half = 0.5 * ang * frac;
+    const double qs[4] = {std::cos(half), axis[0] * std::sin(half), axis[1] * std::sin(half),
+                          axis[2] * std::sin(half)};
+    double qj[4];
+    quat_mul(qs, s->quat, qj);
+    quat_matrix(qj, R);
+}
+
 static void make_pose(const sim_t* s, long long j, long long N, double h, StepPose* sp) {
     const double frac = (double)j / (double)N;
+    pose_at(s, (double)(j + 1) / (double)N, sp->c_end, sp->R_end);
     for (int a = 0; a < 3; ++a) {
         const double d = s->tpos[a] - s->pos[a];
         sp->c[a] = s->pos[a] + d * frac;
@@ -329,6 +422,11 @@ static KArgs kargs(const sim_t* s) {
     a.hf_n = P.hf_n;
     a.hf_half = P.hf_half;
     a.mp = (float)s->mp;
+    a.object_mode = P.object_mode;
+    a.kappa = (float)(P.object_density / P.rho);
+    a.obj_h = s->obj_h;
+    a.obj_z0 = s->obj_z0;
+    a.objW = s->objW;
     a.n = s->n;
     a.e = s->slots_stale ? s->e_slot : (long long)s->slot_of[s->e];
     a.soa = s->soa;
@@ -545,6 +643,15 @@ static int prepare_step(sim_t* s, int32_t n_substeps, std::vector<int>& npass) {
     return sync_args(s);
 }
 
+// The stand-alone particle-to-grid of a step's first exchange starts from
+// empty object-weight accumulators (a kernel fill: no memset node in graphs).
+static void clear_object_weights(sim_t* s, hipStream_t st) {
+    if (!s->objW) return;
+    const long long nf = s->n_nodes * 2;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)std::min<long long>((nf + 255) / 256, 4096)), dim3(256), 0, st,
+                       reinterpret_cast<float*>(s->objW), nf, 0.0f);
+}
+
 static bool coop_supported() {
     static int ok = -1;
     if (ok < 0) {
@@ -694,6 +801,9 @@ int sim_params_default(sim_params* p) {
     p->shape = SIM_SHAPE_SPHERE;
     p->radius = 4.0e-3;
     p->pose0[0] = 8.0e-3; p->pose0[1] = 8.0e-3; p->pose0[2] = 8.0e-3; p->pose0[3] = 1.0;
+    p->object_mode = SIM_OBJECT_COLLIDER;
+    p->object_density = p->rho;
+    p->object_cap = 2.5e-3;
     return SIM_OK;
 }
 
@@ -729,6 +839,19 @@ static int validate(const sim_params* p, std::string& why) {
     double qn = 0;
     for (int k = 3; k < 7; ++k) qn += p->pose0[k] * p->pose0[k];
     if (!(qn > 0)) { why = "pose0 quaternion is zero"; return SIM_EINVAL; }
+    if (p->object_mode != SIM_OBJECT_COLLIDER && p->object_mode != SIM_OBJECT_PARTICLES) {
+        why = "bad object_mode";
+        return SIM_EINVAL;
+    }
+    if (p->object_mode == SIM_OBJECT_PARTICLES) {
+        // the object particles' node weights (up to about 16 kappa) must stay in
+        // the range of the fixed-point node sums
+        if (p->shape == SIM_SHAPE_NONE || !(p->object_density > 0) || !(p->object_density <= 1e4 * p->rho) ||
+            !(p->object_cap > 0) || !(p->object_cap <= 1e3 * p->dx)) {
+            why = "object particles need a shape, 0 < object_density <= 1e4 rho and 0 < object_cap <= 1000 dx";
+            return SIM_EINVAL;
+        }
+    }
     return SIM_OK;
 }
 
@@ -753,11 +876,27 @@ int sim_create(const sim_params* p, void* hip_stream, sim_t** out) {
     for (int k = 1; k <= 4; ++k) if (k * k * k == P.ppc) s->m = k;
     const int m = s->m;
     const int Nx = P.cells[0], Ny = P.cells[1], Nz = P.cells[2];
-    s->n = (long long)Nx * Ny * Nz * P.ppc;
+    s->n_el = (long long)Nx * Ny * Nz * P.ppc;
     s->nn[0] = Nx + 2 * P.pad_lateral + 1;
     s->nn[1] = Ny + 2 * P.pad_lateral + 1;
     s->nn[2] = Nz + P.pad_bottom + P.pad_top + 1;
     s->n_nodes = (long long)s->nn[0] * s->nn[1] * s->nn[2];
+    // object particles (stored after the elastomer's ids) at the initial pose
+    std::vector<int32_t> obj_lat;
+    std::vector<double> obj_world;
+    double body_low[3];
+    lowest_point(P, body_low);
+    if (P.object_mode == SIM_OBJECT_PARTICLES) {
+        double q0[4] = {P.pose0[3], P.pose0[4], P.pose0[5], P.pose0[6]};
+        quat_normalise(q0);
+        double R0[9];
+        quat_matrix(q0, R0);
+        sample_object(P, m, s->nn, P.pose0, R0, body_low[2], obj_lat, obj_world);
+        s->obj_h = P.dx / (double)m;
+        s->obj_z0 = body_low[2];
+    }
+    s->n_obj = (long long)obj_world.size() / 3;
+    s->n = s->n_el + s->n_obj;
     s->mu = P.E / (2.0 * (1.0 + P.nu));
     s->lam = P.E * P.nu / ((1.0 + P.nu) * (1.0 - 2.0 * P.nu));
     s->Vp = P.dx * P.dx * P.dx / (double)P.ppc;
@@ -820,19 +959,53 @@ int sim_create(const sim_params* p, void* hip_stream, sim_t** out) {
                             }
                             flags[id] = fl;
                         }
+    // object particles: cell and offset of their initial position, lattice
+    // indices in G0..G2 (exact in FP32)
+    for (long long q = 0; q < s->n_obj; ++q) {
+        const long long id = s->n_el + q;
+        const int off[3] = {P.pad_lateral, P.pad_lateral, P.pad_bottom};
+        int cc[3];
+        for (int a = 0; a < 3; ++a) {
+            const double g = obj_world[3 * q + a] / P.dx + (double)off[a];
+            double fl = std::floor(g);
+            float fr = (float)(g - fl);
+            if (fr >= 1.0f) { fr = 0.0f; fl += 1.0; }
+            cc[a] = (int)fl;
+            host[(size_t)(F0 + a) * n + id] = fr;
+            host[(size_t)(G0 + a) * n + id] = (float)obj_lat[3 * q + a];
+        }
+        cells[id] = pack_cell(cc);
+        flags[id] = FLAG_OBJECT;
+    }
     // indenter pose and calibration points
     std::memcpy(s->pos, P.pose0, sizeof(s->pos));
     std::memcpy(s->quat, P.pose0 + 3, sizeof(s->quat));
     quat_normalise(s->quat);
     std::memcpy(s->tpos, s->pos, sizeof(s->pos));
     std::memcpy(s->tquat, s->quat, sizeof(s->quat));
-    lowest_point(P, s->po_body);
+    std::memcpy(s->po_body, body_low, sizeof(body_low));
+    if (s->n_obj > 0) {
+        // x_o is the object's bottom particle: the lowest, then the farthest from
+        // the body z axis, then the smallest (x, y)
+        bool found = false;
+        double bz = 0.0, br2 = 0.0;
+        for (long long q = 0; q < s->n_obj; ++q) {
+#pragma clang fp contract(off)
+            const double pb[3] = {((double)obj_lat[3 * q] + 0.5) * s->obj_h, ((double)obj_lat[3 * q + 1] + 0.5) * s->obj_h,
+                                  s->obj_z0 + ((double)obj_lat[3 * q + 2] + 0.5) * s->obj_h};
+            const double r2 = pb[0] * pb[0] + pb[1] * pb[1];
+            const bool better = !found || pb[2] < bz ||
+                                (pb[2] == bz && (r2 > br2 || (r2 == br2 && (pb[0] < s->po_body[0] ||
+                                                                            (pb[0] == s->po_body[0] && pb[1] < s->po_body[1])))));
+            if (better) { found = true; bz = pb[2]; br2 = r2; std::memcpy(s->po_body, pb, sizeof(pb)); }
+        }
+    }
     double R0[9], xo[3];
     quat_matrix(s->quat, R0);
     body_to_world(s->pos, R0, s->po_body, xo);
     double best = 1e300;
     s->e = 0;
-    for (long long id = 0; id < s->n; ++id) {
+    for (long long id = 0; id < s->n_el; ++id) {
         const uint32_t c = cells[id];
         const int cc[3] = {(int)(c & 1023) - P.pad_lateral, (int)((c >> 10) & 1023) - P.pad_lateral,
                            (int)((c >> 20) & 1023) - P.pad_bottom};
@@ -873,6 +1046,10 @@ int sim_create(const sim_params* p, void* hip_stream, sim_t** out) {
         hipMemcpy(s->flags, flags.data(), n, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(s->st, 0, sizeof(DevState)) != hipSuccess)
         return bail(SIM_EHIP);
+    if (s->n_obj > 0) {
+        if (hipMalloc(&s->objW, (size_t)s->n_nodes * sizeof(unsigned long long)) != hipSuccess) return bail(SIM_ENOMEM);
+        if (hipMemset(s->objW, 0, (size_t)s->n_nodes * sizeof(unsigned long long)) != hipSuccess) return bail(SIM_EHIP);
+    }
     if (hipMalloc(&s->d_id_of, n * 4) != hipSuccess) return bail(SIM_ENOMEM);
     if (hipMemcpy(s->d_id_of, s->id_of.data(), n * 4, hipMemcpyHostToDevice) != hipSuccess) return bail(SIM_EHIP);
     if (hipMalloc(&s->surf_rest, srest.size() * sizeof(float)) != hipSuccess) return bail(SIM_ENOMEM);
@@ -893,7 +1070,7 @@ void sim_destroy(sim_t* s) {
     void* bufs[] = {s->soa, s->cell, s->flags, s->order[0], s->order[1], s->bstart[0], s->bstart[1],
                     s->dirrank, s->dircount, s->newcnt, s->scratch, s->gridV, s->dbgM, s->dbgMG,
                     s->st, s->poses, s->surf_rest, s->surf_acc, s->out_tmp, s->d_args, s->d_hf,
-                    s->d_id_of, s->soa_alt, s->cell_alt, s->flags_alt, s->id_of_alt, s->d_e_slot};
+                    s->d_id_of, s->soa_alt, s->cell_alt, s->flags_alt, s->id_of_alt, s->d_e_slot, s->objW};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     for (int k = 0; k < 2; ++k) {
@@ -957,6 +1134,7 @@ int sim_step(sim_t* s, int32_t n_substeps) {
     L.st = s->stream;
     L.coop = !(s->use_graph && !s->prof) && coop_supported();   // eager launches only
     if (!s->pending) {
+        clear_object_weights(s, s->stream);
         L.ops->p2g(L.m, L.tile_blocks, s->cur, s->stream);
         HIPCHK(s, hipGetLastError());
         s->sbin = s->cur;
@@ -1167,7 +1345,7 @@ int sim_get_stats(sim_t* s, sim_stats* out) {
 
 int sim_num_particles(const sim_t* s, int64_t* n) {
     if (!s || !n) return SIM_EINVAL;
-    *n = s->n;
+    *n = s->n_el;
     return SIM_OK;
 }
 
@@ -1181,14 +1359,15 @@ int sim_read_particles(sim_t* s, double* x, float* v, float* C, float* G) {
     if (!s) return SIM_EINVAL;
     if (int rc0 = ensure_slots(s)) return rc0;
     HIPCHK(s, hipStreamSynchronize(s->stream));
-    const size_t n = (size_t)s->n;
+    const size_t n = (size_t)s->n;          // plane pitch (object particles included)
+    const size_t ne = (size_t)s->n_el;      // the particles the caller addresses
     if (x) {
         std::vector<uint32_t> cells(n);
         std::vector<float> f(3 * n);
         HIPCHK(s, hipMemcpy(cells.data(), s->cell, n * 4, hipMemcpyDeviceToHost));
         HIPCHK(s, hipMemcpy(f.data(), s->soa + (size_t)F0 * n, 3 * n * 4, hipMemcpyDeviceToHost));
         const int off[3] = {s->P.pad_lateral, s->P.pad_lateral, s->P.pad_bottom};
-        for (size_t id = 0; id < n; ++id) {
+        for (size_t id = 0; id < ne; ++id) {
             const size_t k = s->slot_of[id];
             const uint32_t c = cells[k];
             const int cc[3] = {(int)(c & 1023), (int)((c >> 10) & 1023), (int)((c >> 20) & 1023)};
@@ -1199,7 +1378,7 @@ int sim_read_particles(sim_t* s, double* x, float* v, float* C, float* G) {
     auto planes = [&](float* dst, int p0, int np) -> int {
         std::vector<float> tmp((size_t)np * n);
         HIPCHK(s, hipMemcpy(tmp.data(), s->soa + (size_t)p0 * n, (size_t)np * n * 4, hipMemcpyDeviceToHost));
-        for (size_t id = 0; id < n; ++id) {
+        for (size_t id = 0; id < ne; ++id) {
             const size_t k = s->slot_of[id];
             for (int q = 0; q < np; ++q) dst[np * id + q] = tmp[(size_t)q * n + k];
         }
@@ -1216,12 +1395,17 @@ int sim_write_particles(sim_t* s, const double* x, const float* v, const float* 
     if (!s) return SIM_EINVAL;
     if (int rc0 = ensure_slots(s)) return rc0;
     HIPCHK(s, hipStreamSynchronize(s->stream));
-    const size_t n = (size_t)s->n;
+    const size_t n = (size_t)s->n;          // plane pitch (object particles included)
+    const size_t ne = (size_t)s->n_el;      // the particles the caller addresses
     if (x) {
         std::vector<uint32_t> cells(n);
         std::vector<float> f(3 * n);
+        if (s->n_obj > 0) {   // the object particles' slots keep their contents
+            HIPCHK(s, hipMemcpy(cells.data(), s->cell, n * 4, hipMemcpyDeviceToHost));
+            HIPCHK(s, hipMemcpy(f.data(), s->soa + (size_t)F0 * n, 3 * n * 4, hipMemcpyDeviceToHost));
+        }
         const int off[3] = {s->P.pad_lateral, s->P.pad_lateral, s->P.pad_bottom};
-        for (size_t id = 0; id < n; ++id) {
+        for (size_t id = 0; id < ne; ++id) {
             int cc[3];
             for (int a = 0; a < 3; ++a) {
                 const double g = x[3 * id + a] / s->P.dx;
@@ -1240,7 +1424,9 @@ int sim_write_particles(sim_t* s, const double* x, const float* v, const float* 
     }
     auto planes = [&](const float* src, int p0, int np) -> int {
         std::vector<float> tmp((size_t)np * n);
-        for (size_t id = 0; id < n; ++id) {
+        if (s->n_obj > 0)
+            HIPCHK(s, hipMemcpy(tmp.data(), s->soa + (size_t)p0 * n, (size_t)np * n * 4, hipMemcpyDeviceToHost));
+        for (size_t id = 0; id < ne; ++id) {
             const size_t k = s->slot_of[id];
             for (int q = 0; q < np; ++q) tmp[(size_t)q * n + k] = src[np * id + q];
         }
@@ -1259,7 +1445,7 @@ int sim_read_rest(sim_t* s, double* X, uint8_t* flags) {
     const sim_params& P = s->P;
     const int m = s->m;
     if (X) {
-        for (long long id = 0; id < s->n; ++id) {
+        for (long long id = 0; id < s->n_el; ++id) {
             const long long cid = id / P.ppc;
             const int sub = (int)(id % P.ppc);
             const int ci[3] = {(int)(cid % P.cells[0]), (int)((cid / P.cells[0]) % P.cells[1]),
@@ -1273,7 +1459,7 @@ int sim_read_rest(sim_t* s, double* X, uint8_t* flags) {
         if (int rc0 = ensure_slots(s)) return rc0;
         std::vector<uint8_t> fs(s->n);
         HIPCHK(s, hipMemcpy(fs.data(), s->flags, s->n, hipMemcpyDeviceToHost));
-        for (long long id = 0; id < s->n; ++id) flags[id] = fs[s->slot_of[id]];
+        for (long long id = 0; id < s->n_el; ++id) flags[id] = fs[s->slot_of[id]];
     }
     return SIM_OK;
 }
@@ -1567,6 +1753,7 @@ int sim_batch_step(sim_batch_t* b, int32_t n_substeps) {
         sets.push_back(L);
     }
     if (!s0->pending) {
+        for (sim_t* s : b->sims) clear_object_weights(s, b->stream);
         for (auto& L : sets) L.ops->p2g(L.m, L.tile_blocks, s0->cur, b->stream);
         for (sim_t* s : b->sims) s->sbin = s->cur;
     }

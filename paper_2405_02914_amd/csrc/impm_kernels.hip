@@ -86,7 +86,7 @@ struct Tile {
     static constexpr int GX = TX + 2, GY = TY + 2, GZ = TZ + 2, GVOL = GX * GY * GZ;
     static constexpr size_t LDS_P2G = (size_t)4 * AVOL * 8;
     static constexpr int NW = NB / 64;
-    static constexpr size_t LDS_G2P2G = LDS_P2G + (size_t)GVOL * 12 + 81 * 4 + (NW * kDirs + kDirs + 4) * 4;
+    static constexpr size_t LDS_G2P2G = LDS_P2G + (size_t)GVOL * 16 + 81 * 4 + (NW * kDirs + kDirs + 4) * 4;
 };
 
 // Particle-to-grid contribution of one particle (Eq. 1-4) into the LDS node
@@ -181,6 +181,57 @@ __device__ __forceinline__ void load_particle(const KArgs& a, long long id, int 
     for (int q = 0; q < 3; ++q) f[q] = glb(a.soa)[(size_t)(F0 + q) * a.n + id];
 }
 
+// Object particles (the object represented by particles, Sec. III-A).  Their
+// velocity is the object's prescribed rigid motion and their affine matrix that
+// motion's [w]x, so their transfer to node i is m_o w_ip (v_o + w x (X_i - c)):
+// the rigid velocity at the node times their mass weight.  They therefore only
+// deposit kappa * w_ip (mass relative to an elastomer particle) into a
+// fixed-point node array; the node kernel adds that weight and its rigid
+// momentum with the step's pose.  Global 64-bit integer atomics: the sums are
+// exact and independent of order.  Returns DEV_CFL if the stencil leaves the grid.
+__device__ __forceinline__ int p2g_object(const KArgs& a, const int cell[3], const float f[3]) {
+    int base[3];
+    float fx[3], w[3][3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) bspline_axis(cell[q], f[q], base[q], fx[q], w[q]);
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+        if (base[q] < 0 || base[q] + 2 > a.nn[q] - 1) return DEV_CFL;
+    const double scale = (double)a.kappa * kFixScale;
+    for (int c = 0; c < 3; ++c)
+        for (int b = 0; b < 3; ++b) {
+            const double wbc = (double)(w[1][b] * w[2][c]) * scale;
+            const long long row = ((long long)(base[2] + c) * a.nn[1] + (base[1] + b)) * a.nn[0] + base[0];
+#pragma unroll
+            for (int aa = 0; aa < 3; ++aa)
+                atomicAdd(&a.objW[row + aa],
+                          (unsigned long long)__double_as_longlong(fma((double)w[0][aa], wbc, kFixMagic)));
+        }
+    return 0;
+}
+
+// Rigid placement of an object particle at the end of a step: its body point
+// ((i + 1/2) h, (j + 1/2) h, z0 + (k + 1/2) h) from the lattice indices in lat,
+// moved by the end pose, as a grid cell plus an FP32 offset.  FP64, evaluated
+// in the order of the host reference.
+__device__ __forceinline__ void place_object(const KArgs& a, const StepPose& sp, const float lat[3], int cell[3],
+                                             float f[3]) {
+#pragma clang fp contract(off)
+    const double p0 = ((double)lat[0] + 0.5) * a.obj_h, p1 = ((double)lat[1] + 0.5) * a.obj_h;
+    const double p2 = a.obj_z0 + ((double)lat[2] + 0.5) * a.obj_h;
+    const double off[3] = {(double)a.pad_l, (double)a.pad_l, (double)a.pad_b};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const double x = sp.c_end[q] + sp.R_end[3 * q] * p0 + sp.R_end[3 * q + 1] * p1 + sp.R_end[3 * q + 2] * p2;
+        const double g = x / a.dxd + off[q];
+        double fl = floor(g);
+        float fr = (float)(g - fl);
+        if (fr >= 1.0f) { fr = 0.0f; fl += 1.0; }
+        cell[q] = (int)fl;
+        f[q] = fr;
+    }
+}
+
 __global__ void k_fill(float* p, long long n, float val) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x)
@@ -214,6 +265,10 @@ __global__ __launch_bounds__(TL::NT) void k_p2g(BatchMap m, int cur) {
         int cell[3];
         float f[3], v[3], C[9], G[9];
         load_particle(a, id, cell, f);
+        if (a.objW && (glb(a.flags)[id] & FLAG_OBJECT)) {
+            err |= p2g_object(a, cell, f);
+            continue;
+        }
         for (int q = 0; q < 3; ++q) v[q] = glb(a.soa)[(size_t)(V0 + q) * a.n + id];
         for (int q = 0; q < 9; ++q) C[q] = glb(a.soa)[(size_t)(C0 + q) * a.n + id];
         for (int q = 0; q < 9; ++q) G[q] = glb(a.soa)[(size_t)(G0 + q) * a.n + id];
@@ -264,12 +319,25 @@ __device__ __forceinline__ void grid_block(const BatchMap& m, int gnb, int sbin,
                 const f32x4 c = glb4(a.scratch)[(size_t)t * TL::PVOL + (l2 * TL::PY + l1) * TL::PX + l0];
                 W += c.x; P0 += c.y; P1 += c.z; P2 += c.w;
             }
+    if (a.objW) {
+        // the object particles' mass weight and its rigid momentum at this node
+        // (read and cleared for the next exchange)
+        const unsigned long long q = glb(a.objW)[nid];
+        if (q) {
+            glb(a.objW)[nid] = 0ull;
+            const float Wo = from_fixed(q);
+            float u[3];
+            rigid_velocity(a, a.poses[step], i, j, k, u);
+            W += Wo;
+            P0 += Wo * u[0]; P1 += Wo * u[1]; P2 += Wo * u[2];
+        }
+    }
     float V[3] = {0.f, 0.f, 0.f};
     if (W > 0.f) {
         const float inv = 1.0f / W;
         V[0] = P0 * inv; V[1] = P1 * inv; V[2] = P2 * inv;
         const StepPose& sp = a.poses[step];
-        if (node_inside(a, sp, i, j, k)) rigid_velocity(a, sp, i, j, k, V);
+        if (a.object_mode == 0 && node_inside(a, sp, i, j, k)) rigid_velocity(a, sp, i, j, k, V);
         const bool bnd = i < a.band || i > a.nn[0] - 1 - a.band || j < a.band ||
                          j > a.nn[1] - 1 - a.band || k > a.nn[2] - 1 - a.band || k <= a.pad_b;
         if (bnd) V[0] = V[1] = V[2] = 0.f;
@@ -311,8 +379,8 @@ __device__ __forceinline__ void g2p2g_tile(const BatchMap& m, int gt, int cur, i
     const gptr<const uint32_t> __restrict__ bstart = glb<const uint32_t>(pick(a.bstart, cur));
     extern __shared__ unsigned long long lds_u64[];
     unsigned long long* acc = lds_u64;                                   // 4 * PVOL
-    float* gv = reinterpret_cast<float*>(lds_u64 + 4 * TL::AVOL);        // GVOL x (vx, vy, vz)
-    float* ve_part = gv + 3 * TL::GVOL;                                  // 27 * 3
+    f32x4* gv = reinterpret_cast<f32x4*>(lds_u64 + 4 * TL::AVOL);        // GVOL x (vx, vy, vz, 0)
+    float* ve_part = reinterpret_cast<float*>(gv + TL::GVOL);            // 27 * 3
     int* wc = reinterpret_cast<int*>(ve_part + 81);                      // NW * 27 wave counts
     int* running = wc + TL::NW * kDirs;                                  // 27 per-direction counts
     int* sh = running + kDirs;                                           // [0] = final
@@ -381,15 +449,16 @@ __device__ __forceinline__ void g2p2g_tile(const BatchMap& m, int gt, int cur, i
     tile_coords(a, t, tc);
     const int orgP[3] = {tc[0] * TL::T0 - 1, tc[1] * TL::T1 - 1, tc[2] * TL::T2 - 1};
     const int orgG[3] = {tc[0] * TL::T0, tc[1] * TL::T1, tc[2] * TL::T2};
-    // ---- stage the grid velocities of the tile's G2P block (without the
-    // weight, which the gather does not use), clear the P2G block
+    // ---- stage the grid velocities of the tile's G2P block as 16-byte records
+    // (one ds_read_b128 with an immediate offset per stencil node in the
+    // gather; the weight slot is unused), clear the P2G block
     for (int kk = tid; kk < TL::GVOL; kk += TL::NT) {
         const int lx = kk % TL::GX, ly = (kk / TL::GX) % TL::GY, lz = kk / (TL::GX * TL::GY);
         const int gx = orgG[0] + lx, gy = orgG[1] + ly, gz = orgG[2] + lz;
         f32x4 V = {0.f, 0.f, 0.f, 0.f};
         if (gx >= 0 && gy >= 0 && gz >= 0 && gx < a.nn[0] && gy < a.nn[1] && gz < a.nn[2])
             V = glb4(a.gridV)[((long long)gz * a.nn[1] + gy) * a.nn[0] + gx];
-        gv[3 * kk] = V.x; gv[3 * kk + 1] = V.y; gv[3 * kk + 2] = V.z;
+        gv[kk] = V;
     }
     for (int kk = tid; kk < 4 * TL::AVOL; kk += TL::NT) acc[kk] = 0ull;
     __syncthreads();
@@ -433,7 +502,7 @@ __device__ __forceinline__ void g2p2g_tile(const BatchMap& m, int gt, int cur, i
                 for (int q = 0; q < 3; ++q)
 #pragma unroll
                     for (int r = 0; r < 3; ++r) { S[q][r] = 0.f; Tb[q][r] = 0.f; U[q][r] = 0.f; }
-                const float* g0 = gv + 3 * ((l2 * TL::GY + l1) * TL::GX + l0);
+                const f32x4* g0 = gv + ((l2 * TL::GY + l1) * TL::GX + l0);
 #pragma unroll
                 for (int cz = 0; cz < 3; ++cz)
 #pragma unroll
@@ -441,8 +510,8 @@ __device__ __forceinline__ void g2p2g_tile(const BatchMap& m, int gt, int cur, i
                         const float wbc = w[1][cy] * w[2][cz];
 #pragma unroll
                         for (int cx = 0; cx < 3; ++cx) {
-                            const float* gp = g0 + 3 * ((cz * TL::GY + cy) * TL::GX + cx);
-                            const float3 V = make_float3(gp[0], gp[1], gp[2]);
+                            const f32x4 V = g0[(cz * TL::GY + cy) * TL::GX + cx];
+                            
                             const float wac = w[0][cx] * w[2][cz], wab = w[0][cx] * w[1][cy];
                             S[cx][0] += wbc * V.x; S[cx][1] += wbc * V.y; S[cx][2] += wbc * V.z;
                             Tb[cy][0] += wac * V.x; Tb[cy][1] += wac * V.y; Tb[cy][2] += wac * V.z;
@@ -473,34 +542,43 @@ __device__ __forceinline__ void g2p2g_tile(const BatchMap& m, int gt, int cur, i
                 fl = glb(a.flags)[id];
             }
             if (a.bottom_rule && (fl & FLAG_BOTTOM)) v[2] = 0.f;
+            // an object particle (G0..G2 hold its body lattice indices) takes no
+            // part in the gather's result: its velocity is the prescribed motion
+            const bool obj = a.objW != nullptr && (fl & FLAG_OBJECT);
             if (fin) {
-                // ---- 3. commit: F <- (I + h C) F, x <- x + h v
-                float Gn[9];
-#pragma unroll
-                for (int r = 0; r < 3; ++r)
-#pragma unroll
-                    for (int c = 0; c < 3; ++c)
-                        Gn[3 * r + c] = G[3 * r + c] +
-                                        a.h * (C[3 * r + c] + (C[3 * r] * G[c] + C[3 * r + 1] * G[3 + c] +
-                                                               C[3 * r + 2] * G[6 + c]));
-                bool finite = true;
-                for (int q = 0; q < 9; ++q) { G[q] = Gn[q]; finite = finite && isfinite(Gn[q]); }
-                for (int q = 0; q < 3; ++q) finite = finite && isfinite(v[q]);
-                if (!finite) err |= DEV_NONFINITE;
-                if (!(1.0f + det_minus_one(G) > 0.0f)) err |= DEV_DETF;
-                int perr = finite ? 0 : DEV_NONFINITE;
+                int perr = 0;
                 int moved[3];
                 float nfr[3];
-                for (int q = 0; q < 3; ++q) {
-                    const float step_cells = a.h_over_dx * v[q];
-                    if (!(fabsf(step_cells) < 1.0f)) perr |= DEV_CFL;
-                    float nf = f[q] + step_cells;
-                    const float fl0 = floorf(nf);
-                    int c = cell[q] + (int)fl0;
-                    nf -= fl0;
-                    if (nf >= 1.0f) { nf -= 1.0f; c += 1; }
-                    moved[q] = c;
-                    nfr[q] = nf;
+                if (obj) {
+                    // ---- 3. the object moves rigidly to the step's end pose
+                    place_object(a, sp, G, moved, nfr);
+                } else {
+                    // ---- 3. commit: F <- (I + h C) F, x <- x + h v
+                    float Gn[9];
+#pragma unroll
+                    for (int r = 0; r < 3; ++r)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c)
+                            Gn[3 * r + c] = G[3 * r + c] +
+                                            a.h * (C[3 * r + c] + (C[3 * r] * G[c] + C[3 * r + 1] * G[3 + c] +
+                                                                   C[3 * r + 2] * G[6 + c]));
+                    bool finite = true;
+                    for (int q = 0; q < 9; ++q) { G[q] = Gn[q]; finite = finite && isfinite(Gn[q]); }
+                    for (int q = 0; q < 3; ++q) finite = finite && isfinite(v[q]);
+                    if (!finite) err |= DEV_NONFINITE;
+                    if (!(1.0f + det_minus_one(G) > 0.0f)) err |= DEV_DETF;
+                    perr = finite ? 0 : DEV_NONFINITE;
+                    for (int q = 0; q < 3; ++q) {
+                        const float step_cells = a.h_over_dx * v[q];
+                        if (!(fabsf(step_cells) < 1.0f)) perr |= DEV_CFL;
+                        float nf = f[q] + step_cells;
+                        const float fl0 = floorf(nf);
+                        int c = cell[q] + (int)fl0;
+                        nf -= fl0;
+                        if (nf >= 1.0f) { nf -= 1.0f; c += 1; }
+                        moved[q] = c;
+                        nfr[q] = nf;
+                    }
                 }
                 bool inside = true;
                 for (int q = 0; q < 3; ++q) inside = inside && moved[q] >= 1 && moved[q] <= a.nn[q] - 3;
@@ -510,7 +588,8 @@ __device__ __forceinline__ void g2p2g_tile(const BatchMap& m, int gt, int cur, i
                     for (int q = 0; q < 3; ++q) { cell[q] = moved[q]; f[q] = nfr[q]; }
                     glb(a.cell)[id] = pack_cell(cell);
                     for (int q = 0; q < 3; ++q) glb(a.soa)[(size_t)(F0 + q) * a.n + id] = f[q];
-                    for (int q = 0; q < 9; ++q) glb(a.soa)[(size_t)(G0 + q) * a.n + id] = G[q];
+                    if (!obj)
+                        for (int q = 0; q < 9; ++q) glb(a.soa)[(size_t)(G0 + q) * a.n + id] = G[q];
                 }
                 if (id == a.e) {
                     a.st->xe_cell[par ^ 1] = pack_cell(cell);
@@ -527,12 +606,13 @@ __device__ __forceinline__ void g2p2g_tile(const BatchMap& m, int gt, int cur, i
                     dir = dir * 3 + (dd + 1);
                 }
             }
-            if (store_vc && fin) {
+            if (store_vc && fin && !obj) {
                 for (int q = 0; q < 3; ++q) glb(a.soa)[(size_t)(V0 + q) * a.n + id] = v[q];
                 for (int q = 0; q < 9; ++q) glb(a.soa)[(size_t)(C0 + q) * a.n + id] = C[q];
             }
             // ---- transfer to the grid of the next exchange
-            err |= p2g_particle<TL>(acc, orgP, cell, f, v, C, G, with_stress, a);
+            if (obj) err |= p2g_object(a, cell, f);
+            else err |= p2g_particle<TL>(acc, orgP, cell, f, v, C, G, with_stress, a);
         }
         if (fin) {
             // stable rank of this particle among the tile's particles that move to

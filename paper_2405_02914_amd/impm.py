@@ -37,7 +37,8 @@ class sim_params(C.Structure):
         ("radius", C.c_double), ("half_length", C.c_double), ("half_extent", C.c_double * 3),
         ("fillet", C.c_double), ("pose0", C.c_double * 7), ("stress_each_pass", C.c_int32),
         ("_pad1", C.c_int32), ("hf_n", C.c_int32), ("_pad2", C.c_int32), ("hf_half", C.c_double),
-        ("hf", C.POINTER(C.c_double)),
+        ("hf", C.POINTER(C.c_double)), ("object_mode", C.c_int32), ("_pad3", C.c_int32),
+        ("object_density", C.c_double), ("object_cap", C.c_double),
     ]
 
 
@@ -143,6 +144,9 @@ def to_params(p) -> sim_params:
     q.fillet = p.fillet
     q.pose0[:] = list(p.pose0)
     q.stress_each_pass = p.stress_each_pass
+    q.object_mode = getattr(p, "object_mode", 0)
+    q.object_density = getattr(p, "object_density", p.rho)
+    q.object_cap = getattr(p, "object_cap", 2.5e-3)
     if getattr(p, "hf", None) is not None:
         t = np.ascontiguousarray(p.hf, np.float64)
         q.hf_n, q.hf_half = t.shape[0], p.hf_half

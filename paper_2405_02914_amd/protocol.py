@@ -1,0 +1,92 @@
+"""The slip and rotation protocol of the paper's experiments (Sec. IV-A and
+V-B), run on synthetic inputs through the C ABI: the holed-disc indenter is
+pressed 0.5 mm into the full-resolution slab, then slid in 1 mm increments up
+to 5 mm, or rotated in 5 degree increments up to 45 degrees, once with the
+improved method (IMPM, Algorithm 1) and once with the plain single-exchange
+MPM the paper compares it against ("normal").  A height map is taken after the
+press and after every increment.
+
+The paper's comparison is against photographs, which are absent; what can be
+reproduced is its description of the two simulations (Sec. V-B): under slip
+the plain method's surface loses the indenter's central hole, and under
+rotation the plain method, lacking the fixed bottom layer, lets the unpressed
+hole region sink deeper.  `hole_metrics` measures both from a height map.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import impm, workloads as W
+
+
+def run(params, segs, hm: int = 256):
+    """Step a sensor through `segs`, taking a hm x hm height map (mm of depth
+    below the undeformed top, positive into the slab) after every segment.
+    Returns (maps [k, hm, hm], poses [(pos, quat)], stats, seconds)."""
+    import torch
+    s = impm.Sim(params)
+    try:
+        maps, poses = [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = torch.empty(hm * hm, device="cuda", dtype=torch.float32)
+        for n, pos, q in segs:
+            s.sim_set_indenter_pose(pos, q)
+            s.sim_step(n)
+            s.sim_surface_heightmap(hm, hm, out=out)
+            maps.append(out.clone())
+            poses.append((pos, q))
+        s.sim_synchronize()
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        depth = [(params.height - m.cpu().numpy().reshape(hm, hm)) * 1e3 for m in maps]
+        return np.stack(depth), poses, s.sim_get_stats(), secs
+    finally:
+        s.close()
+
+
+def _pixel_centres(params, hm):
+    Lx, Ly = params.lengths[0], params.lengths[1]
+    u = (np.arange(hm) + 0.5) * Lx / hm
+    v = (np.arange(hm) + 0.5) * Ly / hm
+    return np.meshgrid(u, v, indexing="xy")
+
+
+def hole_metrics(params, depth_mm, pos, r_out, r_hole, fillet=0.75e-3, hole_fillet=0.3e-3,
+                 start=None, margin=0.25e-3):
+    """From one depth map (mm, rows = y): the mean depth under the indenter's
+    flat annular face and inside its hole (both at the indenter's current
+    centre `pos`), their difference (how visible the hole is), and, when the
+    slide's start position is given, the mean depth of the trace the indenter
+    left behind (the swept band outside the current footprint)."""
+    hm = depth_mm.shape[0]
+    X, Y = _pixel_centres(params, hm)
+    r = np.hypot(X - pos[0], Y - pos[1])
+    face = (r >= r_hole + hole_fillet + margin) & (r <= r_out - fillet - margin)
+    hole = r <= r_hole - margin
+    out = {"face_mm": float(depth_mm[face].mean()), "hole_mm": float(depth_mm[hole].mean())}
+    out["hole_contrast_mm"] = out["face_mm"] - out["hole_mm"]
+    if start is not None and abs(pos[0] - start[0]) > r_out:
+        lo, hi = sorted((start[0], pos[0]))
+        band = (np.abs(Y - start[1]) <= r_out - fillet) & (X >= lo) & (X <= hi) & (r > r_out + 2 * margin)
+        out["trace_mm"] = float(depth_mm[band].mean()) if band.any() else 0.0
+    return out
+
+
+def protocol(kind: str, sign: float = -1.0, dx: float = 0.25e-3, cells=(128, 128, 32), hm: int = 256,
+             r_out: float = 4.0e-3, r_hole: float = 1.5e-3, **sched_kw):
+    """Both methods through one protocol ("slip" or "rotate"; sign -1: leftward
+    or clockwise).  Returns a dict with the per-increment metrics of each
+    method, its stats and its particle-updates per second."""
+    res = {}
+    for name, mode in (("impm", W.MODE_IMPM), ("normal", W.MODE_PLAIN)):
+        p = W.protocol_sensor(dx=dx, cells=cells, r_out=r_out, r_hole=r_hole, mode=mode)
+        segs = W.protocol_schedule(p.pose0, kind, sign=sign, **sched_kw)
+        maps, poses, st, secs = run(p, segs, hm)
+        rows = [hole_metrics(p, d, pz[0], r_out, r_hole, start=p.pose0[:3]) for d, pz in zip(maps, poses)]
+        res[name] = {"metrics": rows, "passes_per_step": st["passes"] / max(st["steps"], 1),
+                     "limit_hits": st["limit_hits"], "steps": st["steps"],
+                     "particle_updates_per_s": p.n_particles * st["steps"] / secs, "seconds": secs}
+    return res

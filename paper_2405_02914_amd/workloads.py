@@ -50,6 +50,10 @@ class SensorParams:
     # height-field indenter: (n, n) body-frame heights over [-hf_half, hf_half]^2
     hf: object = dataclasses.field(default=None, compare=False, repr=False)
     hf_half: float = 0.0
+    # object representation: 0 rigid collider at the grid, 1 object particles
+    object_mode: int = 0
+    object_density: float = 1000.0    # kg/m^3 of the object particles
+    object_cap: float = 2.5e-3        # object particles fill the body this far above its lowest point
 
     @property
     def n_particles(self) -> int:
@@ -116,6 +120,65 @@ def heightfield_table(seed: int, footprint: float, amplitude: float, wavelength:
         + (X * X + Y * Y) / (2.0 * bowl_radius)
     disc = X * X + Y * Y <= footprint * footprint
     return z - z[disc].min()
+
+
+def holed_disc_table(r_out: float, r_hole: float, fillet: float, hole_fillet: float,
+                     hole_depth: float, n: int = 129):
+    """Lower surface of a flat-faced disc indenter with a central circular hole
+    (a stand-in for an indenter with a recessed centre): height 0 on the
+    annular face r_hole <= r <= r_out - fillet, the outer edge rounded with
+    radius `fillet` up to height `fillet` at r = r_out, the hole's edge rounded
+    with radius `hole_fillet` down from the face, and the hole floor at
+    `hole_depth` above the face.  Sampled on an n x n lattice over
+    [-r_out, r_out]^2 (row j = y); the footprint disc is r <= r_out."""
+    t = np.linspace(-r_out, r_out, n)
+    X, Y = np.meshgrid(t, t, indexing="xy")
+    r = np.hypot(X, Y)
+    z = np.zeros_like(r)
+    edge = r > r_out - fillet
+    q = np.clip(r[edge] - (r_out - fillet), 0.0, fillet)
+    z[edge] = fillet - np.sqrt(fillet * fillet - q * q)
+    inner = r < r_hole + hole_fillet
+    q = np.clip((r_hole + hole_fillet) - r[inner], 0.0, hole_fillet)
+    z[inner] = np.minimum(hole_fillet - np.sqrt(hole_fillet * hole_fillet - q * q), hole_depth)
+    z[r <= r_hole] = hole_depth
+    return z
+
+
+def protocol_sensor(dx: float = 0.25e-3, cells=(128, 128, 32), r_out: float = 4.0e-3,
+                    r_hole: float = 1.5e-3, mode: int = MODE_IMPM, subcycle: int = 4, **kw) -> SensorParams:
+    """The slab of the full-resolution sensor with the holed-disc indenter
+    (outer edge rounded 0.75 mm, hole edge 0.3 mm, hole floor 1.0 mm above the
+    face) centred over it, its face touching the top surface."""
+    L, H = cells[0] * dx, cells[2] * dx
+    pad = padding_for(dx)
+    tab = holed_disc_table(r_out, r_hole, 0.75e-3, 0.3e-3, 1.0e-3)
+    p = SensorParams(cells=tuple(cells), dx=dx, pad_lateral=pad, pad_top=pad, mode=mode, subcycle=subcycle,
+                     shape=SHAPE_HEIGHTFIELD, hf=tab, hf_half=r_out,
+                     pose0=(L / 2, cells[1] * dx / 2, H, 1.0, 0.0, 0.0, 0.0))
+    return p.replace(**kw) if kw else p
+
+
+def protocol_schedule(pose0, kind: str, sign: float = 1.0, press: float = 0.5e-3, n_press: int = 250,
+                      increments: int = 5, step_mm: float = 1.0, step_deg: float = 5.0,
+                      n_per_increment: int = 500, n_per_degree_step: int = 250):
+    """The slip / rotation protocol of the paper's experiments (Sec. IV-A),
+    synthetic: press `press` straight down over n_press substeps, then either
+    slip `increments` steps of `step_mm` mm along sign * x ("slip") or rotate
+    `increments` steps of `step_deg` degrees about the normal, sign +1 counter-
+    clockwise ("rotate").  Returns the segment list (n, target_pos,
+    target_quat); a height map is taken after the press and after every
+    increment (the caller takes one per segment)."""
+    x0, y0, z0 = pose0[:3]
+    segs = [(n_press, (x0, y0, z0 - press), (1.0, 0.0, 0.0, 0.0))]
+    for k in range(1, increments + 1):
+        if kind == "slip":
+            segs.append((n_per_increment, (x0 + sign * step_mm * 1e-3 * k, y0, z0 - press), (1.0, 0.0, 0.0, 0.0)))
+        elif kind == "rotate":
+            segs.append((n_per_degree_step, (x0, y0, z0 - press), quat_about_z(sign * step_deg * k)))
+        else:
+            raise ValueError(kind)
+    return segs
 
 
 def quat_about_z(deg: float) -> tuple:
