@@ -111,6 +111,17 @@ typedef struct {
     int32_t _pad3;
     double object_density;     /* kg/m^3, > 0 with SIM_OBJECT_PARTICLES */
     double object_cap;         /* m, > 0 with SIM_OBJECT_PARTICLES */
+    /* Shaped elastomer (Sec. VI: the shape of the elastomer particle cloud can be
+     * adjusted): NULL for the full Nx x Ny x Nz cuboid, else Nx * Ny column
+     * heights in cells (row j, column i; each 0..Nz): column (i, j) holds the
+     * cells k < columns[j * Nx + i] of the cuboid, so the elastomer keeps its
+     * flat bottom and takes any outline and stepped top.  Particle ids then
+     * number the kept cells in (k, j, i) order (id = kept cell * ppc + sub);
+     * each particle's jitter is that of the same particle of the cuboid.  The
+     * surface particles are the top sub-layer of each column's top cell, and
+     * the height map's rest height under a pixel is that of its column (0 where
+     * the column is empty).  The table is caller memory, copied by sim_create. */
+    const uint8_t* columns;
 } sim_params;
 
 typedef struct {

@@ -95,6 +95,11 @@ typedef struct {
     int32_t _pad3;
     double object_density;
     double object_cap;
+    /* elastomer shape (Sec. VI: the elastomer particle cloud shaped at will):
+     * NULL for the full cuboid, else Nx * Ny column heights in cells (row j,
+     * column i, each 0..Nz): column (i, j) holds cells k < columns[j Nx + i],
+     * so the slab keeps its flat glued bottom and takes any outline and top */
+    const uint8_t *columns;
 } orc_params;
 
 typedef struct {
@@ -120,6 +125,7 @@ typedef struct {
     int64_t log_cap, log_len;
     int32_t error;             /* 1: a stencil left the grid, 2: non-finite state, 3: det F <= 0 */
     double *hf_copy;           /* the height-field table (shape 4) */
+    uint8_t *col_copy;         /* the column heights (NULL: the full cuboid) */
     int32_t threads;           /* OpenMP threads of the timing leg (1: the plain serial loops) */
     double *Mt, *MGt;          /* per-thread node sums of the parallel particle-to-grid */
     int64_t n_obj;             /* object particles (object_mode 1) */
@@ -479,6 +485,7 @@ void orc_destroy(orc_sim *s) {
     free((void *)s->hf_copy);
     free(s->obj_body); free(s->obj_x);
     free(s->Mt); free(s->MGt);
+    free(s->col_copy);
     free(s);
 }
 
@@ -497,7 +504,19 @@ orc_sim *orc_create(const orc_params *P) {
         s->P.hf = NULL;
     }
     int Nx = P->cells[0], Ny = P->cells[1], Nz = P->cells[2];
-    s->n = (int64_t)Nx * Ny * Nz * P->ppc;
+    int64_t n_cells = (int64_t)Nx * Ny * Nz;
+    s->P.columns = NULL;
+    if (P->columns) {
+        s->col_copy = (uint8_t *)malloc((size_t)Nx * Ny);
+        memcpy(s->col_copy, P->columns, (size_t)Nx * Ny);
+        s->P.columns = s->col_copy;
+        n_cells = 0;
+        for (int64_t q = 0; q < (int64_t)Nx * Ny; ++q) {
+            if (P->columns[q] > Nz) { orc_destroy(s); return NULL; }
+            n_cells += P->columns[q];
+        }
+    }
+    s->n = n_cells * P->ppc;
     s->nn[0] = Nx + 2 * P->pad_lateral + 1;
     s->nn[1] = Ny + 2 * P->pad_lateral + 1;
     s->nn[2] = Nz + P->pad_bottom + P->pad_top + 1;
@@ -518,20 +537,29 @@ orc_sim *orc_create(const orc_params *P) {
     s->mp = P->rho * s->Vp;
     double H = (double)Nz * P->dx;
 
-    /* stratified jitter: m^3 sub-cells per cell, one particle uniform in each */
+    /* stratified jitter: m^3 sub-cells per cell, one particle uniform in each.
+     * A shaped elastomer keeps the cells k < columns[j Nx + i], numbered in the
+     * same (k, j, i) order; a particle's jitter is that of the same particle of
+     * the full cuboid (its draw is counted by the cuboid id), so a shaped
+     * cloud is a subset of the cuboid's. */
+    int64_t kept = 0;
     for (int k = 0; k < Nz; ++k)
         for (int j = 0; j < Ny; ++j)
-            for (int i = 0; i < Nx; ++i)
+            for (int i = 0; i < Nx; ++i) {
+                if (s->P.columns && k >= s->P.columns[(int64_t)j * Nx + i]) continue;
+                int top_k = s->P.columns ? s->P.columns[(int64_t)j * Nx + i] - 1 : Nz - 1;
+                int64_t cell_full = ((int64_t)k * Ny + j) * Nx + i;
+                int64_t cell = kept++;
                 for (int sz = 0; sz < m; ++sz)
                     for (int sy = 0; sy < m; ++sy)
                         for (int sx = 0; sx < m; ++sx) {
-                            int64_t cell = ((int64_t)k * Ny + j) * Nx + i;
-                            int64_t id = cell * P->ppc + (sz * m + sy) * m + sx;
+                            int64_t sub = (sz * m + sy) * m + sx;
+                            int64_t id = cell * P->ppc + sub, id_full = cell_full * P->ppc + sub;
                             int cidx[3] = {i, j, k}, sidx[3] = {sx, sy, sz};
                             for (int a = 0; a < 3; ++a) {
                                 /* in-cell offset r in [0,1), rounded to FP32 so that the
                                  * start state is exactly representable on an FP32 device */
-                                double u = sm64_unit(P->seed, (uint64_t)(3 * id + a + 1));
+                                double u = sm64_unit(P->seed, (uint64_t)(3 * id_full + a + 1));
                                 float r = (float)(((double)sidx[a] + u) / (double)m);
                                 double xa = ((double)cidx[a] + (double)r) * P->dx;
                                 s->x[3 * id + a] = xa;
@@ -539,8 +567,9 @@ orc_sim *orc_create(const orc_params *P) {
                             }
                             s->F[9 * id + 0] = 1.0; s->F[9 * id + 4] = 1.0; s->F[9 * id + 8] = 1.0;
                             s->bottom[id] = s->Xrest[3 * id + 2] < P->fixed_z_fraction * H;
-                            s->surface[id] = (k == Nz - 1 && sz == m - 1);
+                            s->surface[id] = (k == top_k && sz == m - 1);
                         }
+            }
 
     memcpy(s->pos, P->pose0, 3 * sizeof(double));
     memcpy(s->quat, P->pose0 + 3, 4 * sizeof(double));
@@ -1088,12 +1117,27 @@ void orc_surface_displacement(const orc_sim *s, double *out, int W, int H) {
     free(acc);
 }
 
-/* Height map h = H_slab + u_z (row v, column u). */
+/* Height map h = H_rest + u_z (row v, column u), with H_rest the rest height
+ * of the elastomer column under the pixel centre (the slab height for the
+ * cuboid; 0 where a shaped elastomer has no column). */
 void orc_surface_heightmap(const orc_sim *s, double *out, int W, int H) {
     double *d = (double *)calloc((size_t)W * H * 3, sizeof(double));
     orc_surface_displacement(s, d, W, H);
-    double top = (double)s->P.cells[2] * s->P.dx;
-    for (size_t q = 0; q < (size_t)W * H; ++q) out[q] = top + d[3 * q + 2];
+    int Nx = s->P.cells[0], Ny = s->P.cells[1];
+    for (int v = 0; v < H; ++v)
+        for (int u = 0; u < W; ++u) {
+            double top = (double)s->P.cells[2] * s->P.dx;
+            if (s->P.columns) {
+                /* the column of the pixel centre ((u+1/2) Nx/W, (v+1/2) Ny/H) cells */
+                int i = (int)floor(((double)u + 0.5) * (double)Nx / (double)W);
+                int j = (int)floor(((double)v + 0.5) * (double)Ny / (double)H);
+                if (i > Nx - 1) i = Nx - 1;
+                if (j > Ny - 1) j = Ny - 1;
+                top = (double)s->P.columns[(int64_t)j * Nx + i] * s->P.dx;
+            }
+            size_t q = (size_t)v * W + u;
+            out[q] = top + d[3 * q + 2];
+        }
     free(d);
 }
 

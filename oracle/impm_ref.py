@@ -43,7 +43,7 @@ class _Params(C.Structure):
         ("hf_n", C.c_int32), ("_pad2", C.c_int32), ("hf_half", C.c_double),
         ("hf", C.POINTER(C.c_double)),
         ("object_mode", C.c_int32), ("_pad3", C.c_int32), ("object_density", C.c_double),
-        ("object_cap", C.c_double),
+        ("object_cap", C.c_double), ("columns", C.POINTER(C.c_uint8)),
     ]
 
 
@@ -133,6 +133,10 @@ def to_params(p) -> _Params:
     q.pose0[:] = list(p.pose0)
     q.stress_each_pass = p.stress_each_pass
     q.object_mode, q.object_density, q.object_cap = p.object_mode, p.object_density, p.object_cap
+    if getattr(p, "columns", None) is not None:
+        cols = np.ascontiguousarray(p.columns, np.uint8)
+        q.columns = cols.ctypes.data_as(C.POINTER(C.c_uint8))
+        q._keep_cols = cols              # the oracle copies the table at creation
     if getattr(p, "hf", None) is not None:
         t = np.ascontiguousarray(p.hf, np.float64)
         q.hf_n, q.hf_half = t.shape[0], p.hf_half

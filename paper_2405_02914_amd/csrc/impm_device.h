@@ -110,7 +110,8 @@ struct SurfArgs {
     double pitch_x, pitch_y;     // slab cells per pixel
     float dx;
     long long n;
-    const float* rest_r;         // 3 per surface particle: in-cell rest offsets
+    const float4* rest_r;        // per surface slot (column, sub-column): in-cell rest offsets, rest cell z
+    const int32_t* surf_of;      // surface slot of each elastomer particle id (-1: not a surface particle)
     const uint32_t* id_of;       // particle id of each storage slot
     unsigned long long* acc;     // H*W x 4 fixed-point sums (w, w ux, w uy, w uz), u in cells
 };
@@ -132,6 +133,7 @@ struct BatchMap {
     const int* tile_base;
     const int* node_base;
     int n;
+    int objects;               // some sensor of the launch has object particles
 };
 
 __device__ __forceinline__ int batch_find(const int* base, int n, int g) {
@@ -198,14 +200,15 @@ __device__ __forceinline__ float det_minus_one(const float Y[9]) {
     return tr + m2 + d3;
 }
 
-// Each Newton step squares the error, so once an update is below 1e-4 of the
-// size of G the next iterate is accurate to FP32 precision relative to F - R;
-// the loop stops after that update (at most 10 steps).
+// Each Newton step squares the error: after an update of max-norm u the
+// iterate's error is at most about 4.5 u^2 (the factor covers the change of
+// norms), so the loop stops after the first update with u^2 <= 2^-27 gs, which
+// leaves an error below half an FP32 ulp of gs = max |G| (at most 10 steps).
 __device__ __forceinline__ void polar_rotation_minus_identity(const float G[9], float Q[9]) {
     float gs = 0.0f;
 #pragma unroll
     for (int k = 0; k < 9; ++k) { Q[k] = G[k]; gs = fmaxf(gs, fabsf(G[k])); }
-    const float tol = 1e-4f * gs;
+    const float tol2 = 7.4505806e-9f * gs;   // 2^-27 gs
     for (int it = 0; it < 10; ++it) {
         const float tr = Q[0] + Q[4] + Q[8];
         float cof[9];
@@ -234,7 +237,7 @@ __device__ __forceinline__ void polar_rotation_minus_identity(const float G[9], 
             diff = fmaxf(diff, fabsf(nq - Q[k]));
             Q[k] = nq;
         }
-        if (diff <= tol) break;
+        if (diff * diff <= tol2) break;
     }
 }
 

@@ -24,8 +24,8 @@ __global__ void k_compact(KArgs a, int cur, float* soa_dst, uint32_t* cell_dst, 
                           const uint32_t* id_src, uint32_t* id_dst, long long* e_out);
 __global__ void k_surface_accum(KArgs a, SurfArgs s);
 __global__ void k_depthmap(KArgs a, DepthArgs g, float* out);
-__global__ void k_surface_finish(const unsigned long long* acc, int npix, float top, float dx, int mode,
-                                 float* out);
+__global__ void k_surface_finish(const unsigned long long* acc, int npix, int W, float top, float dx, int mode,
+                                 float* out, const uint8_t* cols, int Nx, int Ny);
 }  // namespace impm
 
 using namespace impm;
@@ -137,8 +137,14 @@ struct sim_s {
     bool args_valid = false;
     StepPose* poses = nullptr;
     long long pose_cap = 0;
-    float* surf_rest = nullptr;
+    float4* surf_rest = nullptr;  // per surface slot: rest offsets, rest cell height
+    int32_t* d_surf_of = nullptr; // surface slot of each elastomer id (-1: none)
     long long n_surf = 0;
+    // shaped elastomer: column heights (empty: the cuboid), and per kept cell
+    // (particle id / ppc) the index of the cuboid cell it is
+    std::vector<uint8_t> cols_host;
+    std::vector<long long> kept_cell;
+    uint8_t* d_cols = nullptr;
     unsigned long long* surf_acc = nullptr;   // 4 per pixel
     long long surf_cap = 0;
     float* out_tmp = nullptr;
@@ -839,6 +845,14 @@ static int validate(const sim_params* p, std::string& why) {
     double qn = 0;
     for (int k = 3; k < 7; ++k) qn += p->pose0[k] * p->pose0[k];
     if (!(qn > 0)) { why = "pose0 quaternion is zero"; return SIM_EINVAL; }
+    if (p->columns) {
+        long long cells = 0;
+        for (long long q = 0; q < (long long)p->cells[0] * p->cells[1]; ++q) {
+            if (p->columns[q] > p->cells[2]) { why = "column heights must be <= cells[2]"; return SIM_EINVAL; }
+            cells += p->columns[q];
+        }
+        if (cells == 0) { why = "the shaped elastomer has no cell"; return SIM_EINVAL; }
+    }
     if (p->object_mode != SIM_OBJECT_COLLIDER && p->object_mode != SIM_OBJECT_PARTICLES) {
         why = "bad object_mode";
         return SIM_EINVAL;
@@ -872,11 +886,21 @@ int sim_create(const sim_params* p, void* hip_stream, sim_t** out) {
         s->P.hf = nullptr;
         s->P.hf_n = 0;
     }
+    if (p->columns) {
+        s->cols_host.assign(p->columns, p->columns + (size_t)p->cells[0] * p->cells[1]);
+        s->P.columns = s->cols_host.data();
+    }
     const sim_params& P = s->P;
     for (int k = 1; k <= 4; ++k) if (k * k * k == P.ppc) s->m = k;
     const int m = s->m;
     const int Nx = P.cells[0], Ny = P.cells[1], Nz = P.cells[2];
-    s->n_el = (long long)Nx * Ny * Nz * P.ppc;
+    // the kept cells of the (shaped) elastomer in (k, j, i) order
+    for (int k = 0; k < Nz; ++k)
+        for (int j = 0; j < Ny; ++j)
+            for (int i = 0; i < Nx; ++i)
+                if (!P.columns || k < P.columns[(size_t)j * Nx + i])
+                    s->kept_cell.push_back(((long long)k * Ny + j) * Nx + i);
+    s->n_el = (long long)s->kept_cell.size() * P.ppc;
     s->nn[0] = Nx + 2 * P.pad_lateral + 1;
     s->nn[1] = Ny + 2 * P.pad_lateral + 1;
     s->nn[2] = Nz + P.pad_bottom + P.pad_top + 1;
@@ -931,34 +955,39 @@ int sim_create(const sim_params* p, void* hip_stream, sim_t** out) {
     std::vector<uint32_t> cells(n);
     std::vector<uint8_t> flags(n);
     s->n_surf = (long long)Nx * Ny * m * m;
-    std::vector<float> srest((size_t)s->n_surf * 3);
+    std::vector<float4> srest((size_t)s->n_surf, make_float4(0.f, 0.f, 0.f, 0.f));
+    std::vector<int32_t> surf_of((size_t)s->n_el, -1);
     const double H = (double)Nz * P.dx;
-    for (int k = 0; k < Nz; ++k)
-        for (int j = 0; j < Ny; ++j)
-            for (int i = 0; i < Nx; ++i)
-                for (int sz = 0; sz < m; ++sz)
-                    for (int sy = 0; sy < m; ++sy)
-                        for (int sx = 0; sx < m; ++sx) {
-                            const long long cid = ((long long)k * Ny + j) * Nx + i;
-                            const long long id = cid * P.ppc + (sz * m + sy) * m + sx;
-                            const int ci[3] = {i, j, k}, si[3] = {sx, sy, sz};
-                            const int gc[3] = {i + P.pad_lateral, j + P.pad_lateral, k + P.pad_bottom};
-                            float r[3];
-                            for (int a = 0; a < 3; ++a) {
-                                r[a] = rest_offset(P.seed, id, a, si[a], m);
-                                host[(size_t)(F0 + a) * n + id] = r[a];
-                            }
-                            cells[id] = pack_cell(gc);
-                            const double z = ((double)ci[2] + (double)r[2]) * P.dx;
-                            uint8_t fl = 0;
-                            if (z < P.fixed_z_fraction * H) fl |= FLAG_BOTTOM;
-                            if (k == Nz - 1 && sz == m - 1) {
-                                fl |= FLAG_SURFACE;
-                                const long long sidx = ((long long)j * Nx + i) * m * m + sy * m + sx;
-                                for (int a = 0; a < 3; ++a) srest[3 * sidx + a] = r[a];
-                            }
-                            flags[id] = fl;
-                        }
+    for (long long cell = 0; cell < (long long)s->kept_cell.size(); ++cell) {
+        const long long cfull = s->kept_cell[cell];
+        const int i = (int)(cfull % Nx), j = (int)((cfull / Nx) % Ny), k = (int)(cfull / ((long long)Nx * Ny));
+        const int top_k = P.columns ? P.columns[(size_t)j * Nx + i] - 1 : Nz - 1;
+        for (int sz = 0; sz < m; ++sz)
+            for (int sy = 0; sy < m; ++sy)
+                for (int sx = 0; sx < m; ++sx) {
+                    const int sub = (sz * m + sy) * m + sx;
+                    const long long id = cell * P.ppc + sub, id_full = cfull * P.ppc + sub;
+                    const int ci[3] = {i, j, k}, si[3] = {sx, sy, sz};
+                    const int gc[3] = {i + P.pad_lateral, j + P.pad_lateral, k + P.pad_bottom};
+                    float r[3];
+                    for (int a = 0; a < 3; ++a) {
+                        // the jitter of the same particle of the full cuboid
+                        r[a] = rest_offset(P.seed, id_full, a, si[a], m);
+                        host[(size_t)(F0 + a) * n + id] = r[a];
+                    }
+                    cells[id] = pack_cell(gc);
+                    const double z = ((double)ci[2] + (double)r[2]) * P.dx;
+                    uint8_t fl = 0;
+                    if (z < P.fixed_z_fraction * H) fl |= FLAG_BOTTOM;
+                    if (k == top_k && sz == m - 1) {
+                        fl |= FLAG_SURFACE;
+                        const long long sidx = ((long long)j * Nx + i) * m * m + sy * m + sx;
+                        srest[sidx] = make_float4(r[0], r[1], r[2], (float)k);
+                        surf_of[id] = (int32_t)sidx;
+                    }
+                    flags[id] = fl;
+                }
+    }
     // object particles: cell and offset of their initial position, lattice
     // indices in G0..G2 (exact in FP32)
     for (long long q = 0; q < s->n_obj; ++q) {
@@ -1052,9 +1081,18 @@ int sim_create(const sim_params* p, void* hip_stream, sim_t** out) {
     }
     if (hipMalloc(&s->d_id_of, n * 4) != hipSuccess) return bail(SIM_ENOMEM);
     if (hipMemcpy(s->d_id_of, s->id_of.data(), n * 4, hipMemcpyHostToDevice) != hipSuccess) return bail(SIM_EHIP);
-    if (hipMalloc(&s->surf_rest, srest.size() * sizeof(float)) != hipSuccess) return bail(SIM_ENOMEM);
-    if (hipMemcpy(s->surf_rest, srest.data(), srest.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+    if (hipMalloc(&s->surf_rest, srest.size() * sizeof(float4)) != hipSuccess) return bail(SIM_ENOMEM);
+    if (hipMemcpy(s->surf_rest, srest.data(), srest.size() * sizeof(float4), hipMemcpyHostToDevice) != hipSuccess)
         return bail(SIM_EHIP);
+    if (hipMalloc(&s->d_surf_of, surf_of.size() * sizeof(int32_t)) != hipSuccess) return bail(SIM_ENOMEM);
+    if (hipMemcpy(s->d_surf_of, surf_of.data(), surf_of.size() * sizeof(int32_t), hipMemcpyHostToDevice) !=
+        hipSuccess)
+        return bail(SIM_EHIP);
+    if (P.columns) {
+        if (hipMalloc(&s->d_cols, s->cols_host.size()) != hipSuccess) return bail(SIM_ENOMEM);
+        if (hipMemcpy(s->d_cols, s->cols_host.data(), s->cols_host.size(), hipMemcpyHostToDevice) != hipSuccess)
+            return bail(SIM_EHIP);
+    }
     {
         std::vector<float> offs(host.begin() + (size_t)F0 * n, host.begin() + (size_t)(F0 + 3) * n);
         if (rebin_host(s, cells, offs) != SIM_OK) return bail(SIM_EHIP);
@@ -1070,7 +1108,8 @@ void sim_destroy(sim_t* s) {
     void* bufs[] = {s->soa, s->cell, s->flags, s->order[0], s->order[1], s->bstart[0], s->bstart[1],
                     s->dirrank, s->dircount, s->newcnt, s->scratch, s->gridV, s->dbgM, s->dbgMG,
                     s->st, s->poses, s->surf_rest, s->surf_acc, s->out_tmp, s->d_args, s->d_hf,
-                    s->d_id_of, s->soa_alt, s->cell_alt, s->flags_alt, s->id_of_alt, s->d_e_slot, s->objW};
+                    s->d_id_of, s->soa_alt, s->cell_alt, s->flags_alt, s->id_of_alt, s->d_e_slot, s->objW,
+                    s->d_surf_of, s->d_cols};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     for (int k = 0; k < 2; ++k) {
@@ -1126,7 +1165,7 @@ int sim_step(sim_t* s, int32_t n_substeps) {
     const long long N = (long long)npass.size();
     LaunchSet L;
     L.ops = &kTileOps[s->tile_idx];
-    L.m = BatchMap{s->d_args, nullptr, nullptr, 1};
+    L.m = BatchMap{s->d_args, nullptr, nullptr, 1, s->n_obj > 0 ? 1 : 0};
     L.tile_blocks = s->n_tiles;
     L.node_blocks = (int)((s->n_nodes + kBlock - 1) / kBlock);
     L.n = 1;
@@ -1226,13 +1265,15 @@ static int surface_raster(sim_t* s, float* out, int W, int H, int on_device, int
     sa.dx = (float)s->P.dx;
     sa.n = s->n;
     sa.rest_r = s->surf_rest;
+    sa.surf_of = s->d_surf_of;
     sa.id_of = s->d_id_of;
     sa.acc = s->surf_acc;
     hipLaunchKernelGGL(k_fill, dim3(std::min<long long>((npix * 8 + 255) / 256, 4096)), dim3(256), 0, s->stream,
                        reinterpret_cast<float*>(s->surf_acc), npix * 8, 0.0f);
     hipLaunchKernelGGL(k_surface_accum, dim3((unsigned)((s->n + 255) / 256)), dim3(256), 0, s->stream, a, sa);
     hipLaunchKernelGGL(k_surface_finish, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, s->stream,
-                       s->surf_acc, (int)npix, (float)(s->P.cells[2] * s->P.dx), (float)s->P.dx, mode, dst);
+                       s->surf_acc, (int)npix, W, (float)(s->P.cells[2] * s->P.dx), (float)s->P.dx, mode, dst,
+                       (const uint8_t*)s->d_cols, s->P.cells[0], s->P.cells[1]);
     HIPCHK(s, hipGetLastError());
     if (!on_device) {
         HIPCHK(s, hipMemcpyAsync(out, dst, nout * sizeof(float), hipMemcpyDeviceToHost, s->stream));
@@ -1303,6 +1344,7 @@ int sim_surface_heightmap_noalloc(sim_t* s, float* out_device, int32_t W, int32_
     sa.dx = (float)s->P.dx;
     sa.n = s->n;
     sa.rest_r = s->surf_rest;
+    sa.surf_of = s->d_surf_of;
     sa.id_of = s->d_id_of;
     sa.acc = acc;
     // the accumulators keep the previous call's sums: clear them with a kernel
@@ -1311,7 +1353,8 @@ int sim_surface_heightmap_noalloc(sim_t* s, float* out_device, int32_t W, int32_
                        reinterpret_cast<float*>(acc), npix * 8, 0.0f);
     hipLaunchKernelGGL(k_surface_accum, dim3((unsigned)((s->n + 255) / 256)), dim3(256), 0, s->stream, a, sa);
     hipLaunchKernelGGL(k_surface_finish, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, s->stream, acc,
-                       (int)npix, (float)(s->P.cells[2] * s->P.dx), (float)s->P.dx, 0, out_device);
+                       (int)npix, W, (float)(s->P.cells[2] * s->P.dx), (float)s->P.dx, 0, out_device,
+                       (const uint8_t*)s->d_cols, s->P.cells[0], s->P.cells[1]);
     const hipError_t e = hipGetLastError();
     if (prev != s->device) (void)hipSetDevice(prev);
     HIPCHK(s, e);
@@ -1446,13 +1489,13 @@ int sim_read_rest(sim_t* s, double* X, uint8_t* flags) {
     const int m = s->m;
     if (X) {
         for (long long id = 0; id < s->n_el; ++id) {
-            const long long cid = id / P.ppc;
+            const long long cid = s->kept_cell[id / P.ppc];     // the cuboid cell of the particle
             const int sub = (int)(id % P.ppc);
             const int ci[3] = {(int)(cid % P.cells[0]), (int)((cid / P.cells[0]) % P.cells[1]),
                                (int)(cid / ((long long)P.cells[0] * P.cells[1]))};
             const int si[3] = {sub % m, (sub / m) % m, sub / (m * m)};
             for (int a = 0; a < 3; ++a)
-                X[3 * id + a] = ((double)ci[a] + (double)rest_offset(P.seed, id, a, si[a], m)) * P.dx;
+                X[3 * id + a] = ((double)ci[a] + (double)rest_offset(P.seed, cid * P.ppc + sub, a, si[a], m)) * P.dx;
         }
     }
     if (flags) {
@@ -1739,7 +1782,9 @@ int sim_batch_step(sim_batch_t* b, int32_t n_substeps) {
     for (auto& g : b->groups) {
         LaunchSet L;
         L.ops = &kTileOps[g.tile_idx];
-        L.m = BatchMap{g.d_args, g.d_tile_base, g.d_node_base, (int)g.members.size()};
+        int objects = 0;
+        for (int mi : g.members) objects |= b->sims[mi]->n_obj > 0 ? 1 : 0;
+        L.m = BatchMap{g.d_args, g.d_tile_base, g.d_node_base, (int)g.members.size(), objects};
         L.tile_blocks = g.tile_blocks;
         L.node_blocks = g.node_blocks;
         L.n = (int)g.members.size();

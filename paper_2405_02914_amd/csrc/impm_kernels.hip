@@ -360,7 +360,7 @@ __device__ __forceinline__ void grid_block(const BatchMap& m, int gnb, int sbin,
 //     next step, and transfer it to the grid of the next step's first pass;
 //     otherwise transfer it (same x and F, new v and C) to the next pass's grid.
 // EXTRA marks the launches for passes after the first of a step.
-template <class TL, bool EXTRA>
+template <class TL, bool EXTRA, bool OBJ>
 __device__ __forceinline__ void g2p2g_tile(const BatchMap& m, int gt, int cur, int step, int par, int pass,
                                            int store_vc) {
     int s = 0, t = gt;
@@ -544,7 +544,7 @@ __device__ __forceinline__ void g2p2g_tile(const BatchMap& m, int gt, int cur, i
             if (a.bottom_rule && (fl & FLAG_BOTTOM)) v[2] = 0.f;
             // an object particle (G0..G2 hold its body lattice indices) takes no
             // part in the gather's result: its velocity is the prescribed motion
-            const bool obj = a.objW != nullptr && (fl & FLAG_OBJECT);
+            const bool obj = OBJ && (fl & FLAG_OBJECT);
             if (fin) {
                 int perr = 0;
                 int moved[3];
@@ -680,15 +680,17 @@ __global__ __launch_bounds__(kBlock) void k_grid(BatchMap m, int total, int sbin
     for (int nb = blockIdx.x; nb < total; nb += gridDim.x) grid_block<TL, EXTRA>(m, nb, sbin, step, pass);
 }
 
-template <class TL, bool EXTRA>
+// OBJ: the launch covers object particles (a separate instantiation, so that
+// sensors without them run the kernel without the object branches).
+template <class TL, bool EXTRA, bool OBJ>
 __global__ __launch_bounds__(TL::NT) void k_g2p2g(BatchMap m, int total, int cur, int step, int par, int pass,
                                                   int store_vc) {
     if (!EXTRA) {
-        g2p2g_tile<TL, EXTRA>(m, blockIdx.x, cur, step, par, pass, store_vc);
+        g2p2g_tile<TL, EXTRA, OBJ>(m, blockIdx.x, cur, step, par, pass, store_vc);
         return;
     }
     for (int gt = blockIdx.x; gt < total; gt += gridDim.x) {
-        g2p2g_tile<TL, EXTRA>(m, gt, cur, step, par, pass, store_vc);
+        g2p2g_tile<TL, EXTRA, OBJ>(m, gt, cur, step, par, pass, store_vc);
         __syncthreads();   // the next tile reuses the block's LDS
     }
 }
@@ -699,7 +701,7 @@ __global__ __launch_bounds__(TL::NT) void k_g2p2g(BatchMap m, int total, int cur
 // so a step that converged at its first pass costs one short launch.  Agent-
 // scope fences around each barrier publish this phase's writes (node
 // velocities, tile partials, flags) and drop stale lines from the vector cache.
-template <class TL>
+template <class TL, bool OBJ>
 __global__ __launch_bounds__(TL::NT) void k_extra_passes(BatchMap m, int tiles, int node_blocks, int cur, int step,
                                                          int par, int npass, int store_vc) {
     cooperative_groups::grid_group grid = cooperative_groups::this_grid();
@@ -713,7 +715,7 @@ __global__ __launch_bounds__(TL::NT) void k_extra_passes(BatchMap m, int tiles, 
         grid.sync();
         __threadfence();
         for (int gt = blockIdx.x; gt < tiles; gt += gridDim.x) {
-            g2p2g_tile<TL, true>(m, gt, cur, step, par, pass, store_vc);
+            g2p2g_tile<TL, true, OBJ>(m, gt, cur, step, par, pass, store_vc);
             __syncthreads();
         }
         __threadfence();
@@ -931,19 +933,22 @@ __global__ void k_surface_accum(KArgs a, SurfArgs s) {
     if (slot >= a.n) return;
     if (!(glb(a.flags)[slot] & FLAG_SURFACE)) return;
     const long long id = s.id_of[slot];
-    const int ppc = s.m * s.m * s.m;
-    const long long cell_id = id / ppc;
-    const int sub = (int)(id % ppc);
-    const int ci = (int)(cell_id % s.Nx), cj = (int)((cell_id / s.Nx) % s.Ny);
-    const int ck = (int)(cell_id / ((long long)s.Nx * s.Ny));
-    const int sx = sub % s.m, sy = (sub / s.m) % s.m;
-    const long long sidx = ((long long)cj * s.Nx + ci) * s.m * s.m + sy * s.m + sx;
+    // the particle's surface slot: column (ci, cj) and sub-column (sx, sy); the
+    // record holds its rest offsets and the rest cell height of its column
+    const long long sidx = s.surf_of[id];
+    if (sidx < 0) return;
+    const int sx = (int)(sidx % s.m), sy = (int)((sidx / s.m) % s.m);
+    const long long col = sidx / ((long long)s.m * s.m);
+    const int ci = (int)(col % s.Nx), cj = (int)(col / s.Nx);
+    const float4 rr = s.rest_r[sidx];
+    const int ck = (int)rr.w;
     int cell[3];
     float f[3];
     load_particle(a, slot, cell, f);
     const int rc[3] = {ci + s.pad_l, cj + s.pad_l, ck + s.pad_b};
+    const float r3[3] = {rr.x, rr.y, rr.z};
     float u[3];
-    for (int q = 0; q < 3; ++q) u[q] = (float)(cell[q] - rc[q]) + (f[q] - s.rest_r[3 * sidx + q]);
+    for (int q = 0; q < 3; ++q) u[q] = (float)(cell[q] - rc[q]) + (f[q] - r3[q]);
     const double px = ((double)(cell[0] - s.pad_l) + (double)f[0]) / s.pitch_x - 0.5;
     const double py = ((double)(cell[1] - s.pad_l) + (double)f[1]) / s.pitch_y - 0.5;
     const int bx = (int)floor(px + 0.5) - 1, by = (int)floor(py + 0.5) - 1;
@@ -1018,15 +1023,26 @@ __global__ __launch_bounds__(256) void k_depthmap(KArgs a, DepthArgs g, float* _
     out[q] = hit ? (float)((g.top - (g.c[2] + zb)) * g.scale) : -1e9f;
 }
 
-__global__ void k_surface_finish(const unsigned long long* __restrict__ acc, int npix, float top,
-                                 float dx, int mode, float* __restrict__ out) {
+// The height map's rest height under a pixel is the slab height, or with a
+// shaped elastomer that of the column under the pixel centre (cols: Nx x Ny
+// heights in cells, null for the cuboid).
+__global__ void k_surface_finish(const unsigned long long* __restrict__ acc, int npix, int W, float top,
+                                 float dx, int mode, float* __restrict__ out, const uint8_t* __restrict__ cols,
+                                 int Nx, int Ny) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= npix) return;
     long long v[4];
     for (int k = 0; k < 4; ++k) v[k] = ((long long)(acc[4 * q + k] << 13)) >> 13;
     const double inv = v[0] > 0 ? (double)dx / (double)v[0] : 0.0;
     if (mode == 0) {
-        out[q] = top + (float)((double)v[3] * inv);
+        float rest = top;
+        if (cols) {
+            const int H = npix / W, u = q % W, vv = q / W;
+            const int i = min((int)floor(((double)u + 0.5) * (double)Nx / (double)W), Nx - 1);
+            const int j = min((int)floor(((double)vv + 0.5) * (double)Ny / (double)H), Ny - 1);
+            rest = (float)((double)cols[(size_t)j * Nx + i] * (double)dx);
+        }
+        out[q] = rest + (float)((double)v[3] * inv);
     } else {
         out[3 * q + 0] = (float)((double)v[1] * inv);
         out[3 * q + 1] = (float)((double)v[2] * inv);
@@ -1040,9 +1056,12 @@ __global__ void k_surface_finish(const unsigned long long* __restrict__ acc, int
     template __global__ void k_p2g<Tile<X, Y, Z, N>>(BatchMap, int);                              \
     template __global__ void k_grid<Tile<X, Y, Z, N>, false>(BatchMap, int, int, int, int);       \
     template __global__ void k_grid<Tile<X, Y, Z, N>, true>(BatchMap, int, int, int, int);        \
-    template __global__ void k_g2p2g<Tile<X, Y, Z, N>, false>(BatchMap, int, int, int, int, int, int); \
-    template __global__ void k_g2p2g<Tile<X, Y, Z, N>, true>(BatchMap, int, int, int, int, int, int); \
-    template __global__ void k_extra_passes<Tile<X, Y, Z, N>>(BatchMap, int, int, int, int, int, int, int);
+    template __global__ void k_g2p2g<Tile<X, Y, Z, N>, false, false>(BatchMap, int, int, int, int, int, int); \
+    template __global__ void k_g2p2g<Tile<X, Y, Z, N>, true, false>(BatchMap, int, int, int, int, int, int); \
+    template __global__ void k_g2p2g<Tile<X, Y, Z, N>, false, true>(BatchMap, int, int, int, int, int, int); \
+    template __global__ void k_g2p2g<Tile<X, Y, Z, N>, true, true>(BatchMap, int, int, int, int, int, int); \
+    template __global__ void k_extra_passes<Tile<X, Y, Z, N>, false>(BatchMap, int, int, int, int, int, int, int); \
+    template __global__ void k_extra_passes<Tile<X, Y, Z, N>, true>(BatchMap, int, int, int, int, int, int, int);
 IMPM_TILE_KERNELS(8, 8, 2, 256)
 IMPM_TILE_KERNELS(8, 8, 2, 512)
 IMPM_TILE_KERNELS(4, 8, 4, 256)
@@ -1073,24 +1092,31 @@ struct TileLaunch {
             hipLaunchKernelGGL((k_grid<TL, false>), dim3(node_blocks), dim3(kBlock), 0, st, m, node_blocks, sbin,
                                step, pass);
     }
-    static void g2p2g(const BatchMap& m, int tile_blocks, int cur, int step, int par, int pass, int store_vc,
-                      bool extra, hipStream_t st) {
+    template <bool OBJ>
+    static void g2p2g_as(const BatchMap& m, int tile_blocks, int cur, int step, int par, int pass, int store_vc,
+                         bool extra, hipStream_t st) {
         if (extra)
-            hipLaunchKernelGGL((k_g2p2g<TL, true>), dim3(std::min(tile_blocks, kExtraBlocks)), dim3(NB),
+            hipLaunchKernelGGL((k_g2p2g<TL, true, OBJ>), dim3(std::min(tile_blocks, kExtraBlocks)), dim3(NB),
                                TL::LDS_G2P2G, st, m, tile_blocks, cur, step, par, pass, store_vc);
         else
-            hipLaunchKernelGGL((k_g2p2g<TL, false>), dim3(tile_blocks), dim3(NB), TL::LDS_G2P2G, st, m, tile_blocks,
-                               cur, step, par, pass, store_vc);
+            hipLaunchKernelGGL((k_g2p2g<TL, false, OBJ>), dim3(tile_blocks), dim3(NB), TL::LDS_G2P2G, st, m,
+                               tile_blocks, cur, step, par, pass, store_vc);
     }
-    static hipError_t extra(const BatchMap& m, int tile_blocks, int node_blocks, int cur, int step, int par,
-                            int npass, int store_vc, hipStream_t st) {
+    static void g2p2g(const BatchMap& m, int tile_blocks, int cur, int step, int par, int pass, int store_vc,
+                      bool extra, hipStream_t st) {
+        if (m.objects) g2p2g_as<true>(m, tile_blocks, cur, step, par, pass, store_vc, extra, st);
+        else g2p2g_as<false>(m, tile_blocks, cur, step, par, pass, store_vc, extra, st);
+    }
+    template <bool OBJ>
+    static hipError_t extra_as(const BatchMap& m, int tile_blocks, int node_blocks, int cur, int step, int par,
+                               int npass, int store_vc, hipStream_t st) {
         static int max_blocks = 0;    // resident blocks of this kernel on the device
         if (max_blocks == 0) {
             int dev = 0, cus = 0, per = 0;
             hipError_t e = hipGetDevice(&dev);
             if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
             if (e == hipSuccess)
-                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_extra_passes<TL>, NB, TL::LDS_G2P2G);
+                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_extra_passes<TL, OBJ>, NB, TL::LDS_G2P2G);
             if (e != hipSuccess) return e;
             max_blocks = per * cus;
         }
@@ -1100,8 +1126,13 @@ struct TileLaunch {
             a_st = store_vc;
         void* args[] = {&mm, &a_tiles, &a_nodes, &a_cur, &a_step, &a_par, &a_np, &a_st};
         const int grid = std::min(max_blocks, std::max(tile_blocks, node_blocks));
-        return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_extra_passes<TL>), dim3(grid), dim3(NB),
-                                          args, (unsigned)TL::LDS_G2P2G, st);
+        return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_extra_passes<TL, OBJ>), dim3(grid),
+                                          dim3(NB), args, (unsigned)TL::LDS_G2P2G, st);
+    }
+    static hipError_t extra(const BatchMap& m, int tile_blocks, int node_blocks, int cur, int step, int par,
+                            int npass, int store_vc, hipStream_t st) {
+        return m.objects ? extra_as<true>(m, tile_blocks, node_blocks, cur, step, par, npass, store_vc, st)
+                         : extra_as<false>(m, tile_blocks, node_blocks, cur, step, par, npass, store_vc, st);
     }
     static constexpr TileOps ops() {
         return TileOps{{TX, TY, TZ}, NB, TL::PVOL, TL::LDS_G2P2G, &p2g, &grid, &g2p2g, &extra};

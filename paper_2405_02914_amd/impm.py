@@ -38,7 +38,7 @@ class sim_params(C.Structure):
         ("fillet", C.c_double), ("pose0", C.c_double * 7), ("stress_each_pass", C.c_int32),
         ("_pad1", C.c_int32), ("hf_n", C.c_int32), ("_pad2", C.c_int32), ("hf_half", C.c_double),
         ("hf", C.POINTER(C.c_double)), ("object_mode", C.c_int32), ("_pad3", C.c_int32),
-        ("object_density", C.c_double), ("object_cap", C.c_double),
+        ("object_density", C.c_double), ("object_cap", C.c_double), ("columns", C.POINTER(C.c_uint8)),
     ]
 
 
@@ -147,6 +147,10 @@ def to_params(p) -> sim_params:
     q.object_mode = getattr(p, "object_mode", 0)
     q.object_density = getattr(p, "object_density", p.rho)
     q.object_cap = getattr(p, "object_cap", 2.5e-3)
+    if getattr(p, "columns", None) is not None:
+        cols = np.ascontiguousarray(p.columns, np.uint8)
+        q.columns = cols.ctypes.data_as(C.POINTER(C.c_uint8))
+        q._keep_cols = cols              # the library copies the table at creation
     if getattr(p, "hf", None) is not None:
         t = np.ascontiguousarray(p.hf, np.float64)
         q.hf_n, q.hf_half = t.shape[0], p.hf_half

@@ -54,9 +54,13 @@ class SensorParams:
     object_mode: int = 0
     object_density: float = 1000.0    # kg/m^3 of the object particles
     object_cap: float = 2.5e-3        # object particles fill the body this far above its lowest point
+    # shaped elastomer: (Ny, Nx) column heights in cells (None: the full cuboid)
+    columns: object = dataclasses.field(default=None, compare=False, repr=False)
 
     @property
     def n_particles(self) -> int:
+        if self.columns is not None:
+            return int(np.asarray(self.columns, np.int64).sum()) * self.ppc
         return self.cells[0] * self.cells[1] * self.cells[2] * self.ppc
 
     @property
@@ -123,21 +127,26 @@ def heightfield_table(seed: int, footprint: float, amplitude: float, wavelength:
 
 
 def holed_disc_table(r_out: float, r_hole: float, fillet: float, hole_fillet: float,
-                     hole_depth: float, n: int = 129):
+                     hole_depth: float, n: int = 129, skirt: float = 0.5e-3, skirt_slope: float = 5.0):
     """Lower surface of a flat-faced disc indenter with a central circular hole
     (a stand-in for an indenter with a recessed centre): height 0 on the
     annular face r_hole <= r <= r_out - fillet, the outer edge rounded with
-    radius `fillet` up to height `fillet` at r = r_out, the hole's edge rounded
-    with radius `hole_fillet` down from the face, and the hole floor at
+    radius `fillet` up to height `fillet` at r = r_out, then a steep skirt
+    (rising skirt_slope per unit radius) out to r_out + skirt, so that the
+    solid's vertical side wall stands well above the slab; the hole's edge
+    rounded with radius `hole_fillet` down from the face and the hole floor at
     `hole_depth` above the face.  Sampled on an n x n lattice over
-    [-r_out, r_out]^2 (row j = y); the footprint disc is r <= r_out."""
-    t = np.linspace(-r_out, r_out, n)
+    [-R, R]^2 with R = r_out + skirt (row j = y); the footprint disc is r <= R."""
+    R = r_out + skirt
+    t = np.linspace(-R, R, n)
     X, Y = np.meshgrid(t, t, indexing="xy")
     r = np.hypot(X, Y)
     z = np.zeros_like(r)
     edge = r > r_out - fillet
     q = np.clip(r[edge] - (r_out - fillet), 0.0, fillet)
     z[edge] = fillet - np.sqrt(fillet * fillet - q * q)
+    out = r > r_out
+    z[out] = fillet + skirt_slope * (r[out] - r_out)
     inner = r < r_hole + hole_fillet
     q = np.clip((r_hole + hole_fillet) - r[inner], 0.0, hole_fillet)
     z[inner] = np.minimum(hole_fillet - np.sqrt(hole_fillet * hole_fillet - q * q), hole_depth)
@@ -148,13 +157,14 @@ def holed_disc_table(r_out: float, r_hole: float, fillet: float, hole_fillet: fl
 def protocol_sensor(dx: float = 0.25e-3, cells=(128, 128, 32), r_out: float = 4.0e-3,
                     r_hole: float = 1.5e-3, mode: int = MODE_IMPM, subcycle: int = 4, **kw) -> SensorParams:
     """The slab of the full-resolution sensor with the holed-disc indenter
-    (outer edge rounded 0.75 mm, hole edge 0.3 mm, hole floor 1.0 mm above the
-    face) centred over it, its face touching the top surface."""
+    (outer edge rounded 0.75 mm, a steep 0.5 mm skirt beyond it, hole edge
+    0.3 mm, hole floor 1.0 mm above the face) centred over it, its face
+    touching the top surface."""
     L, H = cells[0] * dx, cells[2] * dx
     pad = padding_for(dx)
     tab = holed_disc_table(r_out, r_hole, 0.75e-3, 0.3e-3, 1.0e-3)
     p = SensorParams(cells=tuple(cells), dx=dx, pad_lateral=pad, pad_top=pad, mode=mode, subcycle=subcycle,
-                     shape=SHAPE_HEIGHTFIELD, hf=tab, hf_half=r_out,
+                     shape=SHAPE_HEIGHTFIELD, hf=tab, hf_half=r_out + 0.5e-3,
                      pose0=(L / 2, cells[1] * dx / 2, H, 1.0, 0.0, 0.0, 0.0))
     return p.replace(**kw) if kw else p
 
@@ -179,6 +189,32 @@ def protocol_schedule(pose0, kind: str, sign: float = 1.0, press: float = 0.5e-3
         else:
             raise ValueError(kind)
     return segs
+
+
+def dome_columns(cells, dx: float, radius: float, base_cells: int, centre=None):
+    """Column heights of a shaped elastomer: a flat pad of base_cells layers
+    under a spherical cap of the given radius (m), clipped to the slab's
+    height and outline (a dome-topped gel).  Returns (Ny, Nx) uint8."""
+    Nx, Ny, Nz = cells
+    cx, cy = centre if centre is not None else (Nx * dx / 2, Ny * dx / 2)
+    x = (np.arange(Nx) + 0.5) * dx - cx
+    y = (np.arange(Ny) + 0.5) * dx - cy
+    X, Y = np.meshgrid(x, y, indexing="xy")
+    r2 = X * X + Y * Y
+    top = Nz * dx
+    cap = np.where(r2 < radius * radius, np.sqrt(np.maximum(radius * radius - r2, 0.0)) - (radius - (top - base_cells * dx)), 0.0)
+    h = base_cells + np.floor(np.maximum(cap, 0.0) / dx + 1e-9)
+    return np.clip(h, 0, Nz).astype(np.uint8)
+
+
+def disc_columns(cells, dx: float, radius: float, centre=None):
+    """Column heights of a round pad: full height inside the disc, empty outside."""
+    Nx, Ny, Nz = cells
+    cx, cy = centre if centre is not None else (Nx * dx / 2, Ny * dx / 2)
+    x = (np.arange(Nx) + 0.5) * dx - cx
+    y = (np.arange(Ny) + 0.5) * dx - cy
+    X, Y = np.meshgrid(x, y, indexing="xy")
+    return np.where(X * X + Y * Y <= radius * radius, Nz, 0).astype(np.uint8)
 
 
 def quat_about_z(deg: float) -> tuple:

@@ -48,7 +48,7 @@ def test_library_exports_every_surrogate_symbol():
 def test_binding_struct_layouts_match_header():
     """The ctypes records have the sizes the header's field lists imply."""
     from paper_2405_02914_amd import impm
-    assert ctypes.sizeof(impm.sim_params) == 12 + 4 + 8 + 8 + 8 * 4 + 4 * 8 + 8 * 2 + 8 + 8 * 2 + 24 + 8 + 56 + 8 + 8 + 8 + 8 + 8 + 8 + 8
+    assert ctypes.sizeof(impm.sim_params) == 12 + 4 + 8 + 8 + 8 * 4 + 4 * 8 + 8 * 2 + 8 + 8 * 2 + 24 + 8 + 56 + 8 + 8 + 8 + 8 + 8 + 8 + 8 + 8
     assert ctypes.sizeof(impm.sim_stats) == 8 * 5 + 8 + 56 + 24 + 8
 
 

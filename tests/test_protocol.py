@@ -9,7 +9,7 @@ from tests.conftest import gpu_available
 
 
 def test_holed_disc_table_shape():
-    t = W.holed_disc_table(4e-3, 1.5e-3, 0.75e-3, 0.3e-3, 1.0e-3, n=129)
+    t = W.holed_disc_table(4e-3, 1.5e-3, 0.75e-3, 0.3e-3, 1.0e-3, n=129, skirt=0.0)
     step = 8e-3 / 128
     x = np.arange(129) * step - 4e-3
     X, Y = np.meshgrid(x, x, indexing="xy")
@@ -18,6 +18,8 @@ def test_holed_disc_table_shape():
     assert np.all(t[r <= 1.5e-3] == 1.0e-3)                           # the hole floor
     assert np.all(t[(r > 3.26e-3) & (r <= 4e-3)] > 0.0)               # the rounded outer edge
     assert abs(t[64, 128] - 0.75e-3) < 1e-9                           # edge height at r = r_out
+    s = W.holed_disc_table(4e-3, 1.5e-3, 0.75e-3, 0.3e-3, 1.0e-3, n=129)
+    assert abs(s[64, 128] - (0.75e-3 + 5.0 * 0.5e-3)) < 1e-9          # the skirt beyond r_out
 
 
 def test_protocol_schedules():
