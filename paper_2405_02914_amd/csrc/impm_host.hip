@@ -25,7 +25,7 @@ __global__ void k_compact(KArgs a, int cur, float* soa_dst, uint32_t* cell_dst, 
 __global__ void k_surface_accum(KArgs a, SurfArgs s);
 __global__ void k_depthmap(KArgs a, DepthArgs g, float* out);
 __global__ void k_surface_finish(const unsigned long long* acc, int npix, int W, float top, float dx, int mode,
-                                 float* out, const uint8_t* cols, int Nx, int Ny);
+                                 float* out, const float* col_top, int Nx, int Ny);
 }  // namespace impm
 
 using namespace impm;
@@ -144,7 +144,7 @@ struct sim_s {
     // (particle id / ppc) the index of the cuboid cell it is
     std::vector<uint8_t> cols_host;
     std::vector<long long> kept_cell;
-    uint8_t* d_cols = nullptr;
+    float* d_col_top = nullptr;   // rest height of each column (m), shaped elastomers only
     unsigned long long* surf_acc = nullptr;   // 4 per pixel
     long long surf_cap = 0;
     float* out_tmp = nullptr;
@@ -1089,8 +1089,10 @@ int sim_create(const sim_params* p, void* hip_stream, sim_t** out) {
         hipSuccess)
         return bail(SIM_EHIP);
     if (P.columns) {
-        if (hipMalloc(&s->d_cols, s->cols_host.size()) != hipSuccess) return bail(SIM_ENOMEM);
-        if (hipMemcpy(s->d_cols, s->cols_host.data(), s->cols_host.size(), hipMemcpyHostToDevice) != hipSuccess)
+        std::vector<float> ct(s->cols_host.size());
+        for (size_t q = 0; q < ct.size(); ++q) ct[q] = (float)((double)s->cols_host[q] * P.dx);
+        if (hipMalloc(&s->d_col_top, ct.size() * sizeof(float)) != hipSuccess) return bail(SIM_ENOMEM);
+        if (hipMemcpy(s->d_col_top, ct.data(), ct.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
             return bail(SIM_EHIP);
     }
     {
@@ -1109,7 +1111,7 @@ void sim_destroy(sim_t* s) {
                     s->dirrank, s->dircount, s->newcnt, s->scratch, s->gridV, s->dbgM, s->dbgMG,
                     s->st, s->poses, s->surf_rest, s->surf_acc, s->out_tmp, s->d_args, s->d_hf,
                     s->d_id_of, s->soa_alt, s->cell_alt, s->flags_alt, s->id_of_alt, s->d_e_slot, s->objW,
-                    s->d_surf_of, s->d_cols};
+                    s->d_surf_of, s->d_col_top};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     for (int k = 0; k < 2; ++k) {
@@ -1273,7 +1275,7 @@ static int surface_raster(sim_t* s, float* out, int W, int H, int on_device, int
     hipLaunchKernelGGL(k_surface_accum, dim3((unsigned)((s->n + 255) / 256)), dim3(256), 0, s->stream, a, sa);
     hipLaunchKernelGGL(k_surface_finish, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, s->stream,
                        s->surf_acc, (int)npix, W, (float)(s->P.cells[2] * s->P.dx), (float)s->P.dx, mode, dst,
-                       (const uint8_t*)s->d_cols, s->P.cells[0], s->P.cells[1]);
+                       s->d_col_top, s->P.cells[0], s->P.cells[1]);
     HIPCHK(s, hipGetLastError());
     if (!on_device) {
         HIPCHK(s, hipMemcpyAsync(out, dst, nout * sizeof(float), hipMemcpyDeviceToHost, s->stream));
@@ -1354,7 +1356,7 @@ int sim_surface_heightmap_noalloc(sim_t* s, float* out_device, int32_t W, int32_
     hipLaunchKernelGGL(k_surface_accum, dim3((unsigned)((s->n + 255) / 256)), dim3(256), 0, s->stream, a, sa);
     hipLaunchKernelGGL(k_surface_finish, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, s->stream, acc,
                        (int)npix, W, (float)(s->P.cells[2] * s->P.dx), (float)s->P.dx, 0, out_device,
-                       (const uint8_t*)s->d_cols, s->P.cells[0], s->P.cells[1]);
+                       s->d_col_top, s->P.cells[0], s->P.cells[1]);
     const hipError_t e = hipGetLastError();
     if (prev != s->device) (void)hipSetDevice(prev);
     HIPCHK(s, e);

@@ -1024,10 +1024,10 @@ __global__ __launch_bounds__(256) void k_depthmap(KArgs a, DepthArgs g, float* _
 }
 
 // The height map's rest height under a pixel is the slab height, or with a
-// shaped elastomer that of the column under the pixel centre (cols: Nx x Ny
-// heights in cells, null for the cuboid).
+// shaped elastomer that of the column under the pixel centre (col_top: Nx x Ny
+// rest heights in metres, null for the cuboid).
 __global__ void k_surface_finish(const unsigned long long* __restrict__ acc, int npix, int W, float top,
-                                 float dx, int mode, float* __restrict__ out, const uint8_t* __restrict__ cols,
+                                 float dx, int mode, float* __restrict__ out, const float* __restrict__ col_top,
                                  int Nx, int Ny) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= npix) return;
@@ -1036,11 +1036,11 @@ __global__ void k_surface_finish(const unsigned long long* __restrict__ acc, int
     const double inv = v[0] > 0 ? (double)dx / (double)v[0] : 0.0;
     if (mode == 0) {
         float rest = top;
-        if (cols) {
+        if (col_top) {
             const int H = npix / W, u = q % W, vv = q / W;
             const int i = min((int)floor(((double)u + 0.5) * (double)Nx / (double)W), Nx - 1);
             const int j = min((int)floor(((double)vv + 0.5) * (double)Ny / (double)H), Ny - 1);
-            rest = (float)((double)cols[(size_t)j * Nx + i] * (double)dx);
+            rest = col_top[(size_t)j * Nx + i];
         }
         out[q] = rest + (float)((double)v[3] * inv);
     } else {
