@@ -22,13 +22,23 @@
  * lights (their draws are numbered 0..7 at p and 18..25 at p2; the bounce
  * direction takes draws 16 and 17).
  * Surface: the height map's samples at the pixel centres of the map, joined
- * into two triangles per cell along the (u, v)-(u+1, v+1) diagonal; the
- * visible side faces -z.  Texture: the base image, an RGB array over the
- * footprint, looked up at the nearest texel of (x / Lx, y / Ly).
+ * into two triangles per cell along the (u, v)-(u+1, v+1) diagonal; rays meet
+ * these flat triangles.  Shading normal (our reading: the paper names none):
+ * the normal (sx, sy, -1) / |.| of the slope field (sx, sy) that is linear on
+ * each triangle and, at each sample, the central-difference slope of the map
+ * (one-sided on its border), so that it is continuous across triangle edges
+ * and the same on either side of the diagonal; the visible side faces -z.
+ * Texture: the base image, an RGB array over the
+ * footprint, texel (i, j) centred at ((i + 1/2) Lx / tex_w, (j + 1/2) Ly / tex_h),
+ * interpolated bilinearly between texel centres and held constant beyond the
+ * outer centres (our reading: the paper maps the image onto the mesh by UV
+ * mapping and names no filter; a continuous lookup keeps pixels that fall on
+ * texel edges well defined).
  * Random numbers: the k-th draw of sample s of pixel q is the top 24 bits of
  * SplitMix64(seed, (q * spp + s) * 32 + k + 1), scaled by 2^-24 (exact in
  * FP32 and FP64, so both implementations draw the same numbers).
- * Compiled with -ffp-contract=off.
+ * Compiled with -ffp-contract=off; pixels are independent, so they run on
+ * OpenMP threads without changing any result.
  */
 #include <math.h>
 #include <stdint.h>
@@ -75,7 +85,17 @@ static void vertex(const surf *S, int u, int v, double *out) {
     out[2] = S->h[(int64_t)v * S->P->W + u];
 }
 
-/* Height and unit normal (visible side, facing -z) of the surface above
+/* Central-difference slope (dz/dx, dz/dy) of the map at sample (u, v),
+ * one-sided on the border. */
+static void vertex_slope(const surf *S, int u, int v, double *g) {
+    int W = S->P->W, H = S->P->H;
+    int u0 = u > 0 ? u - 1 : u, u1 = u < W - 1 ? u + 1 : u;
+    int v0 = v > 0 ? v - 1 : v, v1 = v < H - 1 ? v + 1 : v;
+    g[0] = (S->h[(int64_t)v * W + u1] - S->h[(int64_t)v * W + u0]) / ((double)(u1 - u0) * S->px);
+    g[1] = (S->h[(int64_t)v1 * W + u] - S->h[(int64_t)v0 * W + u]) / ((double)(v1 - v0) * S->py);
+}
+
+/* Height of the mesh and the shading normal (visible side, facing -z) above
  * (x, y), clamped to the mesh. */
 static void surface_at(const surf *S, double x, double y, double *p, double *n) {
     int W = S->P->W, H = S->P->H;
@@ -93,23 +113,25 @@ static void surface_at(const surf *S, double x, double y, double *p, double *n) 
     vertex(S, u + 1, v, b);
     vertex(S, u, v + 1, c);
     vertex(S, u + 1, v + 1, d);
-    double z, e1[3], e2[3];
-    if (fx >= fy) {      /* triangle (a, b, d) */
+    double ga[2], gb[2], gc[2], gd[2];
+    vertex_slope(S, u, v, ga);
+    vertex_slope(S, u + 1, v, gb);
+    vertex_slope(S, u, v + 1, gc);
+    vertex_slope(S, u + 1, v + 1, gd);
+    double z, sl[2];
+    if (fx >= fy) {      /* triangle (a, b, d): barycentric weights 1 - fx, fx - fy, fy */
         z = a[2] + fx * (b[2] - a[2]) + fy * (d[2] - b[2]);
-        for (int k = 0; k < 3; ++k) { e1[k] = b[k] - a[k]; e2[k] = d[k] - a[k]; }
-    } else {             /* triangle (a, d, c) */
+        for (int k = 0; k < 2; ++k) sl[k] = (1.0 - fx) * ga[k] + (fx - fy) * gb[k] + fy * gd[k];
+    } else {             /* triangle (a, d, c): barycentric weights 1 - fy, fx, fy - fx */
         z = a[2] + fy * (c[2] - a[2]) + fx * (d[2] - c[2]);
-        for (int k = 0; k < 3; ++k) { e1[k] = d[k] - a[k]; e2[k] = c[k] - a[k]; }
+        for (int k = 0; k < 2; ++k) sl[k] = (1.0 - fy) * ga[k] + fx * gd[k] + (fy - fx) * gc[k];
     }
     p[0] = ((double)u + fx + 0.5) * S->px;
     p[1] = ((double)v + fy + 0.5) * S->py;
     p[2] = z;
-    /* e1 x e2 points up (+z) for both triangles; the visible side is its negative */
-    double nx = e1[1] * e2[2] - e1[2] * e2[1];
-    double ny = e1[2] * e2[0] - e1[0] * e2[2];
-    double nz = e1[0] * e2[1] - e1[1] * e2[0];
-    double l = sqrt(nx * nx + ny * ny + nz * nz);
-    n[0] = -nx / l; n[1] = -ny / l; n[2] = -nz / l;
+    /* the surface z = f(x, y) has upward normal (-fx, -fy, 1); the visible side is its negative */
+    double l = sqrt(sl[0] * sl[0] + sl[1] * sl[1] + 1.0);
+    n[0] = sl[0] / l; n[1] = sl[1] / l; n[2] = -1.0 / l;
 }
 
 /* Ray-triangle intersection (Moller-Trumbore); returns t or -1. */
@@ -148,14 +170,30 @@ static double trace(const surf *S, const double *o, const double *d, double tmin
     return best;
 }
 
-static void albedo(const rt_params *P, const double *tex, const double *p, double *rho) {
-    int i = (int)floor(p[0] / P->Lx * (double)P->tex_w);
-    int j = (int)floor(p[1] / P->Ly * (double)P->tex_h);
+/* Texel coordinate of x along an axis of n texels over length L: the index
+ * i0 of the left centre and the weight f of the right one (clamped). */
+static void texel_axis(double x, double L, int n, int *i0, double *f) {
+    double s = x / L * (double)n - 0.5;
+    if (s < 0.0) s = 0.0;
+    if (s > (double)(n - 1)) s = (double)(n - 1);
+    int i = (int)floor(s);
+    if (i > n - 2) i = n - 2;
     if (i < 0) i = 0;
-    if (j < 0) j = 0;
-    if (i > P->tex_w - 1) i = P->tex_w - 1;
-    if (j > P->tex_h - 1) j = P->tex_h - 1;
-    for (int k = 0; k < 3; ++k) rho[k] = tex[((int64_t)j * P->tex_w + i) * 3 + k];
+    *i0 = i;
+    *f = n > 1 ? s - (double)i : 0.0;
+}
+
+static void albedo(const rt_params *P, const double *tex, const double *p, double *rho) {
+    int i, j;
+    double fx, fy;
+    texel_axis(p[0], P->Lx, P->tex_w, &i, &fx);
+    texel_axis(p[1], P->Ly, P->tex_h, &j, &fy);
+    int i1 = P->tex_w > 1 ? i + 1 : i, j1 = P->tex_h > 1 ? j + 1 : j;
+    for (int k = 0; k < 3; ++k) {
+        double t00 = tex[((int64_t)j * P->tex_w + i) * 3 + k], t10 = tex[((int64_t)j * P->tex_w + i1) * 3 + k];
+        double t01 = tex[((int64_t)j1 * P->tex_w + i) * 3 + k], t11 = tex[((int64_t)j1 * P->tex_w + i1) * 3 + k];
+        rho[k] = (1.0 - fy) * ((1.0 - fx) * t00 + fx * t10) + fy * ((1.0 - fx) * t01 + fx * t11);
+    }
 }
 
 /* Direct light at surface point p (normal n, albedo rho) with the draws
@@ -186,51 +224,65 @@ static void direct(const surf *S, const rt_light *Lt, const double *p, const dou
     }
 }
 
+/* One pixel's mean over its samples (out: 3 doubles). */
+static void render_pixel(const surf *S, const rt_light *lights, const double *tex, int64_t pix, double *out) {
+    const rt_params *P = S->P;
+    int u = (int)(pix % P->out_w), v = (int)(pix / P->out_w);
+    double x = ((double)u + 0.5) * P->Lx / (double)P->out_w;
+    double y = ((double)v + 0.5) * P->Ly / (double)P->out_h;
+    double p[3], n[3], rho[3];
+    surface_at(S, x, y, p, n);
+    albedo(P, tex, p, rho);
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int s = 0; s < P->spp; ++s) {
+        double c[3] = {0.0, 0.0, 0.0};
+        direct(S, lights, p, n, rho, pix, s, 0, c);
+        if (P->bounces > 1) {
+            /* cosine-weighted direction about n (a frame built from n) */
+            double x1 = draw(P, pix, s, 16), x2 = draw(P, pix, s, 17);
+            double r = sqrt(x1), phi = 2.0 * M_PI * x2;
+            double lx = r * cos(phi), ly = r * sin(phi), lz = sqrt(1.0 - x1 > 0.0 ? 1.0 - x1 : 0.0);
+            double t1[3];
+            if (fabs(n[0]) > 0.5) { t1[0] = -n[1]; t1[1] = n[0]; t1[2] = 0.0; }
+            else { t1[0] = 0.0; t1[1] = -n[2]; t1[2] = n[1]; }
+            double tl = sqrt(t1[0] * t1[0] + t1[1] * t1[1] + t1[2] * t1[2]);
+            for (int k = 0; k < 3; ++k) t1[k] /= tl;
+            double t2[3] = {n[1] * t1[2] - n[2] * t1[1], n[2] * t1[0] - n[0] * t1[2], n[0] * t1[1] - n[1] * t1[0]};
+            double d[3];
+            for (int k = 0; k < 3; ++k) d[k] = lx * t1[k] + ly * t2[k] + lz * n[k];
+            double o[3] = {p[0] + 1e-7 * n[0], p[1] + 1e-7 * n[1], p[2] + 1e-7 * n[2]};
+            double t = trace(S, o, d, 0.0, 1e30);
+            if (t > 0.0) {
+                double q[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
+                double p2[3], n2[3], rho2[3];
+                surface_at(S, q[0], q[1], p2, n2);
+                /* only the camera side reflects back */
+                if (n2[0] * d[0] + n2[1] * d[1] + n2[2] * d[2] < 0.0) {
+                    albedo(P, tex, p2, rho2);
+                    double c2[3] = {0.0, 0.0, 0.0};
+                    direct(S, lights, p2, n2, rho2, pix, s, 18, c2);
+                    for (int k = 0; k < 3; ++k) c[k] += rho[k] * c2[k];
+                }
+            }
+        }
+        for (int k = 0; k < 3; ++k) acc[k] += c[k];
+    }
+    for (int k = 0; k < 3; ++k) out[k] = acc[k] / (double)P->spp;
+}
+
 /* Render out (out_h x out_w x 3) from the height map h (H x W, metres). */
 void rt_render_oracle(const rt_params *P, const double *h, const rt_light *lights, const double *tex, double *out) {
     surf S = {P, h, P->Lx / (double)P->W, P->Ly / (double)P->H};
-    for (int v = 0; v < P->out_h; ++v)
-        for (int u = 0; u < P->out_w; ++u) {
-            int64_t pix = (int64_t)v * P->out_w + u;
-            double x = ((double)u + 0.5) * P->Lx / (double)P->out_w;
-            double y = ((double)v + 0.5) * P->Ly / (double)P->out_h;
-            double p[3], n[3], rho[3];
-            surface_at(&S, x, y, p, n);
-            albedo(P, tex, p, rho);
-            double acc[3] = {0.0, 0.0, 0.0};
-            for (int s = 0; s < P->spp; ++s) {
-                double c[3] = {0.0, 0.0, 0.0};
-                direct(&S, lights, p, n, rho, pix, s, 0, c);
-                if (P->bounces > 1) {
-                    /* cosine-weighted direction about n (a frame built from n) */
-                    double x1 = draw(P, pix, s, 16), x2 = draw(P, pix, s, 17);
-                    double r = sqrt(x1), phi = 2.0 * M_PI * x2;
-                    double lx = r * cos(phi), ly = r * sin(phi), lz = sqrt(1.0 - x1 > 0.0 ? 1.0 - x1 : 0.0);
-                    double t1[3];
-                    if (fabs(n[0]) > 0.5) { t1[0] = -n[1]; t1[1] = n[0]; t1[2] = 0.0; }
-                    else { t1[0] = 0.0; t1[1] = -n[2]; t1[2] = n[1]; }
-                    double tl = sqrt(t1[0] * t1[0] + t1[1] * t1[1] + t1[2] * t1[2]);
-                    for (int k = 0; k < 3; ++k) t1[k] /= tl;
-                    double t2[3] = {n[1] * t1[2] - n[2] * t1[1], n[2] * t1[0] - n[0] * t1[2], n[0] * t1[1] - n[1] * t1[0]};
-                    double d[3];
-                    for (int k = 0; k < 3; ++k) d[k] = lx * t1[k] + ly * t2[k] + lz * n[k];
-                    double o[3] = {p[0] + 1e-7 * n[0], p[1] + 1e-7 * n[1], p[2] + 1e-7 * n[2]};
-                    double t = trace(&S, o, d, 0.0, 1e30);
-                    if (t > 0.0) {
-                        double q[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
-                        double p2[3], n2[3], rho2[3];
-                        surface_at(&S, q[0], q[1], p2, n2);
-                        /* only the camera side reflects back */
-                        if (n2[0] * d[0] + n2[1] * d[1] + n2[2] * d[2] < 0.0) {
-                            albedo(P, tex, p2, rho2);
-                            double c2[3] = {0.0, 0.0, 0.0};
-                            direct(&S, lights, p2, n2, rho2, pix, s, 18, c2);
-                            for (int k = 0; k < 3; ++k) c[k] += rho[k] * c2[k];
-                        }
-                    }
-                }
-                for (int k = 0; k < 3; ++k) acc[k] += c[k];
-            }
-            for (int k = 0; k < 3; ++k) out[pix * 3 + k] = acc[k] / (double)P->spp;
-        }
+    int64_t npix = (int64_t)P->out_w * P->out_h;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t pix = 0; pix < npix; ++pix) render_pixel(&S, lights, tex, pix, out + 3 * pix);
+}
+
+/* The pixels pix[0..n) of the same image only (out: n x 3), for images too
+ * large to render whole by brute force. */
+void rt_render_oracle_pixels(const rt_params *P, const double *h, const rt_light *lights, const double *tex,
+                             const int64_t *pix, int64_t n, double *out) {
+    surf S = {P, h, P->Lx / (double)P->W, P->Ly / (double)P->H};
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t q = 0; q < n; ++q) render_pixel(&S, lights, tex, pix[q], out + 3 * q);
 }
