@@ -471,3 +471,68 @@ def surrogate_batch(n, H, W, seed=0):
     prev = rng.normal(0.0, 0.3, (n, H, W, 3)).astype(np.float32)
     tgt = (prev + rng.normal(0.0, 0.05, (n, H, W, 3))).astype(np.float32)
     return depth, pose, prev, tgt
+
+
+# ---------------------------------------------------------------- rendering inputs
+
+# The four LEDs of the Gelsight-style scene (Sec. IV-B: coloured LEDs whose RGB
+# values were fitted to real images; the commented LED table gives green
+# (200, 255, 200), blue (25, 75, 255) and red (255, 50, 75) at energy 2e3 and
+# white (255, 255, 255) at 1e3).  One LED per side of the footprint.
+GELSIGHT_LEDS = (((200, 255, 200), 2.0e3), ((25, 75, 255), 2.0e3), ((255, 50, 75), 2.0e3),
+                 ((255, 255, 255), 1.0e3))
+
+
+def sensor_lights(Lx: float, Ly: float, top: float, colours=GELSIGHT_LEDS, below: float = 3.0e-3,
+                  out: float = 1.0e-3, tilt_deg: float = 30.0, strip: float = 1.0e-3,
+                  radiance: float = 16.0):
+    """Rectangular LED strips along the four sides of an Lx x Ly footprint
+    (order -x, +x, -y, +y), each `out` outside its edge and `below` under the
+    undeformed surface at height `top`, 0.8 of the side long and `strip` wide,
+    emitting toward the footprint's centre line tilted `tilt_deg` up toward the
+    surface.  Radiance: RGB / 255 x energy / 1e3 x `radiance`.  Returns dicts
+    with keys c, e1, e2, L (the renderer's light records)."""
+    s, c = math.sin(math.radians(tilt_deg)), math.cos(math.radians(tilt_deg))
+    sides = [((-out, Ly / 2), (1.0, 0.0), Ly), ((Lx + out, Ly / 2), (-1.0, 0.0), Ly),
+             ((Lx / 2, -out), (0.0, 1.0), Lx), ((Lx / 2, Ly + out), (0.0, -1.0), Lx)]
+    lights = []
+    for ((x, y), (ux, uy), side), (rgb, energy) in zip(sides, colours):
+        n = np.array([ux * c, uy * c, s])               # emitting normal
+        t = np.array([-uy, ux, 0.0])                    # along the side
+        e1 = 0.8 * side * t
+        e2 = strip * np.cross(n, t)                     # e1 x e2 = |e1| |e2| n
+        L = tuple(float(v) / 255.0 * energy / 1e3 * radiance for v in rgb)
+        lights.append(dict(c=(x, y, top - below), e1=tuple(e1), e2=tuple(e2), L=L))
+    return lights
+
+
+def sensor_texture(h: int, w: int, seed: int = 0, markers: int = 12):
+    """Synthetic base image of the coated elastomer (the real no-contact images
+    are absent): a light grey coat with seeded low-frequency mottling and a
+    markers x markers grid of dark dots; h x w x 3 albedos in (0, 1)."""
+    yy, xx = np.meshgrid(np.arange(h) + 0.5, np.arange(w) + 0.5, indexing="ij")
+    base = 0.72 + 0.06 * perlin2(xx / w * 6.0, yy / h * 6.0, seed) + 0.03 * perlin2(xx / w * 23.0, yy / h * 23.0,
+                                                                                      seed + 1)
+    pitch_x, pitch_y = w / markers, h / markers
+    dx = (xx % pitch_x) - pitch_x / 2
+    dy = (yy % pitch_y) - pitch_y / 2
+    dot = np.hypot(dx / pitch_x, dy / pitch_y) < 0.12
+    img = np.repeat(base[:, :, None], 3, axis=2) * np.array([1.0, 0.98, 0.95])
+    img[dot] *= 0.25
+    return np.clip(img, 0.02, 0.98)
+
+
+def dented_heightmap(h: int, w: int, Lx: float, Ly: float, top: float, depth: float = 1.0e-3,
+                     radius: float = 3.0e-3, centre=None, seed: int = 0, roughness: float = 2.0e-6):
+    """A height map of a slab pressed by a sphere: top minus the spherical cap
+    of the given depth and contact radius, plus seeded roughness; row v, column
+    u at the pixel centres ((u+1/2) Lx/w, (v+1/2) Ly/h)."""
+    cx, cy = centre if centre is not None else (Lx / 2, Ly / 2)
+    x = (np.arange(w) + 0.5) * Lx / w
+    y = (np.arange(h) + 0.5) * Ly / h
+    X, Y = np.meshgrid(x, y, indexing="xy")
+    R = (radius * radius + depth * depth) / (2.0 * depth)     # sphere radius of that cap
+    r2 = (X - cx) ** 2 + (Y - cy) ** 2
+    cap = np.where(r2 < radius * radius, np.sqrt(np.maximum(R * R - r2, 0.0)) - (R - depth), 0.0)
+    rng = np.random.default_rng(seed)
+    return top - cap + roughness * rng.standard_normal((h, w))

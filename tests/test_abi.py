@@ -1,5 +1,6 @@
-"""The C ABI library loads and exports every entry point include/impm.h and
-include/sur.h declare (no device calls: runs without a GPU)."""
+"""The C ABI library loads and exports every entry point include/impm.h,
+include/sur.h and include/render.h declare (no device calls: runs without a
+GPU)."""
 import ctypes
 import os
 import re
@@ -9,6 +10,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "impm.h")
 SUR_HEADER = os.path.join(ROOT, "include", "sur.h")
+RENDER_HEADER = os.path.join(ROOT, "include", "render.h")
 
 
 def declared_functions(header=HEADER, prefix="sim"):
@@ -58,3 +60,43 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(impm, "_lib", None)
     with pytest.raises(RuntimeError):
         impm.lib()
+
+
+def test_library_exports_every_renderer_symbol():
+    from paper_2405_02914_amd import impm, render
+    lib = ctypes.CDLL(impm.LIB_PATH)
+    names = declared_functions(RENDER_HEADER, "rt")
+    assert names == ["rt_render", "rt_render_work", "rt_workspace_bytes"]
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(names) <= set(render.EXPORTS)
+    assert ctypes.sizeof(render.rt_light) == 12 * 8
+    assert ctypes.sizeof(render.rt_params) == 4 * 4 + 2 * 8 + 2 * 4 + 8 + 4 * 4
+
+
+def test_renderer_host_validation():
+    """Workspace size and argument checks run on the host before any device
+    call (pointers here are never dereferenced: invalid calls return -1)."""
+    from paper_2405_02914_amd import render as R
+    p = R.rt_params(W=640, H=480, out_w=640, out_h=480, Lx=32e-3, Ly=32e-3, spp=128, bounces=2, seed=1,
+                    n_lights=4, tex_w=64, tex_h=48)
+    tiles = ((640 - 1 + 7) // 8) * ((480 - 1 + 7) // 8)
+    assert R.rt_workspace_bytes(p) == 256 + 8 * tiles
+    bad = [dict(W=1), dict(spp=0), dict(bounces=3), dict(n_lights=5), dict(n_lights=0), dict(Lx=0.0),
+           dict(tex_w=0), dict(out_h=0)]
+    L = R.lib()
+    for kw in bad:
+        q = R.rt_params(**{**{f: getattr(p, f) for f, _ in R.rt_params._fields_}, **kw})
+        assert L.rt_workspace_bytes(ctypes.byref(q)) == 0, kw
+        lights = R.light_records([dict(c=(0, 0, 0), e1=(1, 0, 0), e2=(0, 1, 0), L=(1, 1, 1))] * 4)
+        fake = ctypes.c_void_p(1 << 20)
+        assert L.rt_render(ctypes.byref(q), fake, lights, fake, fake, fake, 1 << 30, None) == -1, kw
+    lights = R.light_records([dict(c=(0, 0, 0), e1=(1, 0, 0), e2=(0, 1, 0), L=(1, 1, 1))] * 4)
+    fake = ctypes.c_void_p(1 << 20)
+    # too small or misaligned workspace, null pointers, a degenerate light
+    assert L.rt_render(ctypes.byref(p), fake, lights, fake, fake, fake, 255, None) == -1
+    assert L.rt_render(ctypes.byref(p), fake, lights, fake, fake, ctypes.c_void_p((1 << 20) + 4), 1 << 30,
+                       None) == -1
+    assert L.rt_render(ctypes.byref(p), None, lights, fake, fake, fake, 1 << 30, None) == -1
+    flat = R.light_records([dict(c=(0, 0, 0), e1=(1, 0, 0), e2=(2, 0, 0), L=(1, 1, 1))] * 4)
+    assert L.rt_render(ctypes.byref(p), fake, flat, fake, fake, fake, 1 << 30, None) == -1
