@@ -23,6 +23,7 @@ wall time.
     python bench.py --workload surrogate   # surrogate training and serving vs IMPM
     python bench.py --workload protocol    # the paper's slip / rotation protocol, IMPM vs normal MPM
     python bench.py --workload object      # object particles against the grid collider, same trajectory
+    python bench.py --workload render      # the tactile image: 640 x 480, 128 samples, path traced
     python bench.py --copy-calibration     # 1 GiB device copy for counter scaling
 
 The batch workload: 64 independent sensors of 32x32x8 to 96x96x24 cells (dx
@@ -63,6 +64,17 @@ PMC_SOURCE_SHA = None
 KERNEL_SOURCES = ("paper_2405_02914_amd/csrc/impm_kernels.hip", "paper_2405_02914_amd/csrc/impm_device.h")
 
 
+# The rendered frame (Sec. III-B, IV-B): a 640 x 480 height-field mesh and
+# image, 128 samples per pixel, 4 LEDs, one interreflection.
+RT_W, RT_H, RT_SPP = 640, 480, 128
+PEAK_FP32_TFLOPS = 157.3
+# FP32 operations per unit of the renderer's work counts, counted from its
+# source: a ray-triangle test up to the hit distance (52), a mesh cell visit
+# (corner positions, height range and ray height tests, exit distances: 24), a
+# tile visit (16), and the set-up and shading of a ray (50).
+RT_FLOPS = {"triangles": 52, "cells": 24, "tiles": 16, "rays": 50}
+
+
 def kernel_source_sha():
     """SHA-256 (first 16 hex digits) of the IMPM kernel sources."""
     import hashlib
@@ -82,7 +94,8 @@ def parse(argv=None):
     ap.add_argument("--cpu-steps", type=int, default=8, help="oracle executed steps timed on all threads")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--tile", default=None, help="tile cells tx,ty,tz[,threads] of the binned order")
-    ap.add_argument("--workload", choices=("sensor", "batch", "surrogate", "protocol", "object"), default="sensor")
+    ap.add_argument("--workload", choices=("sensor", "batch", "surrogate", "protocol", "object", "render"),
+                    default="sensor")
     ap.add_argument("--graph", type=int, default=None, help="1/0: replay step sequences as HIP graphs")
     ap.add_argument("--compact-every", type=int, default=100,
                     help="executed steps between storage compactions of the sensor (0: never)")
@@ -393,7 +406,9 @@ def bench_protocol(args):
     """The paper's slip and rotation protocol on the full-resolution slab with the
     holed-disc indenter: press 0.5 mm, then slide leftward 1-5 mm or rotate
     clockwise 5-45 degrees, IMPM against the plain method; a height map after
-    every increment.  Reports the hole and trace depths of each map."""
+    every increment.  Reports the hole and trace depths of each map, and the
+    segment (0: the press, k: increment k) at which a run was rejected, if
+    any."""
     import torch
     from paper_2405_02914_amd import protocol as P
     torch.cuda.set_device(0)
@@ -428,8 +443,89 @@ def bench_protocol(args):
                    "passes_per_step": {"slip_impm": slip["impm"]["passes_per_step"],
                                        "rotate_impm": rot["impm"]["passes_per_step"]},
                    "limit_hits": {"slip_impm": slip["impm"]["limit_hits"],
-                                  "rotate_impm": rot["impm"]["limit_hits"]}},
+                                  "rotate_impm": rot["impm"]["limit_hits"]},
+                   "failed_segment": {f"{k}_{m}": res[m]["failed_segment"]
+                                      for k, res in (("slip", slip), ("rotate", rot)) for m in ("impm", "normal")}},
     }
+    print(json.dumps(out), flush=True)
+
+
+def render_cpu_baseline(hm, Lx, Ly, lights, tex, n_pix=32):
+    """The renderer oracle (FP64, brute-force ray casting, all host threads)
+    on n_pix pixels of the same frame, scaled to frames/s."""
+    import numpy as np
+    from oracle import render_ref
+    render_ref.build()
+    rng = np.random.default_rng(0)
+    pix = rng.choice(RT_W * RT_H, n_pix, replace=False)
+    h64 = hm.astype(np.float64)
+    t64 = tex.astype(np.float32).astype(np.float64)
+    t0 = time.perf_counter()
+    render_ref.render_pixels(pix, h64, Lx, Ly, lights, t64, RT_W, RT_H, RT_SPP, seed=1, bounces=2)
+    sec = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": n_pix / (RT_W * RT_H) / sec, "unit": "frames/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n_pix} random pixels of the same frame (128 samples each), FP64 brute-force ray casting "
+                      f"over the whole mesh, {threads} OpenMP threads, {sec:.1f} s"}
+
+
+def bench_render(args):
+    """The tactile image (Sec. III-B, IV-B): the full-resolution sensor pressed
+    1.5 mm by the capsule (the trajectory's first 10 frames, IMPM), its surface
+    as a 640 x 480 height map, path traced into a 640 x 480 image with 128
+    samples per pixel, four LEDs and one interreflection.  A step is one
+    rendered frame from the height map resident in HBM."""
+    import numpy as np
+    import torch
+    from paper_2405_02914_amd import impm, render as RD, workloads as W
+    torch.cuda.set_device(0)
+    p = W.config2(subcycle=SUBCYCLE)
+    hm = torch.empty((RT_H, RT_W), device="cuda", dtype=torch.float32)
+    s = impm.Sim(p)
+    for n, pos, q in W.config2_schedule()[:10]:
+        s.sim_set_indenter_pose(pos, q)
+        s.sim_step(n)
+    s.sim_surface_heightmap(RT_W, RT_H, out=hm.view(-1))
+    s.sim_synchronize()
+    s.close()
+    Lx, Ly = p.lengths[0], p.lengths[1]
+    lights = W.sensor_lights(Lx, Ly, p.height)
+    tex = W.sensor_texture(RT_H, RT_W)
+    r = RD.Renderer(lights, tex, Lx, Ly, spp=RT_SPP, bounces=2, seed=1)
+    img, work = r.render_work(hm)
+    for _ in range(args.warmup):
+        r.render(hm, out=img)
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        r.render(hm, out=img)
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    frame_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    flops = sum(RT_FLOPS[k] * work[k] for k in RT_FLOPS)
+    achieved = flops / (frame_ms * 1e-3) / 1e12
+    im = img.cpu().numpy()
+    depth = (p.height - hm.cpu().numpy()) * 1e3
+    out = {
+        "metric": "rendered frames/s", "value": args.steps / wall, "unit": "frames/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "tactile image: 640x480 height map of the 128x128x32-cell sensor pressed 1.5 mm by "
+                               "the capsule, path traced at 640x480, 128 samples/pixel, 4 LEDs, one interreflection",
+                   "paper_s_per_frame": 3.8, "max_depth_mm": round(float(depth.max()), 4),
+                   "image_mean": [round(float(v), 5) for v in im.reshape(-1, 3).mean(0)],
+                   "work_per_frame": work, "rays_per_s": work["rays"] / (frame_ms * 1e-3)},
+        "roofline": {"bound": "alu", "kernel": "k_render<false> (+ k_tile_range, k_block_range, k_range_total)",
+                     "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                     "avg_kernel_ms": round(frame_ms, 4), "alg_flops_per_launch": flops},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = render_cpu_baseline(hm.cpu().numpy(), Lx, Ly, lights, tex)
     print(json.dumps(out), flush=True)
 
 
@@ -455,6 +551,9 @@ def main():
         return
     if args.workload == "object":
         bench_object(args)
+        return
+    if args.workload == "render":
+        bench_render(args)
         return
     import numpy as np
     import torch

@@ -56,8 +56,8 @@ typedef struct {
 } rt_params;
 
 /* Bytes of device workspace rt_render needs for these parameters (the height
- * range of every 8 x 8-cell tile of the mesh and of the whole map), or 0 when
- * the parameters are invalid.  Depends on W and H only. */
+ * range of every 8 x 8-cell tile, every 64 x 64-cell block and the whole map),
+ * or 0 when the parameters are invalid.  Depends on W and H only. */
 uint64_t rt_workspace_bytes(const rt_params* p);
 
 /* Render out_h x out_w x 3 floats (row-major, RGB) into out_device from the
@@ -76,7 +76,8 @@ int rt_render(const rt_params* p, const float* height_device, const rt_light* li
               uint64_t workspace_bytes, void* hip_stream);
 
 /* rt_render, then a wait for it, returning the work it did: work[0] rays
- * traced (shadow and bounce rays), work[1] tiles and work[2] cells of the mesh
+ * traced (shadow and bounce rays), work[1] blocks of the height-range grid
+ * (8 x 8-cell tiles and 64 x 64-cell blocks) and work[2] cells of the mesh
  * the rays visited, work[3] ray-triangle tests.  The same image is written to
  * out_device (the traversal is unchanged; only counting is added).  Used to
  * price a frame's arithmetic; blocks the calling thread until the stream has

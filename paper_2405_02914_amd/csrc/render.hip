@@ -4,15 +4,15 @@
 // estimator, its random numbers and the scene conventions are those stated in
 // include/render.h; the arithmetic is FP32.
 //
-// Three kernels per frame.  k_tile_range writes the height range of every
-// kTile x kTile-cell tile of the mesh and k_range_total the range of the whole
-// map, both into the caller's workspace.  k_render then takes four lanes per
-// pixel (each lane every fourth sample, the lanes' sums combined by
-// cross-lane shuffles) and 64 pixels per block.  A ray walks the tiles it
-// crosses in order; a tile whose height range the ray's height over the tile
-// does not meet is skipped whole, otherwise the ray walks that tile's cells
-// (two triangles per cell, a cell skipped when the same test fails on its
-// four corners).  The first hit found is the nearest: a triangle lies inside
+// Four kernels per frame.  k_tile_range writes the height range of every
+// kTile x kTile-cell tile of the mesh, k_block_range that of every block of
+// kTile x kTile tiles and k_range_total that of the whole map, all into the
+// caller's workspace.  k_render then takes four lanes per pixel (each lane
+// every fourth sample, the lanes' sums combined by cross-lane shuffles) and 64
+// pixels per block.  A ray walks the blocks it crosses in order, the tiles of
+// a block, then the cells of a tile; a block or tile whose height range the
+// ray's height over it does not meet is skipped whole (two triangles per cell,
+// a cell skipped when the same test fails on its four corners).  The first hit found is the nearest: a triangle lies inside
 // its cell's footprint, and the cells are met in order of t.  A ray heading
 // down below the map's lowest point, or up above its highest, stops.
 #include <hip/hip_runtime.h>
@@ -38,12 +38,14 @@ struct LightF {
 struct Args {
     int W, H, out_w, out_h, spp, bounces, n_lights, tex_w, tex_h;
     int TW, TH;                           // tiles per row, per column
+    int BW, BH;                           // blocks (kTile x kTile tiles) per row, per column
     float Lx, Ly, px, py;
     unsigned long long seed;
     LightF lights[4];
     const float* h;
     const float* tex;
     const float2* tiles;                  // TH x TW (min, max)
+    const float2* blocks;                 // BH x BW (min, max)
     const float2* total;                  // (min, max) of the map
     float* out;
 };
@@ -55,6 +57,7 @@ struct Work {
 };
 
 __host__ __device__ inline int tiles_along(int n) { return (n - 1 + kTile - 1) / kTile; }
+__host__ __device__ inline int blocks_along(int n) { return (tiles_along(n) + kTile - 1) / kTile; }
 
 __host__ __device__ __forceinline__ float draw(const Args& a, long long pix, int s, int k) {
     const unsigned long long t =
@@ -213,42 +216,62 @@ __host__ __device__ float walk_cells(const Args& a, const Ray& r, float ta, floa
     return -1.0f;
 }
 
+// Nearest hit in (0, tmax) among the cells [ulo, uhi] x [vlo, vhi] that the
+// ray crosses over [ta, tb], walking the blocks of level LEVEL of the height-
+// range grid in order (1: kTile-cell tiles, 2: kTile^2-cell blocks) and
+// skipping those whose height range the ray's height over them misses.  The
+// windows passed down are aligned to the blocks below.  At the top level the
+// ray also stops once it is below the map's lowest point heading down, or
+// above its highest heading up.
+template <int LEVEL, bool COUNT>
+__host__ __device__ float walk_blocks(const Args& a, const Ray& r, float ta, float tb, float tmax, int ulo, int uhi,
+                                      int vlo, int vhi, float zmin, float zmax, float mz, Work& w) {
+    constexpr int S = LEVEL == 1 ? kTile : kTile * kTile;    // cells per block side
+    const float2* ranges = LEVEL == 1 ? a.tiles : a.blocks;
+    const int per_row = LEVEL == 1 ? a.TW : a.BW;
+    const int blo = ulo / S, bhi = uhi / S, clo = vlo / S, chi = vhi / S;
+    int bu = min(max((int)floorf((r.gx + ta * r.dgx) / (float)S), blo), bhi);
+    int bv = min(max((int)floorf((r.gy + ta * r.dgy) / (float)S), clo), chi);
+    float t0 = ta;
+    for (int guard = 0; guard < (bhi - blo) + (chi - clo) + 2; ++guard) {
+        if constexpr (LEVEL == 2) {
+            const float z0 = r.o[2] + t0 * r.d[2];
+            if ((r.d[2] < 0.0f && z0 < zmin - mz) || (r.d[2] > 0.0f && z0 > zmax + mz)) return -1.0f;
+        }
+        const int cu0 = max(bu * S, ulo), cu1 = min(bu * S + S - 1, uhi);
+        const int cv0 = max(bv * S, vlo), cv1 = min(bv * S + S - 1, vhi);
+        const float tx = cross_x(r, r.su > 0 ? cu1 + 1 : cu0), ty = cross_y(r, r.sv > 0 ? cv1 + 1 : cv0);
+        const float t1 = fminf(fminf(tx, ty), tb);
+        if constexpr (COUNT) ++w.tiles;
+        const float2 rg = ranges[bv * per_row + bu];
+        if (meets(r, t0, t1, rg.x, rg.y, mz)) {
+            float t;
+            if constexpr (LEVEL == 1)
+                t = walk_cells<COUNT>(a, r, t0, t1, tmax, cu0, cu1, cv0, cv1, mz, w);
+            else
+                t = walk_blocks<LEVEL - 1, COUNT>(a, r, t0, t1, tmax, cu0, cu1, cv0, cv1, zmin, zmax, mz, w);
+            if (t > 0.0f) return t;
+        }
+        if (t1 >= tb) break;
+        if (tx < ty) {
+            bu += r.su;
+            if (bu < blo || bu > bhi) break;
+        } else {
+            bv += r.sv;
+            if (bv < clo || bv > chi) break;
+        }
+        t0 = t1;
+    }
+    return -1.0f;
+}
+
 // Nearest hit in (0, tmax) of the ray o + t d with the mesh, or -1.
 template <bool COUNT>
 __host__ __device__ float trace(const Args& a, const float o[3], const float d[3], float tmax, float zmin, float zmax,
                                 float mz, Work& w) {
     if constexpr (COUNT) ++w.rays;
     const Ray r = make_ray(a, o, d);
-    const int cw = a.W - 1, ch = a.H - 1;   // cells per row, per column
-    int ti = min(max((int)floorf(r.gx / (float)kTile), 0), a.TW - 1);
-    int tj = min(max((int)floorf(r.gy / (float)kTile), 0), a.TH - 1);
-    float ta = 0.0f;
-    for (int guard = 0; guard < a.TW + a.TH + 2; ++guard) {
-        if (ta > tmax) return -1.0f;
-        const float za = r.o[2] + ta * r.d[2];
-        if ((r.d[2] < 0.0f && za < zmin - mz) || (r.d[2] > 0.0f && za > zmax + mz)) return -1.0f;
-        const int ulo = ti * kTile, uhi = min(ulo + kTile, cw) - 1;
-        const int vlo = tj * kTile, vhi = min(vlo + kTile, ch) - 1;
-        const float tx = cross_x(r, r.su > 0 ? uhi + 1 : ulo), ty = cross_y(r, r.sv > 0 ? vhi + 1 : vlo);
-        const float tb = fminf(fminf(tx, ty), tmax);
-        if constexpr (COUNT) ++w.tiles;
-        const float2 rg = a.tiles[tj * a.TW + ti];
-        if (meets(r, ta, tb, rg.x, rg.y, mz)) {
-            const float t = walk_cells<COUNT>(a, r, ta, tb, tmax, ulo, uhi, vlo, vhi, mz, w);
-            if (t > 0.0f) return t;
-        }
-        if (tx >= FLT_MAX && ty >= FLT_MAX) return -1.0f;   // a vertical ray meets one tile only
-        if (tx < ty) {
-            ti += r.su;
-            if (ti < 0 || ti >= a.TW) return -1.0f;
-            ta = tx;
-        } else {
-            tj += r.sv;
-            if (tj < 0 || tj >= a.TH) return -1.0f;
-            ta = ty;
-        }
-    }
-    return -1.0f;
+    return walk_blocks<2, COUNT>(a, r, 0.0f, tmax, tmax, 0, a.W - 2, 0, a.H - 2, zmin, zmax, mz, w);
 }
 
 // Texel coordinate of x along an axis of n texels over length L: the index
@@ -313,12 +336,28 @@ __global__ __launch_bounds__(256) void k_tile_range(const float* __restrict__ h,
     tiles[q] = make_float2(lo, hi);
 }
 
-__global__ __launch_bounds__(256) void k_range_total(const float2* __restrict__ tiles, int n,
+// Height range of every block of kTile x kTile tiles, from the tiles' ranges.
+__global__ __launch_bounds__(256) void k_block_range(const float2* __restrict__ tiles, int TW, int TH, int BW, int BH,
+                                                     float2* __restrict__ blocks) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= BW * BH) return;
+    const int bi = q % BW, bj = q / BW;
+    float lo = FLT_MAX, hi = -FLT_MAX;
+    for (int tj = bj * kTile; tj < min(bj * kTile + kTile, TH); ++tj)
+        for (int ti = bi * kTile; ti < min(bi * kTile + kTile, TW); ++ti) {
+            const float2 r = tiles[tj * TW + ti];
+            lo = fminf(lo, r.x);
+            hi = fmaxf(hi, r.y);
+        }
+    blocks[q] = make_float2(lo, hi);
+}
+
+__global__ __launch_bounds__(256) void k_range_total(const float2* __restrict__ ranges, int n,
                                                      float2* __restrict__ total) {
     __shared__ float2 part[4];
     float lo = FLT_MAX, hi = -FLT_MAX;
     for (int q = threadIdx.x; q < n; q += blockDim.x) {
-        const float2 r = tiles[q];
+        const float2 r = ranges[q];
         lo = fminf(lo, r.x);
         hi = fmaxf(hi, r.y);
     }
@@ -430,6 +469,8 @@ static bool pack_args(const rt_params* p, const rt_light* lights, Args& a) {
     a.tex_w = p->tex_w; a.tex_h = p->tex_h;
     a.TW = tiles_along(p->W);
     a.TH = tiles_along(p->H);
+    a.BW = blocks_along(p->W);
+    a.BH = blocks_along(p->H);
     a.Lx = (float)p->Lx; a.Ly = (float)p->Ly;
     a.px = (float)(p->Lx / p->W); a.py = (float)(p->Ly / p->H);
     a.seed = p->seed;
@@ -456,22 +497,26 @@ static int launch(const rt_params* p, const float* height, const float* texture,
     char* ws = static_cast<char*>(workspace);
     float2* total = reinterpret_cast<float2*>(ws);
     float2* tiles = reinterpret_cast<float2*>(ws + 256);
+    float2* blocks = tiles + (size_t)a.TW * a.TH;
     a.h = height;
     a.tex = texture;
     a.tiles = tiles;
+    a.blocks = blocks;
     a.total = total;
     a.out = out;
     const hipStream_t st = (hipStream_t)stream;
-    const int nt = a.TW * a.TH;
+    const int nt = a.TW * a.TH, nb = a.BW * a.BH;
     hipLaunchKernelGGL(k_tile_range, dim3((nt + 255) / 256), dim3(256), 0, st, height, a.W, a.H, a.TW, a.TH, tiles);
-    hipLaunchKernelGGL(k_range_total, dim3(1), dim3(256), 0, st, tiles, nt, total);
+    hipLaunchKernelGGL(k_block_range, dim3((nb + 255) / 256), dim3(256), 0, st, tiles, a.TW, a.TH, a.BW, a.BH,
+                       blocks);
+    hipLaunchKernelGGL(k_range_total, dim3(1), dim3(256), 0, st, blocks, nb, total);
     const long long npix = (long long)p->out_w * p->out_h;
-    const unsigned blocks = (unsigned)((npix + kPixels - 1) / kPixels);
+    const unsigned grid = (unsigned)((npix + kPixels - 1) / kPixels);
     if (counts) {
         hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(64), 0, st, counts);
-        hipLaunchKernelGGL(k_render<true>, dim3(blocks), dim3(kThreads), 0, st, a, counts);
+        hipLaunchKernelGGL(k_render<true>, dim3(grid), dim3(kThreads), 0, st, a, counts);
     } else {
-        hipLaunchKernelGGL(k_render<false>, dim3(blocks), dim3(kThreads), 0, st, a, counts);
+        hipLaunchKernelGGL(k_render<false>, dim3(grid), dim3(kThreads), 0, st, a, counts);
     }
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
@@ -481,7 +526,8 @@ static int launch(const rt_params* p, const float* height, const float* texture,
 extern "C" uint64_t rt_workspace_bytes(const rt_params* p) {
     if (!rt::valid(p)) return 0;
     const uint64_t tiles = (uint64_t)rt::tiles_along(p->W) * (uint64_t)rt::tiles_along(p->H);
-    return 256 + tiles * sizeof(float2);
+    const uint64_t blocks = (uint64_t)rt::blocks_along(p->W) * (uint64_t)rt::blocks_along(p->H);
+    return 256 + (tiles + blocks) * sizeof(float2);
 }
 
 extern "C" int rt_render(const rt_params* p, const float* height_device, const rt_light* lights,

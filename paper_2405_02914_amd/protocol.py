@@ -24,25 +24,34 @@ from . import impm, workloads as W
 def run(params, segs, hm: int = 256):
     """Step a sensor through `segs`, taking a hm x hm height map (mm of depth
     below the undeformed top, positive into the slab) after every segment.
-    Returns (maps [k, hm, hm], poses [(pos, quat)], stats, seconds)."""
+    A segment whose state the library rejects (SIM_ENUMERIC: the sticking
+    contact has sheared the slab past what the elastomer model can carry) ends
+    the run.  Returns (maps [k, hm, hm] of the completed segments, their poses
+    [(pos, quat)], stats, seconds, the failed segment's index or None)."""
     import torch
     s = impm.Sim(params)
     try:
-        maps, poses = [], []
+        maps, poses, failed = [], [], None
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         out = torch.empty(hm * hm, device="cuda", dtype=torch.float32)
-        for n, pos, q in segs:
+        for k, (n, pos, q) in enumerate(segs):
             s.sim_set_indenter_pose(pos, q)
             s.sim_step(n)
             s.sim_surface_heightmap(hm, hm, out=out)
+            try:
+                s.sim_synchronize()
+            except impm.SimError as e:
+                if e.code != impm.SIM_ENUMERIC:
+                    raise
+                failed = k
+                break
             maps.append(out.clone())
             poses.append((pos, q))
-        s.sim_synchronize()
         torch.cuda.synchronize()
         secs = time.perf_counter() - t0
         depth = [(params.height - m.cpu().numpy().reshape(hm, hm)) * 1e3 for m in maps]
-        return np.stack(depth), poses, s.sim_get_stats(), secs
+        return np.stack(depth) if depth else np.zeros((0, hm, hm)), poses, s.sim_get_stats(check=False), secs, failed
     finally:
         s.close()
 
@@ -84,9 +93,9 @@ def protocol(kind: str, sign: float = -1.0, dx: float = 0.25e-3, cells=(128, 128
     for name, mode in (("impm", W.MODE_IMPM), ("normal", W.MODE_PLAIN)):
         p = W.protocol_sensor(dx=dx, cells=cells, r_out=r_out, r_hole=r_hole, mode=mode)
         segs = W.protocol_schedule(p.pose0, kind, sign=sign, **sched_kw)
-        maps, poses, st, secs = run(p, segs, hm)
+        maps, poses, st, secs, failed = run(p, segs, hm)
         rows = [hole_metrics(p, d, pz[0], r_out, r_hole, start=p.pose0[:3]) for d, pz in zip(maps, poses)]
         res[name] = {"metrics": rows, "passes_per_step": st["passes"] / max(st["steps"], 1),
-                     "limit_hits": st["limit_hits"], "steps": st["steps"],
+                     "limit_hits": st["limit_hits"], "steps": st["steps"], "failed_segment": failed,
                      "particle_updates_per_s": p.n_particles * st["steps"] / secs, "seconds": secs}
     return res

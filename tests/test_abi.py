@@ -80,8 +80,9 @@ def test_renderer_host_validation():
     from paper_2405_02914_amd import render as R
     p = R.rt_params(W=640, H=480, out_w=640, out_h=480, Lx=32e-3, Ly=32e-3, spp=128, bounces=2, seed=1,
                     n_lights=4, tex_w=64, tex_h=48)
-    tiles = ((640 - 1 + 7) // 8) * ((480 - 1 + 7) // 8)
-    assert R.rt_workspace_bytes(p) == 256 + 8 * tiles
+    tw, th = (640 - 1 + 7) // 8, (480 - 1 + 7) // 8
+    blocks = ((tw + 7) // 8) * ((th + 7) // 8)
+    assert R.rt_workspace_bytes(p) == 256 + 8 * (tw * th + blocks)
     bad = [dict(W=1), dict(spp=0), dict(bounces=3), dict(n_lights=5), dict(n_lights=0), dict(Lx=0.0),
            dict(tex_w=0), dict(out_h=0)]
     L = R.lib()

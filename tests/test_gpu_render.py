@@ -72,6 +72,29 @@ def test_render_matches_oracle(gpu, oracle, bounces, shape):
     check(img, ref, spp, f"{w}x{h} -> {ow}x{oh}, {bounces} bounce(s)")
 
 
+@pytest.mark.parametrize("shape", [(200, 150, 100, 75), (257, 131, 257, 131)])
+def test_multi_block_maps_sampled_pixels(gpu, oracle, shape):
+    """Maps of several 64 x 64-cell blocks of the height-range grid, ragged at
+    both ends, with an off-centre dent: 48 pixels computed one by one."""
+    import torch
+    w, h, ow, oh = shape
+    Lx, Ly, top = 16e-3, 12e-3, 3e-3
+    hm = W.dented_heightmap(h, w, Lx, Ly, top, depth=1.0e-3, radius=3e-3, centre=(6e-3, 7e-3), seed=w,
+                            roughness=1e-6).astype(np.float32)
+    lights = W.sensor_lights(Lx, Ly, top)
+    tex = W.sensor_texture(48, 64, seed=w)
+    r = gpu.Renderer(lights, tex, Lx, Ly, spp=4, bounces=2, seed=11)
+    img = r.render(torch.from_numpy(hm).cuda(), oh, ow).cpu().numpy().reshape(-1, 3)
+    pix = np.random.default_rng(1).choice(ow * oh, 48, replace=False)
+    ref = oracle.render_pixels(pix, hm.astype(np.float64), Lx, Ly, lights, tex.astype(np.float32).astype(np.float64),
+                               ow, oh, 4, seed=11, bounces=2)
+    err = np.abs(img[pix] - ref).max(axis=-1)
+    scale = ref.max()
+    print(f"[render] {w}x{h} -> {ow}x{oh}: sampled max |diff| {err.max() / scale:.2e} of the max", flush=True)
+    assert int((err <= 1e-4 * scale).sum()) >= len(pix) - 1
+    assert err.max() <= 2.0 / 4 * scale
+
+
 def test_render_flat_surface_and_degenerate_sizes(gpu, oracle):
     """A flat map (every ray below the map's range at once), the smallest map
     (2 x 2: one cell, one tile) and a one-pixel image."""
