@@ -56,11 +56,12 @@ ALG_BYTES_PER_PARTICLE_PASS = 192.0 + 7.0
 # rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) scaled by
 # the counters' reading of a copy of known size (fetched bytes = 2.0 x
 # FETCH_SIZE, written = 1.0 x WRITE_SIZE), with the default storage compaction
-# every 100 executed steps.  PMC_SOURCE_SHA is the SHA-256 (first 16 hex digits)
+# every 100 executed steps (first 200 executed steps of the trajectory).
+# PMC_SOURCE_SHA is the SHA-256 (first 16 hex digits)
 # of the kernel sources the counters were read on; the figure is reported only
 # while the sources still hash to it.
-PMC_TRAFFIC_BYTES = (2.0 * 152514 + 305138) * 1024
-PMC_SOURCE_SHA = None
+PMC_TRAFFIC_BYTES = (2.0 * 147895.19 + 300085.81) * 1024
+PMC_SOURCE_SHA = "ed306f692f38ee7c"
 KERNEL_SOURCES = ("paper_2405_02914_amd/csrc/impm_kernels.hip", "paper_2405_02914_amd/csrc/impm_device.h")
 
 
