@@ -7,9 +7,14 @@
 // Four kernels per frame.  k_tile_range writes the height range of every
 // kTile x kTile-cell tile of the mesh, k_block_range that of every block of
 // kTile x kTile tiles and k_range_total that of the whole map, all into the
-// caller's workspace.  k_render then takes four lanes per pixel (each lane
-// every fourth sample, the lanes' sums combined by cross-lane shuffles) and 64
-// pixels per block.  A ray walks the blocks it crosses in order, the tiles of
+// caller's workspace.  k_render then takes one wave per pixel (lane l takes
+// samples l, l + 64, ..., the lanes' sums combined by cross-lane shuffles) and
+// four pixels per block: all lanes of a wave start their rays at the same
+// surface point, so their walks stay close (measured on a 640 x 480 map with a
+// 1.4 mm dent, 128 samples: 24 ms per frame, against 31 ms with 4 lanes per
+// pixel and 16 pixels per wave), and the register budget is held to 4 waves
+// per SIMD (128 VGPRs; 36 ms at the 141 the compiler takes unbounded, 3 waves
+// per SIMD).  A ray walks the blocks it crosses in order, the tiles of
 // a block, then the cells of a tile; a block or tile whose height range the
 // ray's height over it does not meet is skipped whole (two triangles per cell,
 // a cell skipped when the same test fails on its four corners).  The first hit found is the nearest: a triangle lies inside
@@ -25,8 +30,8 @@
 namespace rt {
 
 constexpr int kTile = 8;                  // cells per tile side
-constexpr int kLanes = 4;                 // lanes per pixel
-constexpr int kPixels = 64;               // pixels per block
+constexpr int kLanes = 64;                // lanes per pixel: one pixel per wave
+constexpr int kPixels = 4;                // pixels per block
 constexpr int kThreads = kLanes * kPixels;
 constexpr float kRayOffset = 1e-7f;       // m, off the surface along n
 
@@ -428,7 +433,8 @@ __host__ __device__ inline float range_slack(const Args& a, float zmin, float zm
 
 // One image; the COUNT instantiation also adds its work counts to counts[4].
 template <bool COUNT>
-__global__ __launch_bounds__(kThreads) void k_render(Args a, unsigned long long* counts) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_render(
+    Args a, unsigned long long* counts) {
     const float2 tot = *a.total;
     const float zmin = tot.x, zmax = tot.y;
     const float mz = range_slack(a, zmin, zmax);

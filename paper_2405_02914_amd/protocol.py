@@ -85,13 +85,16 @@ def hole_metrics(params, depth_mm, pos, r_out, r_hole, fillet=0.75e-3, hole_fill
 
 
 def protocol(kind: str, sign: float = -1.0, dx: float = 0.25e-3, cells=(128, 128, 32), hm: int = 256,
-             r_out: float = 4.0e-3, r_hole: float = 1.5e-3, **sched_kw):
+             r_out: float = 4.0e-3, r_hole: float = 1.5e-3, object_density: float = None, **sched_kw):
     """Both methods through one protocol ("slip" or "rotate"; sign -1: leftward
-    or clockwise).  Returns a dict with the per-increment metrics of each
-    method, its stats and its particle-updates per second."""
+    or clockwise), the object a grid collider, or object particles of the given
+    density (kg/m^3) when object_density is set.  Returns a dict with the
+    per-increment metrics of each method, its stats and its particle-updates
+    per second."""
     res = {}
+    extra = {} if object_density is None else dict(object_mode=W.OBJECT_PARTICLES, object_density=object_density)
     for name, mode in (("impm", W.MODE_IMPM), ("normal", W.MODE_PLAIN)):
-        p = W.protocol_sensor(dx=dx, cells=cells, r_out=r_out, r_hole=r_hole, mode=mode)
+        p = W.protocol_sensor(dx=dx, cells=cells, r_out=r_out, r_hole=r_hole, mode=mode, **extra)
         segs = W.protocol_schedule(p.pose0, kind, sign=sign, **sched_kw)
         maps, poses, st, secs, failed = run(p, segs, hm)
         rows = [hole_metrics(p, d, pz[0], r_out, r_hole, start=p.pose0[:3]) for d, pz in zip(maps, poses)]

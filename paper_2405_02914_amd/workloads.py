@@ -18,6 +18,7 @@ import numpy as np
 
 SHAPE_NONE, SHAPE_SPHERE, SHAPE_CAPSULE, SHAPE_BOX, SHAPE_HEIGHTFIELD = 0, 1, 2, 3, 4
 MODE_IMPM, MODE_PLAIN = 0, 1
+OBJECT_COLLIDER, OBJECT_PARTICLES = 0, 1
 
 
 @dataclasses.dataclass

@@ -52,15 +52,19 @@ def test_hole_metrics_on_a_synthetic_map():
 @pytest.mark.skipif(not gpu_available(), reason="needs a HIP device")
 @pytest.mark.parametrize("kind", ["slip", "rotate"])
 @pytest.mark.parametrize("mode", [W.MODE_IMPM, W.MODE_PLAIN])
-def test_small_protocol_matches_oracle(oracle_lib, kind, mode):
+@pytest.mark.parametrize("obj", ["collider", "particles"])
+def test_small_protocol_matches_oracle(oracle_lib, kind, mode, obj):
     """The protocol on a 16 x 16 x 6-cell slab (dx 0.5 mm): press 0.5 mm, two
-    increments of 0.5 mm slip or 10 degrees; the device replays the oracle's
-    pass schedule; every height map within 1e-3 dx."""
+    increments of 0.5 mm slip or 10 degrees, the object a grid collider or
+    object particles as dense as the elastomer; the device replays the
+    oracle's pass schedule; every height map within 1e-3 dx."""
     from paper_2405_02914_amd import impm
-    p = W.protocol_sensor(dx=0.5e-3, cells=(16, 16, 6), r_out=2.5e-3, r_hole=1.0e-3, mode=mode, subcycle=2)
+    extra = {} if obj == "collider" else dict(object_mode=W.OBJECT_PARTICLES, object_density=1000.0)
+    p = W.protocol_sensor(dx=0.5e-3, cells=(16, 16, 6), r_out=2.5e-3, r_hole=1.0e-3, mode=mode, subcycle=2,
+                          **extra)
     segs = W.protocol_schedule(p.pose0, kind, sign=-1.0, n_press=40, increments=2, step_mm=0.5,
                                step_deg=10.0, n_per_increment=40, n_per_degree_step=40)
-    print(f"[protocol] {kind} mode {mode}: {p.n_particles} particles", flush=True)
+    print(f"[protocol] {kind} mode {mode} {obj}: {p.n_particles} particles", flush=True)
     o = oracle_lib.OracleSim(p)
     o.enable_pass_log(100000)
     ho = []
