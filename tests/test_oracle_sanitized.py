@@ -1,0 +1,71 @@
+"""The FP64 oracles built with AddressSanitizer and UndefinedBehaviorSanitizer
+(gcc), driven through the same ctypes bindings over short runs of every mode:
+the cuboid with a collider, object particles, a shaped elastomer (two
+threads), the height and displacement maps, and the renderer's whole-image
+and per-pixel entries.  Any out-of-bounds access, use after free or undefined
+operation aborts the run."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+FLAGS = ["-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer",
+         "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared"]
+
+DRIVER = r'''
+import sys
+sys.path.insert(0, ROOT)
+import numpy as np
+from oracle import impm_ref, render_ref
+impm_ref.build = lambda force=False: IMPM_LIB
+render_ref.build = lambda force=False: RENDER_LIB
+from paper_2405_02914_amd import workloads as W
+p = W.small_sensor(cells=(10, 9, 4), subcycle=2)
+cols = W.dome_columns((10, 9, 4), p.dx, 2.5e-3, 2)
+for kw in (dict(), dict(object_mode=1, object_density=1000.0, object_cap=1e-3),
+           dict(columns=cols, shape=W.SHAPE_NONE)):
+    q = p.replace(**kw)
+    o = impm_ref.OracleSim(q)
+    o.set_threads(2)
+    c = np.array(q.pose0[:3])
+    o.set_target_pose(tuple(c + [0, 0, -0.2e-3]), (1, 0, 0, 0))
+    o.step(6)
+    o.set_target_pose(tuple(c + [0.1e-3, 0, -0.2e-3]), W.quat_about_z(5))
+    o.step(6)
+    o.surface_heightmap(12, 10)
+    o.surface_displacement(12, 10)
+    o.close()
+hm = W.dented_heightmap(20, 24, 8e-3, 6e-3, 3e-3, depth=0.5e-3, radius=1.5e-3)
+L = W.sensor_lights(8e-3, 6e-3, 3e-3)
+render_ref.render(hm, 8e-3, 6e-3, L, W.sensor_texture(6, 8), 12, 10, 4, seed=3, bounces=2)
+render_ref.render_pixels([0, 5, 119], hm, 8e-3, 6e-3, L, W.sensor_texture(6, 8), 12, 10, 4, seed=3, bounces=2)
+print("sanitized oracles: ok")
+'''
+
+
+def _runtime(name):
+    r = subprocess.run(["gcc", f"-print-file-name={name}"], capture_output=True, text=True)
+    path = r.stdout.strip()
+    return path if r.returncode == 0 and os.path.isabs(path) and os.path.exists(path) else None
+
+
+def test_oracles_clean_under_asan_and_ubsan(tmp_path):
+    asan, ubsan = _runtime("libasan.so"), _runtime("libubsan.so")
+    if not asan or not ubsan:
+        pytest.skip("gcc's sanitizer runtimes are not installed")
+    libs = {}
+    for name, src in (("impm", "impm_oracle.c"), ("render", "render_oracle.c")):
+        out = str(tmp_path / f"lib{name}_san.so")
+        subprocess.check_call(["gcc", *FLAGS, "-o", out, os.path.join(ROOT, "oracle", src), "-lm"])
+        libs[name] = out
+    script = tmp_path / "drive.py"
+    script.write_text(f"ROOT = {ROOT!r}\nIMPM_LIB = {libs['impm']!r}\nRENDER_LIB = {libs['render']!r}\n" + DRIVER)
+    env = dict(os.environ, LD_PRELOAD=f"{asan}:{ubsan}", ASAN_OPTIONS="detect_leaks=0",
+               UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1", OMP_NUM_THREADS="2")
+    r = subprocess.run([sys.executable, str(script)], capture_output=True, text=True, env=env, timeout=600)
+    log = r.stdout + r.stderr
+    assert r.returncode == 0, log[-3000:]
+    assert "sanitized oracles: ok" in r.stdout
+    assert "runtime error" not in log and "AddressSanitizer" not in log, log[-3000:]
