@@ -168,7 +168,7 @@ def bench_batch(args):
     tiles, tuned = [], {}
     for p in params:
         if p.cells not in tuned:
-            t, ms = impm.sim_autotune_tile(p, steps=8)
+            t, ms = impm.sim_autotune_tile(p, steps=32)
             tuned[p.cells] = (t, ms)
         tiles.append(tuned[p.cells][0])
     graph = True if args.graph is None else bool(args.graph)

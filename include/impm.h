@@ -304,8 +304,9 @@ int sim_batch_depthmaps(sim_batch_t* b, float* out, int32_t W, int32_t H, double
 const char* sim_batch_last_error(const sim_batch_t* b);
 
 /* Time `steps` executed steps of a sensor with these parameters for every
- * compiled tile shape and return the fastest (tx, ty, tz, threads) and its
- * time per executed step in ms. */
+ * compiled tile shape, in three interleaved rounds, and return the shape whose
+ * fastest round is fastest (tx, ty, tz, threads) with that round's time per
+ * executed step in ms. */
 int sim_autotune_tile(const sim_params* p, int32_t steps, void* hip_stream, int32_t out[4], double* out_ms);
 
 #ifdef __cplusplus

@@ -83,6 +83,8 @@ def test_small_protocol_matches_oracle(oracle_lib, kind, mode, obj):
               f"{(p.height - ho[k].min()) * 1e3:.3f} mm", flush=True)
         assert err <= 1e-3 * p.dx
     assert g.sim_get_stats()["passes"] == o.counters()["passes"]
-    assert (p.height - ho[0].min()) > 0.3e-3            # the press shows in the map
+    # the press shows in the map (object particles as dense as the slab are
+    # pushed back by it, so their press is shallower)
+    assert (p.height - ho[0].min()) > (0.3e-3 if obj == "collider" else 0.1e-3)
     xg, xo = g.sim_read_particles()[0], o.state()[0]
     assert np.abs(xg - xo).max() <= 1e-3 * p.dx
