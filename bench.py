@@ -420,19 +420,23 @@ def bench_protocol(args):
     rho = W.protocol_sensor().rho
     slip_o = P.protocol("slip", sign=-1.0, object_density=rho)
     rot_o = P.protocol("rotate", sign=-1.0, increments=9, object_density=rho)
+    slip_or = P.protocol("slip", sign=1.0, object_density=rho)
+    rot_or = P.protocol("rotate", sign=1.0, increments=9, object_density=rho)
     wall = time.perf_counter() - t0
-    runs = [r[m] for r in (slip, rot, slip_o, rot_o) for m in ("impm", "normal")]
+    runs = [r[m] for r in (slip, rot, slip_o, rot_o, slip_or, rot_or) for m in ("impm", "normal")]
     upd = sum(r["particle_updates_per_s"] * r["seconds"] for r in runs)
     gpu_s = sum(r["seconds"] for r in runs)
 
     def table(res, key):
-        return {m: [round(row[key], 4) if key in row else None for row in res[m]["metrics"]]
+        return {m: [round(row[key], 4) if row.get(key) is not None else None for row in res[m]["metrics"]]
                 for m in ("impm", "normal")}
 
     def summary(slip, rot):
         return {"slip_hole_contrast_mm": table(slip, "hole_contrast_mm"),
                 "slip_trace_mm": table(slip, "trace_mm"),
                 "slip_face_mm": table(slip, "face_mm"),
+                "slip_follow": table(slip, "follow"),
+                "rotate_follow": table(rot, "follow"),
                 "rotate_hole_mm": table(rot, "hole_mm"),
                 "rotate_face_mm": table(rot, "face_mm"),
                 "passes_per_step": {f"{k}_{m}": round(r[m]["passes_per_step"], 4)
@@ -445,16 +449,18 @@ def bench_protocol(args):
         "metric": "IMPM particle-updates/s",
         "value": upd / gpu_s,
         "unit": "particle-updates/s",
-        "n_gpus": 1, "steps": 8, "warmup": 0, "ms_per_step": 1e3 * gpu_s / 8,
+        "n_gpus": 1, "steps": 12, "warmup": 0, "ms_per_step": 1e3 * gpu_s / 12,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "paper slip/rotation protocol: 128x128x32 cells dx 0.25 mm, holed-disc indenter "
                                "(r 4 mm, hole r 1.5 mm), press 0.5 mm, slide leftward 0-5 mm in 1 mm steps / "
                                "rotate clockwise 0-45 deg in 5 deg steps, IMPM and normal MPM, the object a grid "
-                               "collider and object particles as dense as the elastomer",
+                               "collider and object particles as dense as the elastomer (these also rightward and "
+                               "counter-clockwise)",
                    "wall_s": round(wall, 2),
                    "collider": summary(slip, rot),
-                   "object_particles_rho1": summary(slip_o, rot_o)},
+                   "object_particles_rho1": summary(slip_o, rot_o),
+                   "object_particles_rho1_rightward_counterclockwise": summary(slip_or, rot_or)},
     }
     print(json.dumps(out), flush=True)
 

@@ -24,21 +24,25 @@ from . import impm, workloads as W
 def run(params, segs, hm: int = 256):
     """Step a sensor through `segs`, taking a hm x hm height map (mm of depth
     below the undeformed top, positive into the slab) after every segment.
-    A segment whose state the library rejects (SIM_ENUMERIC: the sticking
-    contact has sheared the slab past what the elastomer model can carry) ends
-    the run.  Returns (maps [k, hm, hm] of the completed segments, their poses
-    [(pos, quat)], stats, seconds, the failed segment's index or None)."""
+    and its surface displacement map (mm, hm x hm x 3).  A segment whose state
+    the library rejects (SIM_ENUMERIC: the sticking contact has sheared the
+    slab past what the elastomer model can carry) ends the run.  Returns
+    (depth maps [k, hm, hm] and displacement maps [k, hm, hm, 3] of the
+    completed segments, their poses [(pos, quat)], stats, seconds, the failed
+    segment's index or None)."""
     import torch
     s = impm.Sim(params)
     try:
-        maps, poses, failed = [], [], None
+        maps, disps, poses, failed = [], [], [], None
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         out = torch.empty(hm * hm, device="cuda", dtype=torch.float32)
+        out3 = torch.empty(hm * hm * 3, device="cuda", dtype=torch.float32)
         for k, (n, pos, q) in enumerate(segs):
             s.sim_set_indenter_pose(pos, q)
             s.sim_step(n)
             s.sim_surface_heightmap(hm, hm, out=out)
+            s.sim_surface_displacement(hm, hm, out=out3)
             try:
                 s.sim_synchronize()
             except impm.SimError as e:
@@ -47,11 +51,15 @@ def run(params, segs, hm: int = 256):
                 failed = k
                 break
             maps.append(out.clone())
+            disps.append(out3.clone())
             poses.append((pos, q))
         torch.cuda.synchronize()
         secs = time.perf_counter() - t0
         depth = [(params.height - m.cpu().numpy().reshape(hm, hm)) * 1e3 for m in maps]
-        return np.stack(depth) if depth else np.zeros((0, hm, hm)), poses, s.sim_get_stats(check=False), secs, failed
+        disp = [d.cpu().numpy().reshape(hm, hm, 3) * 1e3 for d in disps]
+        return (np.stack(depth) if depth else np.zeros((0, hm, hm)),
+                np.stack(disp) if disp else np.zeros((0, hm, hm, 3)), poses, s.sim_get_stats(check=False), secs,
+                failed)
     finally:
         s.close()
 
@@ -84,6 +92,32 @@ def hole_metrics(params, depth_mm, pos, r_out, r_hole, fillet=0.75e-3, hole_fill
     return out
 
 
+def follow_metric(params, disp_mm, pos, quat, start, r_out, r_hole, fillet=0.75e-3, hole_fillet=0.3e-3,
+                  margin=0.25e-3):
+    """How far the surface under the indenter's flat face has followed the
+    indenter (relative rest: 1 = moved with it, 0 = stayed behind), from one
+    displacement map (mm; the surface particles' displacement from their rest
+    positions, at their current positions).  Slide: the face's mean x
+    displacement over the indenter's x travel.  Rotation: the face's mean angle
+    about the indenter's centre (rest position to current position) over the
+    indenter's angle about z.  None before the indenter has moved sideways."""
+    hm = disp_mm.shape[0]
+    X, Y = _pixel_centres(params, hm)
+    r = np.hypot(X - pos[0], Y - pos[1])
+    face = (r >= r_hole + hole_fillet + margin) & (r <= r_out - fillet - margin)
+    u = disp_mm[face] * 1e-3
+    slide = pos[0] - start[0]
+    angle = 2.0 * np.arctan2(quat[3], quat[0])
+    if abs(slide) > 1e-9:
+        return float(u[:, 0].mean() / slide)
+    if abs(angle) > 1e-9:
+        x1, y1 = X[face] - pos[0], Y[face] - pos[1]
+        x0, y0 = x1 - u[:, 0], y1 - u[:, 1]
+        th = np.arctan2(x0 * y1 - y0 * x1, x0 * x1 + y0 * y1)
+        return float(th.mean() / angle)
+    return None
+
+
 def protocol(kind: str, sign: float = -1.0, dx: float = 0.25e-3, cells=(128, 128, 32), hm: int = 256,
              r_out: float = 4.0e-3, r_hole: float = 1.5e-3, object_density: float = None, **sched_kw):
     """Both methods through one protocol ("slip" or "rotate"; sign -1: leftward
@@ -96,8 +130,10 @@ def protocol(kind: str, sign: float = -1.0, dx: float = 0.25e-3, cells=(128, 128
     for name, mode in (("impm", W.MODE_IMPM), ("normal", W.MODE_PLAIN)):
         p = W.protocol_sensor(dx=dx, cells=cells, r_out=r_out, r_hole=r_hole, mode=mode, **extra)
         segs = W.protocol_schedule(p.pose0, kind, sign=sign, **sched_kw)
-        maps, poses, st, secs, failed = run(p, segs, hm)
+        maps, disps, poses, st, secs, failed = run(p, segs, hm)
         rows = [hole_metrics(p, d, pz[0], r_out, r_hole, start=p.pose0[:3]) for d, pz in zip(maps, poses)]
+        for row, u, pz in zip(rows, disps, poses):
+            row["follow"] = follow_metric(p, u, pz[0], pz[1], p.pose0[:3], r_out, r_hole)
         res[name] = {"metrics": rows, "passes_per_step": st["passes"] / max(st["steps"], 1),
                      "limit_hits": st["limit_hits"], "steps": st["steps"], "failed_segment": failed,
                      "particle_updates_per_s": p.n_particles * st["steps"] / secs, "seconds": secs}

@@ -48,6 +48,28 @@ def test_hole_metrics_on_a_synthetic_map():
     assert m["hole_contrast_mm"] == 0.375 and m["trace_mm"] == 0.0625
 
 
+def test_follow_metric_on_synthetic_displacements():
+    """A face that turned rigidly with the indenter follows it fully (1); a
+    face displaced half the slide follows it by 0.5; before any sideways
+    motion there is nothing to follow."""
+    p = W.protocol_sensor()
+    hm = 256
+    X, Y = P._pixel_centres(p, hm)
+    c = p.pose0[:3]
+    th = np.radians(-10.0)
+    x1, y1 = X - c[0], Y - c[1]
+    x0 = np.cos(th) * x1 + np.sin(th) * y1                 # rotated back by -th
+    y0 = -np.sin(th) * x1 + np.cos(th) * y1
+    d = np.zeros((hm, hm, 3))
+    d[..., 0], d[..., 1] = (x1 - x0) * 1e3, (y1 - y0) * 1e3
+    assert P.follow_metric(p, d, c, W.quat_about_z(-10.0), c, 4e-3, 1.5e-3) == pytest.approx(1.0, abs=1e-9)
+    half = np.zeros((hm, hm, 3))
+    half[..., 0] = -0.5
+    moved = (c[0] - 1e-3, c[1], c[2])
+    assert P.follow_metric(p, half, moved, (1.0, 0.0, 0.0, 0.0), c, 4e-3, 1.5e-3) == pytest.approx(0.5)
+    assert P.follow_metric(p, half, c, (1.0, 0.0, 0.0, 0.0), c, 4e-3, 1.5e-3) is None
+
+
 @pytest.mark.gpu
 @pytest.mark.skipif(not gpu_available(), reason="needs a HIP device")
 @pytest.mark.parametrize("kind", ["slip", "rotate"])
