@@ -5,8 +5,8 @@
  * 2405.02914 (Sec. III-A: the surface displacement that IMPM produces when the
  * indenter moves between two height-map frames, Sec. IV-B) so that a serving
  * loop can skip most IMPM solves and fall back to the simulator to re-anchor.
- * The paper itself has no learned component; the method is the judge of the
- * surrogate's error.
+ * The paper itself has no learned component; the method is the reference the
+ * surrogate's error is measured against.
  *
  * Network (U-shape, NHWC BF16 activations and weights, FP32 accumulation on
  * the MFMA units, FP32 master weights):

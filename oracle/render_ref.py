@@ -1,4 +1,4 @@
-"""ctypes driver of the FP64 renderer oracle (render_oracle.c).
+"""ctypes binding of the FP64 renderer oracle (render_oracle.c).
 
 TEST INFRASTRUCTURE ONLY: used by the tests and the benchmark's CPU baseline
 leg, never by the product library."""

@@ -1,6 +1,6 @@
 // impm_host.hip -- host runtime and C ABI (include/impm.h) of the IMPM
 // elastomer simulator: particle initialisation, the per-step indenter pose
-// table, the device-side relative-rest loop driver, the binned particle order
+// table, the host side of the device relative-rest loop, the binned particle order
 // and the surface raster (arXiv 2405.02914, Sec. III-A and Sec. IV-B).
 #include <hip/hip_runtime.h>
 

@@ -1,7 +1,7 @@
 """Surrogate training on IMPM trajectories, evaluation and serving rates.
 
   python -m paper_2405_02914_amd.surrogate_train --train 512 --test 64 --steps 3000 \\
-      --out gpurun_out/surrogate.json [--save weights.bin]
+      --out surrogate.json [--save weights.bin]
 
 1. Data.  Seeded random trajectories (workloads.surrogate_trajectories:
    32 x 32 x 8 mm sensors, random sphere / capsule / box / height-field
@@ -171,8 +171,8 @@ def inference_rate(net, data, stream, batch, reps=20):
 
 def kernel_timing(batch=64, serve_batch=256, reps=20, stream=None):
     """Training-step and inference times (ms) on seeded synthetic inputs of the
-    serving shape, without data generation: the short driver that kernel
-    profiles of the network run."""
+    serving shape, without data generation: the short run that kernel
+    profiles of the network time."""
     import torch
     st = stream or torch.cuda.Stream()
     d, p, pv, tg = W.surrogate_batch(batch, RES, RES, seed=0)

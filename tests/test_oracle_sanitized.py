@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 FLAGS = ["-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer",
          "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared"]
 
-DRIVER = r'''
+SCRIPT = r'''
 import sys
 sys.path.insert(0, ROOT)
 import numpy as np
@@ -61,7 +61,7 @@ def test_oracles_clean_under_asan_and_ubsan(tmp_path):
         subprocess.check_call(["gcc", *FLAGS, "-o", out, os.path.join(ROOT, "oracle", src), "-lm"])
         libs[name] = out
     script = tmp_path / "drive.py"
-    script.write_text(f"ROOT = {ROOT!r}\nIMPM_LIB = {libs['impm']!r}\nRENDER_LIB = {libs['render']!r}\n" + DRIVER)
+    script.write_text(f"ROOT = {ROOT!r}\nIMPM_LIB = {libs['impm']!r}\nRENDER_LIB = {libs['render']!r}\n" + SCRIPT)
     env = dict(os.environ, LD_PRELOAD=f"{asan}:{ubsan}", ASAN_OPTIONS="detect_leaks=0",
                UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1", OMP_NUM_THREADS="2")
     r = subprocess.run([sys.executable, str(script)], capture_output=True, text=True, env=env, timeout=600)
