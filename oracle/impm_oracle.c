@@ -999,12 +999,19 @@ double orc_min_margin(const orc_sim *s) { return s->min_margin; }
 
 /* Place the indenter at a pose (current and target) without stepping: a test
  * hook that lets a state taken elsewhere continue from its pose. */
+/* Set the indenter's pose (and target) without stepping; object particles,
+ * which move rigidly with the object, are placed at the new pose. */
 void orc_set_pose(orc_sim *s, const double *pos, const double *quat) {
     memcpy(s->pos, pos, 3 * sizeof(double));
     memcpy(s->quat, quat, 4 * sizeof(double));
     quat_normalize(s->quat);
     memcpy(s->tpos, s->pos, sizeof(s->pos));
     memcpy(s->tquat, s->quat, sizeof(s->quat));
+    if (s->n_obj > 0) {
+        step_pose sp;
+        make_step_pose(s, 0, 1, s->P.dt, &sp);
+        place_object(s, &sp);
+    }
 }
 
 void orc_get_pose(const orc_sim *s, double *pose7) {

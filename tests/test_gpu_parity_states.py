@@ -237,3 +237,57 @@ def test_config2_full_size_first_slip_substep(gpu, ref):
     if not forced:
         assert abs(st["last_r"] - oc["last_r"]) <= 1e-5 * oc["last_r"]
     compare_states(g, o, x, "config2 substep 500", dx=p.dx)
+
+
+@pytest.mark.parametrize("case", ["config2_objects_rho100", "protocol_objects_rho1"])
+def test_full_size_object_particles_substep(gpu, ref, case):
+    """Object particles at full size (4,194,304 elastomer particles) in the
+    benchmarks' launch configuration: config 2 with object particles 100 times
+    denser than the elastomer, pressed 1.5 mm over substeps 0-499 then its first
+    slip substep; the protocol's holed disc as object particles as dense as the
+    elastomer, pressed 0.5 mm then its first slide substep (where the loop runs
+    several passes).  The device's state goes to the oracle (the object
+    particles placed at the same pose) and both run the substep, the device
+    deciding its passes itself unless r came within 1e-4 of the threshold."""
+    if case == "config2_objects_rho100":
+        base = W.config2(subcycle=4)
+        p = base.replace(object_mode=W.OBJECT_PARTICLES, object_density=100.0 * base.rho)
+        segs = W.config2_schedule()
+        pre, nxt = segs[:10], segs[10]
+        x0 = p.pose0[0]
+        tgt = ((nxt[1][0] - x0) / nxt[0] + x0, nxt[1][1], nxt[1][2]), W.quat_about_z(30.0 / 1500)
+    else:
+        p = W.protocol_sensor(object_mode=W.OBJECT_PARTICLES, object_density=1000.0)
+        segs = W.protocol_schedule(p.pose0, "slip", sign=-1.0)
+        pre, nxt = segs[:1], segs[1]
+        c = np.array(pre[0][1])
+        tgt = tuple(c + (np.array(nxt[1]) - c) / nxt[0]), nxt[2]
+    g = gpu.Sim(p)
+    g.sim_set_compaction(100)
+    g.run_schedule(pre)
+    g.sim_synchronize()
+    st0 = g.sim_get_stats()
+    x, v, Cm, G = g.sim_read_particles()
+    o = ref.OracleSim(p)
+    o.set_state(x=x, v=v, Cm=Cm, F=np.eye(3)[None] + G.astype(np.float64))
+    pose = st0["pose"]
+    o.set_pose(pose[:3], pose[3:])
+    o.enable_pass_log(100)
+    o.set_target_pose(*tgt)
+    print(f"[parity] {case}: substep {st0['substeps']} on the oracle ({o.n} particles, "
+          f"{len(o.objects()[0])} object particles)", flush=True)
+    o.step(1)
+    sched = o.pass_log()
+    margin = o.min_margin()
+    forced = margin < MARGIN
+    if forced:
+        g.sim_debug_force_passes(sched)
+    g.sim_set_indenter_pose(*tgt)
+    g.sim_step(1)
+    st, oc = g.sim_get_stats(), o.counters()
+    print(f"[parity] {case}: oracle passes {sched.tolist()} r {oc['last_r']:.6f} margin {margin:.2e}; "
+          f"device passes {st['passes'] - st0['passes']} r {st['last_r']:.6f}", flush=True)
+    assert st["passes"] - st0["passes"] == int(sched.sum())
+    if not forced:
+        assert abs(st["last_r"] - oc["last_r"]) <= 1e-5 * oc["last_r"]
+    compare_states(g, o, x, f"{case} substep", dx=p.dx)
