@@ -259,9 +259,10 @@ def test_full_size_object_particles_substep(gpu, ref, case):
     else:
         p = W.protocol_sensor(object_mode=W.OBJECT_PARTICLES, object_density=1000.0)
         segs = W.protocol_schedule(p.pose0, "slip", sign=-1.0)
-        pre, nxt = segs[:1], segs[1]
-        c = np.array(pre[0][1])
-        tgt = tuple(c + (np.array(nxt[1]) - c) / nxt[0]), nxt[2]
+        c = np.array(segs[0][1])
+        step = (np.array(segs[1][1]) - c) / segs[1][0]           # one substep of the first slide
+        pre = [segs[0], (100, tuple(c + 100 * step), segs[1][2])]
+        tgt = tuple(c + 101 * step), segs[1][2]
     g = gpu.Sim(p)
     g.sim_set_compaction(100)
     g.run_schedule(pre)
