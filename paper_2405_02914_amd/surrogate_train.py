@@ -106,24 +106,44 @@ def generate(params, scheds, stream, batch=64, log=print):
     return d
 
 
-def train(net, data, steps, batch, stream, lr=1e-3, seed=0, log=print, log_every=250):
-    """Adam on random transitions; cosine learning-rate decay to lr / 20."""
+def train(net, data, steps, batch, stream, lr=1e-3, seed=0, log=print, log_every=250, rollout=0,
+          rollout_from=0.25):
+    """Adam on random transitions; cosine learning-rate decay to lr / 20.
+
+    rollout = R > 0 (pushforward training): after the first `rollout_from` of
+    the steps, the previous displacement of each minibatch is the network's own
+    prediction r frames on from the IMPM frame k - 1 - r, with r drawn from
+    0..R per step (no gradient through those predictions), so that training
+    sees the inputs a served roll-out feeds the network."""
     import torch
-    g = torch.Generator(device="cuda")
+    dev = data.depth.device
+    g = torch.Generator(device=dev)
     g.manual_seed(seed)
+    gc = torch.Generator()
+    gc.manual_seed(seed + 1)
     losses = []
     t0 = time.perf_counter()
     with torch.cuda.stream(stream):
         for it in range(steps):
             net.sur_set_lr(lr * (0.05 + 0.95 * 0.5 * (1 + math.cos(math.pi * it / max(1, steps)))))
-            t = torch.randint(0, data.T, (batch,), device="cuda", generator=g)
-            k = torch.randint(1, data.F + 1, (batch,), device="cuda", generator=g)
+            t = torch.randint(0, data.T, (batch,), device=dev, generator=g)
+            k = torch.randint(1, data.F + 1, (batch,), device=dev, generator=g)
+            r = 0
+            if rollout and it >= rollout_from * steps:
+                r = min(int(torch.randint(0, rollout + 1, (1,), generator=gc)), data.F - 1)
+                k = torch.clamp(k, min=r + 1)
+            prev = data.disp[t, k - 1 - r].contiguous()
+            for j in range(r):
+                kk = k - r + j
+                prev = net.sur_infer(data.depth[t, kk].contiguous(), data.pose6[t, kk].contiguous(), prev)
             want = (it % log_every == 0) or it == steps - 1
-            loss = net.sur_train_step(*data.transitions(t, k), want_loss=want)
+            loss = net.sur_train_step(data.depth[t, k].contiguous(), data.pose6[t, k].contiguous(), prev,
+                                      data.disp[t, k].contiguous(), want_loss=want)
             if want:
                 losses.append((it, loss))
                 log(f"[train] step {it} loss {loss:.4e} ({time.perf_counter() - t0:.1f} s)", flush=True)
-    stream.synchronize()
+    if stream is not None:
+        stream.synchronize()
     return losses, time.perf_counter() - t0
 
 
@@ -207,6 +227,8 @@ def main():
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--serve-batch", type=int, default=256)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--rollout", type=int, default=0,
+                    help="pushforward training: feed up to this many of the network's own predictions")
     ap.add_argument("--out", default=None)
     ap.add_argument("--save", default=None)
     ap.add_argument("--timing-only", action="store_true",
@@ -224,14 +246,14 @@ def main():
     dte = generate(pte, ste, st)
     gen_s = time.perf_counter() - t0
     net = sur.Surrogate(RES, RES, max_batch=max(a.batch, a.serve_batch), lr=a.lr, stream=st.cuda_stream)
-    losses, train_s = train(net, dtr, a.steps, a.batch, st, lr=a.lr)
+    losses, train_s = train(net, dtr, a.steps, a.batch, st, lr=a.lr, rollout=a.rollout)
     ev = evaluate(net, dte, st)
     ev_train = evaluate(net, dtr, st)
     fps, lat = inference_rate(net, dte, st, a.serve_batch)
     res = {"train_trajectories": dtr.T, "test_trajectories": dte.T,
            "dropped_trajectories": len(dtr.dropped) + len(dte.dropped), "frames_per_trajectory": dtr.F,
            "sensor_particles": dtr.particles, "data_generation_s": gen_s, "train_steps": a.steps,
-           "batch": a.batch, "train_s": train_s, "train_ms_per_step": 1e3 * train_s / a.steps,
+           "batch": a.batch, "rollout": a.rollout, "train_s": train_s, "train_ms_per_step": 1e3 * train_s / a.steps,
            "losses": losses, "test": ev, "train_set": ev_train,
            "surrogate_frames_per_s": fps, "surrogate_batch_latency_ms": 1e3 * lat, "serve_batch": a.serve_batch,
            "impm_frames_per_s": dtr.impm_frames_per_s, "speedup_vs_impm": fps / dtr.impm_frames_per_s}
