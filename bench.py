@@ -102,6 +102,10 @@ def parse(argv=None):
     ap.add_argument("--graph", type=int, default=None, help="1/0: replay step sequences as HIP graphs")
     ap.add_argument("--compact-every", type=int, default=100,
                     help="executed steps between storage compactions of the sensor (0: never)")
+    ap.add_argument("--sur-train", type=int, default=1024, help="surrogate workload: training trajectories")
+    ap.add_argument("--sur-steps", type=int, default=6000, help="surrogate workload: Adam steps timed")
+    ap.add_argument("--sur-rollout", type=int, default=4,
+                    help="surrogate workload: pushforward depth (the network's own predictions fed back)")
     return ap.parse_args(argv)
 
 
@@ -245,32 +249,44 @@ def surrogate_flops(H=128, W=128, channels=(32, 64, 128, 256), in_ch=10):
 
 
 def bench_surrogate(args):
-    """Surrogate on IMPM data: a compact run of the whole pipeline (IMPM
-    trajectories from the batched simulator, Adam training with the BF16 MFMA
-    kernels, held-out RMS error, serving rate)."""
+    """Surrogate on IMPM data: the whole pipeline (IMPM trajectories from the
+    batched simulator, Adam training with pushforward on the BF16 MFMA kernels,
+    held-out RMS error, inference rate, and serving with IMPM fallback under
+    three re-solve policies against plain IMPM of the same trajectories)."""
+    import math
     import torch
     from paper_2405_02914_amd import sur, surrogate_train as T, workloads as W
     torch.cuda.set_device(0)
     st = torch.cuda.Stream()
-    n_train, n_test, steps, batch, serve = 96, 16, max(args.steps, 200), 64, 256
+    n_train, n_test, steps, batch, serve = args.sur_train, 64, args.sur_steps, 64, 256
+    err = lambda *a, **k: print(*a, file=sys.stderr, **k)
     ptr, s_tr = W.surrogate_trajectories(n_train, seed=1)
     pte, s_te = W.surrogate_trajectories(n_test, seed=2)
-    dtr = T.generate(ptr, s_tr, st, log=lambda *a, **k: print(*a, file=sys.stderr, **k))
-    dte = T.generate(pte, s_te, st, log=lambda *a, **k: print(*a, file=sys.stderr, **k))
+    dtr = T.generate(ptr, s_tr, st, log=err)
+    dte = T.generate(pte, s_te, st, log=err)
     net = sur.Surrogate(T.RES, T.RES, max_batch=serve, stream=st.cuda_stream)
     T.train(net, dtr, args.warmup, batch, st, log=lambda *a, **k: None)          # warm-up steps
-    losses, secs = T.train(net, dtr, steps, batch, st, log=lambda *a, **k: print(*a, file=sys.stderr, **k))
+    losses, secs = T.train(net, dtr, steps, batch, st, log=err, log_every=1000, rollout=args.sur_rollout)
     ev = T.evaluate(net, dte, st)
     fps, lat = T.inference_rate(net, dte, st, serve, reps=20)
-    # serving with IMPM fallback: held-out sensors against plain IMPM of the same trajectories
+    impm_fps, n_tr, n_te = dtr.impm_frames_per_s, dtr.T, dte.T
+    del dtr
+    torch.cuda.empty_cache()
+    # serving with IMPM fallback: 16 held-out sensors of 40 frames against plain IMPM of the same trajectories
     from paper_2405_02914_amd import serving
     sp, ss = W.surrogate_trajectories(16, seed=31, n_substeps=50 * 40)
-    srv = serving.Server(sp, ss, net, st, record=True)
-    served = srv.run()
     ref = T.generate(sp, ss, st, log=lambda *a, **k: None)
-    served["served_rms_mm"] = float(((srv.record[:, 1:] - ref.disp[:, 1:]) ** 2).mean().sqrt())
-    served["plain_impm_frames_per_s"] = ref.impm_frames_per_s
-    srv.close()
+    served = {}
+    for name, every, tol in (("every_20th_and_contact_area_10pct", 20, 0.10), ("every_20th_only", 20, math.inf),
+                             ("no_resolve", len(ss[0]) + 1, math.inf)):
+        srv = serving.Server(sp, ss, net, st, resolve_every=every, area_tol=tol, record=True)
+        r = srv.run()
+        r["served_rms_mm"] = float(((srv.record[:, 1:] - ref.disp[:, 1:]) ** 2).mean().sqrt())
+        r["plain_impm_frames_per_s"] = ref.impm_frames_per_s
+        r["speedup_vs_plain_impm"] = r["frames_per_s"] / ref.impm_frames_per_s
+        served[name] = r
+        srv.close()
+        err(f"[serve] {name}: {r['served_rms_mm']:.4f} mm, {r['speedup_vs_plain_impm']:.1f}x plain IMPM")
     mp, ms = serving.sensor_mix(8, 40)
     srv = serving.Server(mp, ms, net, st)
     mixed = srv.run()
@@ -278,10 +294,13 @@ def bench_surrogate(args):
     fwd, trn = surrogate_flops()
     step_ms = 1e3 * secs / steps
     achieved = trn * batch / (step_ms * 1e-3) / 1e12
+    # the headline: the fastest serving policy whose frames stay within the 0.02 mm gate
+    ok = [k for k, r in served.items() if r["served_rms_mm"] <= 0.02]
+    best = max(ok, key=lambda k: served[k]["frames_per_s"]) if ok else None
     out = {
-        "metric": "surrogate vs IMPM frames/s",
-        "value": fps,
-        "unit": "frames/s",
+        "metric": "surrogate served sensor-frames/s at <=0.02 mm RMS vs IMPM",
+        "value": served[best]["frames_per_s"] if best else None,
+        "unit": "sensor-frames/s",
         "n_gpus": 1, "steps": steps, "warmup": args.warmup,
         "ms_per_step": step_ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -289,14 +308,18 @@ def bench_surrogate(args):
         "config": {"workload": "U-shaped conv surrogate 32-64-128-256 on 128x128 maps, trained on IMPM "
                                "trajectories of 32x32x8 mm sensors (64x64x16 cells, dx 0.5 mm) with random "
                                "indenters; serving batch 256",
-                   "train_trajectories": dtr.T, "test_trajectories": dte.T, "train_batch": batch,
-                   "serve_batch": serve, "impm_frames_per_s": dtr.impm_frames_per_s,
-                   "speedup_vs_impm": fps / dtr.impm_frames_per_s,
+                   "served_policy": best,
+                   "served_vs_plain_impm": served[best]["speedup_vs_plain_impm"] if best else None,
+                   "train_trajectories": n_tr, "test_trajectories": n_te, "train_batch": batch,
+                   "train_steps": steps, "pushforward_rollout": args.sur_rollout,
+                   "serve_batch": serve, "impm_frames_per_s": impm_fps,
+                   "inference_frames_per_s": fps, "inference_vs_impm": fps / impm_fps,
                    "rms_one_step_mm": ev["rms_one_step_mm"], "rms_rollout_mm": ev["rms_rollout_mm"],
                    "rms_persistence_mm": ev["rms_persistence_mm"],
                    "train_gflop_per_sample": trn / 1e9, "infer_gflop_per_sample": fwd / 1e9,
                    "serve_batch_ms": 1e3 * lat,
-                   "serving_64cells": served, "serving_mixed_64_96_128": mixed},
+                   "serving_16_heldout_64cells_40frames": served,
+                   "serving_mixed_64_96_128_policy_20th_and_area": mixed},
         "roofline": {"bound": "mfma", "kernel": "whole training step (all kernels, wall clock)",
                      "achieved": round(achieved, 1), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "traffic": None,
