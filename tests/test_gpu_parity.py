@@ -188,6 +188,37 @@ def test_slip_and_rotation_with_oracle_pass_schedule(gpu, ref):
     assert np.abs(x2 - xo).max() <= 1e-2 * p.dx
 
 
+def test_tilted_start_orientation_matches_oracle(gpu, ref):
+    """A capsule whose start orientation is turned 40 deg about its own axis
+    (the same solid), pressed and then turned about the world z axis: the step's
+    rotation q1 q0^-1 and its angular velocity are taken in the world frame on
+    both sides, so the positions agree on the oracle's pass schedule."""
+    p = W.small_sensor(cells=(12, 12, 5), radius=1.2e-3, subcycle=2)
+    t = np.radians(40.0)
+    q0 = (float(np.cos(t / 2)), float(np.sin(t / 2)), 0.0, 0.0)
+    p = p.replace(half_length=1.5e-3, pose0=(*p.pose0[:3], *q0))
+    c = np.array(p.pose0[:3])
+    w1, x1, y1, z1 = W.quat_about_z(15)
+    w2, x2, y2, z2 = q0
+    q1 = (w1 * w2 - x1 * x2 - y1 * y2 - z1 * z2, w1 * x2 + x1 * w2 + y1 * z2 - z1 * y2,
+          w1 * y2 - x1 * z2 + y1 * w2 + z1 * x2, w1 * z2 + x1 * y2 - y1 * x2 + z1 * w2)
+    segs = [(10, tuple(c + [0, 0, -0.3e-3]), q0), (20, tuple(c + [0.1e-3, 0, -0.3e-3]), q1)]
+    o = ref.OracleSim(p)
+    o.enable_pass_log(10000)
+    o.run_schedule(segs)
+    g = gpu.Sim(p)
+    g.sim_debug_force_passes(o.pass_log())
+    g.run_schedule(segs)
+    xg = g.sim_read_particles()[0]
+    xo = o.state()[0]
+    X0 = o.rest()[0]
+    err = np.abs(xg - xo).max()
+    print(f"tilted start: max|dx| = {err / p.dx:.3e} dx, max displacement {np.abs(xo - X0).max() / p.dx:.2f} dx",
+          flush=True)
+    assert np.abs(xo - X0).max() > 0.2 * p.dx
+    assert err <= 1e-3 * p.dx
+
+
 def test_heightfield_indenter_matches_oracle(gpu, ref):
     """A textured (Perlin height-field) indenter pressed, slipped and rotated:
     same calibration points and, on the oracle's pass schedule, the same

@@ -373,6 +373,39 @@ def test_energy_does_not_grow(ref):
         assert all(b <= a * (1 + 1e-9) for a, b in zip(e, e[1:])), e
 
 
+def test_energy_is_the_stress_potential(ref):
+    """The energy the stability test watches is the one whose derivative is the
+    stress the method uses: for a slab at rest with one uniform F, the central
+    difference of the total energy in F_ab equals n V_p P_ab, with the first
+    Piola stress P = tau F^-T from the Kirchhoff stress; and with v = 0 and
+    F = I it is zero, with F = I and a uniform v it is the kinetic energy."""
+    p = W.small_sensor(cells=(3, 3, 2), shape=W.SHAPE_NONE)
+    s = ref.OracleSim(p)
+    n = s.n
+    Vp = p.dx ** 3 / p.ppc
+    mp = p.rho * Vp
+    mu, lam = p.E / (2 * (1 + p.nu)), p.E * p.nu / ((1 + p.nu) * (1 - 2 * p.nu))
+    s.set_state(v=np.zeros((n, 3)), F=np.tile(np.eye(3), (n, 1, 1)))
+    assert s.energy() == 0.0
+    s.set_state(v=np.tile([0.3, -0.2, 0.1], (n, 1)))
+    assert np.isclose(s.energy(), 0.5 * n * mp * 0.14, rtol=1e-14)
+    s.set_state(v=np.zeros((n, 3)))
+    rng = np.random.default_rng(8)
+    F0 = np.eye(3) + 0.08 * rng.normal(size=(3, 3))
+    Pk = ref.kirchhoff(F0, mu, lam) @ np.linalg.inv(F0).T
+    eps = 1e-6
+    for a in range(3):
+        for b in range(3):
+            E = []
+            for sgn in (1, -1):
+                F = F0.copy()
+                F[a, b] += sgn * eps
+                s.set_state(F=np.tile(F, (n, 1, 1)))
+                E.append(s.energy())
+            dE = (E[0] - E[1]) / (2 * eps)
+            assert np.isclose(dE, n * Vp * Pk[a, b], rtol=1e-6, atol=1e-9 * p.E * n * Vp), (a, b)
+
+
 def test_stability_limit_bites_without_subcycling(ref):
     """The same slab at the configured dt without sub-cycling (CFL 1.35) fails,
     which is why the sub-cycle factor exists."""
@@ -533,18 +566,20 @@ def test_displacement_uniform_shift_reproduced(ref):
 
 
 def test_displacement_brute_force_pixels(ref):
-    """Surface displacement at pixel centres by brute force over surface particles."""
+    """Surface displacement at pixel centres by brute force over surface
+    particles; the pixel pitches differ along x and y (0.5 dx and 5/7 dx)."""
     p = W.small_sensor(cells=(6, 5, 3), shape=W.SHAPE_NONE)
     s = ref.OracleSim(p)
     X, _, surf = s.rest()
     rng = np.random.default_rng(4)
     x = X + rng.normal(0, 0.1 * p.dx, X.shape)
     s.set_state(x=x)
-    Wd, Hd = 12, 10
+    Wd, Hd = 12, 7
     got = s.surface_displacement(Wd, Hd)
     px, py = p.lengths[0] / Wd, p.lengths[1] / Hd
+    assert abs(px - py) > 0.1 * p.dx
     xs, Xs = x[surf], X[surf]
-    for (v, u) in [(0, 0), (3, 7), (9, 11), (5, 5)]:
+    for (v, u) in [(0, 0), (3, 7), (6, 11), (5, 5), (2, 1)]:
         cx, cy = (u + 0.5) * px, (v + 0.5) * py
         w = brute.N((xs[:, 0] - cx) / px) * brute.N((xs[:, 1] - cy) / py)
         want = (w[:, None] * (xs - Xs)).sum(0) / w.sum()
@@ -590,16 +625,37 @@ def test_rotation_sense_of_sticking_contact(ref):
     assert d[right, 1].mean() > 1e-5 and d[left, 1].mean() < -1e-5
 
 
-def test_contact_velocity_is_the_rigid_motion(ref):
+def _quat_matrix(q):
+    w, x, y, z = q
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+def _quat_mul(a, b):
+    w1, x1, y1, z1 = a
+    w2, x2, y2, z2 = b
+    return np.array([w1 * w2 - x1 * x2 - y1 * y2 - z1 * z2, w1 * x2 + x1 * w2 + y1 * z2 - z1 * y2,
+                     w1 * y2 - x1 * z2 + y1 * w2 + z1 * x2, w1 * z2 + x1 * y2 - y1 * x2 + z1 * w2])
+
+
+@pytest.mark.parametrize("tilt", [0.0, 40.0])
+def test_contact_velocity_is_the_rigid_motion(ref, tilt):
     """Nodes inside the indenter take the object's velocity (relative rest): it
     equals the displacement of a body-fixed point between the two poses divided
-    by the step, up to the second-order term of the rotation."""
+    by the step, up to the second-order term of the rotation.  With the start
+    orientation tilted about the capsule's own axis (the same solid), the step's
+    rotation is applied in the world frame, q1 = dq q0, and the velocity is that
+    of dq's world axis, not of the body-frame axis q0^-1 dq q0."""
     p = W.small_sensor(cells=(8, 8, 4), shape=W.SHAPE_CAPSULE, radius=1.0e-3)
-    p = p.replace(half_length=1.0e-3, pose0=(p.pose0[0], p.pose0[1], p.height + 0.5e-3, 1, 0, 0, 0))
+    t = math.radians(tilt)
+    q0 = np.array([math.cos(t / 2), math.sin(t / 2), 0.0, 0.0])
+    p = p.replace(half_length=1.0e-3, pose0=(p.pose0[0], p.pose0[1], p.height + 0.5e-3, *q0))
     s = ref.OracleSim(p)
     ang = 0.01
-    q = (math.cos(ang / 2), 0.02 * math.sin(ang / 2), -0.03 * math.sin(ang / 2), math.sin(ang / 2))
-    qn = np.array(q) / np.linalg.norm(q)
+    dq = np.array((math.cos(ang / 2), 0.02 * math.sin(ang / 2), -0.03 * math.sin(ang / 2), math.sin(ang / 2)))
+    dq /= np.linalg.norm(dq)
+    qn = _quat_mul(dq, q0)
     c0 = np.array(p.pose0[:3])
     c1 = c0 + np.array([2e-6, -1e-6, -3e-6])
     s.set_target_pose(c1, qn)
@@ -609,10 +665,7 @@ def test_contact_velocity_is_the_rigid_motion(ref):
     inside = s.inside_mask()
     assert inside.sum() > 10
     X = brute.node_positions(p)[inside]
-    w, x, y, z = qn
-    R = np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
-                  [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
-                  [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+    R = _quat_matrix(qn) @ _quat_matrix(q0).T
     moved = (X - c0) @ R.T + c1
     want = (moved - X) / p.dt
     err = np.abs(V[inside] - want).max()
