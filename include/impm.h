@@ -295,6 +295,19 @@ int sim_batch_set_indenter_poses(sim_batch_t* b, const double* pos, const double
 int sim_batch_step(sim_batch_t* b, int32_t n_substeps);
 /* on = 0: launch the kernels one by one instead of replaying a graph. */
 int sim_batch_set_graph(sim_batch_t* b, int32_t on);
+/* Which members the following sim_batch_step calls advance: active[i] != 0
+ * (n flags, host memory, read during the call; every member is active after
+ * sim_batch_create).  For callers that re-solve some sensors of a batch and
+ * not others, such as a serving loop whose learned model covers the rest: a
+ * member that sits a call out keeps its particles, grid, counters and pose, and
+ * its next active call moves the indenter from its last stepped pose to the
+ * latest target.  Its kernels' blocks exit at once, so the call costs what its
+ * active members cost.  Errors, at the sim_batch_step call: SIM_EINVAL when a
+ * member sits out a call of an odd number of executed steps (n_substeps times
+ * subcycle: members keep their binned-order parity only over even counts), and
+ * SIM_ESTATE when a member sits out the batch's first call.  A call with no
+ * active member does nothing. */
+int sim_batch_set_active(sim_batch_t* b, const int32_t* active);
 int sim_batch_synchronize(sim_batch_t* b);
 /* out: n x H x W (heightmaps) or n x H x W x 3 (displacements), host or device. */
 int sim_batch_heightmaps(sim_batch_t* b, float* out, int32_t W, int32_t H, int32_t out_on_device);

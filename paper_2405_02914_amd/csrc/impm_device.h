@@ -134,7 +134,12 @@ struct BatchMap {
     const int* node_base;
     int n;
     int objects;               // some sensor of the launch has object particles
+    const int* active;         // n flags: members a batch call steps (NULL: every member)
 };
+
+// A member that sits out a batch call: every kernel of the call leaves its
+// state alone (its blocks exit before touching it).
+__device__ __forceinline__ bool member_active(const BatchMap& m, int s) { return !m.active || m.active[s] != 0; }
 
 __device__ __forceinline__ int batch_find(const int* base, int n, int g) {
     int lo = 0, hi = n - 1;

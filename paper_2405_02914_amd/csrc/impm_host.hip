@@ -1600,9 +1600,12 @@ struct sim_batch_s {
         KArgs* d_args = nullptr;
         int* d_tile_base = nullptr;
         int* d_node_base = nullptr;
+        int* d_active = nullptr;               // members' flags for the launches
+        std::vector<int> h_active;             // what d_active holds
         int tile_blocks = 0, node_blocks = 0;
         std::vector<KArgs> h_args;
     };
+    std::vector<int> active;                   // per sensor: stepped by sim_batch_step
     std::vector<Group> groups;
     bool use_graph = true;
     GraphCache graphs;
@@ -1628,8 +1631,10 @@ static int batch_build_groups(sim_batch_t* b) {
         (void)hipFree(g.d_args);
         (void)hipFree(g.d_tile_base);
         (void)hipFree(g.d_node_base);
+        (void)hipFree(g.d_active);
     }
     b->groups.clear();
+    b->active.assign(b->sims.size(), 1);
     for (int i = 0; i < (int)b->sims.size(); ++i) {
         const int t = b->sims[i]->tile_idx;
         int gi = -1;
@@ -1657,7 +1662,35 @@ static int batch_build_groups(sim_batch_t* b) {
         BHIPCHK(b, hipMalloc(&g.d_node_base, (n + 1) * sizeof(int)));
         BHIPCHK(b, hipMemcpy(g.d_tile_base, tb.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice));
         BHIPCHK(b, hipMemcpy(g.d_node_base, nb.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice));
+        g.h_active.assign(n, 1);
+        BHIPCHK(b, hipMalloc(&g.d_active, n * sizeof(int)));
+        BHIPCHK(b, hipMemcpy(g.d_active, g.h_active.data(), n * sizeof(int), hipMemcpyHostToDevice));
         g.h_args.assign(n, KArgs());
+    }
+    return SIM_OK;
+}
+
+// Upload the members' active flags of every group whose flags changed (after
+// the launches already enqueued have finished: they read the old flags).
+static int batch_sync_active(sim_batch_t* b) {
+    bool waited = false;
+    for (auto& g : b->groups) {
+        bool changed = false;
+        for (int k = 0; k < (int)g.members.size(); ++k) {
+            const int a = b->active[g.members[k]];
+            if (a != g.h_active[k]) {
+                g.h_active[k] = a;
+                changed = true;
+            }
+        }
+        if (changed) {
+            if (!waited) {
+                BHIPCHK(b, hipStreamSynchronize(b->stream));
+                waited = true;
+            }
+            BHIPCHK(b, hipMemcpy(g.d_active, g.h_active.data(), g.members.size() * sizeof(int),
+                                 hipMemcpyHostToDevice));
+        }
     }
     return SIM_OK;
 }
@@ -1727,6 +1760,7 @@ void sim_batch_destroy(sim_batch_t* b) {
         (void)hipFree(g.d_args);
         (void)hipFree(g.d_tile_base);
         (void)hipFree(g.d_node_base);
+        (void)hipFree(g.d_active);
     }
     for (sim_t* s : b->sims) sim_destroy(s);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
@@ -1754,12 +1788,34 @@ int sim_batch_set_indenter_poses(sim_batch_t* b, const double* pos, const double
     return SIM_OK;
 }
 
+int sim_batch_set_active(sim_batch_t* b, const int32_t* active) {
+    if (!b || !active) return bfail(b, SIM_EINVAL, "null argument");
+    for (int i = 0; i < (int)b->sims.size(); ++i) b->active[i] = active[i] ? 1 : 0;
+    return SIM_OK;
+}
+
 int sim_batch_step(sim_batch_t* b, int32_t n_substeps) {
     if (!b) return SIM_EINVAL;
     if (n_substeps < 1) return bfail(b, SIM_EINVAL, "n_substeps must be >= 1");
     const int n = (int)b->sims.size();
+    int first = -1;
+    bool all = true;
+    for (int i = 0; i < n; ++i) {
+        if (b->active[i] && first < 0) first = i;
+        all = all && b->active[i];
+    }
+    if (first < 0) return SIM_OK;                   // every member sits this call out
+    if (!all) {
+        // members that sit out keep their binned-order parity only over an even
+        // number of executed steps, and the first call prepares every member
+        if (((long long)n_substeps * b->sims[first]->P.subcycle) % 2 != 0)
+            return bfail(b, SIM_EINVAL, "members can sit out only calls of an even number of executed steps");
+        if (!b->sims[first]->pending)
+            return bfail(b, SIM_ESTATE, "the first sim_batch_step of a batch steps every member");
+    }
     std::vector<int> npass_max, npass;
     for (int i = 0; i < n; ++i) {
+        if (!b->active[i]) continue;
         sim_t* s = b->sims[i];
         const int rc = prepare_step(s, n_substeps, npass);
         if (rc) return bfail(b, rc, "sensor " + std::to_string(i) + ": " + s->err);
@@ -1768,8 +1824,10 @@ int sim_batch_step(sim_batch_t* b, int32_t n_substeps) {
     }
     int rc = batch_sync_args(b);
     if (rc) return rc;
-    sim_t* s0 = b->sims[0];
-    for (int i = 1; i < n; ++i) {
+    rc = batch_sync_active(b);
+    if (rc) return rc;
+    sim_t* s0 = b->sims[first];
+    for (int i = 0; i < n; ++i) {
         const sim_t* s = b->sims[i];
         if (s->cur != s0->cur || s->sbin != s0->sbin || s->pending != s0->pending ||
             ((s->gstep ^ s0->gstep) & 1))
@@ -1786,7 +1844,7 @@ int sim_batch_step(sim_batch_t* b, int32_t n_substeps) {
         L.ops = &kTileOps[g.tile_idx];
         int objects = 0;
         for (int mi : g.members) objects |= b->sims[mi]->n_obj > 0 ? 1 : 0;
-        L.m = BatchMap{g.d_args, g.d_tile_base, g.d_node_base, (int)g.members.size(), objects};
+        L.m = BatchMap{g.d_args, g.d_tile_base, g.d_node_base, (int)g.members.size(), objects, g.d_active};
         L.tile_blocks = g.tile_blocks;
         L.node_blocks = g.node_blocks;
         L.n = (int)g.members.size();
@@ -1832,12 +1890,14 @@ int sim_batch_step(sim_batch_t* b, int32_t n_substeps) {
     }
     if (le != hipSuccess) return bfail(b, SIM_EHIP, std::string("batch step launch: ") + hipGetErrorString(le));
     BHIPCHK(b, hipGetLastError());
-    for (sim_t* s : b->sims) finish_call(s, n_substeps, N);
+    for (int i = 0; i < n; ++i)
+        if (b->active[i]) finish_call(b->sims[i], n_substeps, N);
     // Members with storage compaction (sim_set_compaction on a member handle)
     // compact on their own streams once the batch's launches have completed;
     // the next call's argument sync picks up their new buffers.
     bool synced = false;
     for (int i = 0; i < n; ++i) {
+        if (!b->active[i]) continue;
         sim_t* s = b->sims[i];
         s->since_compact += N;
         if (s->compact_every > 0 && s->since_compact >= s->compact_every) {

@@ -249,6 +249,7 @@ __global__ __launch_bounds__(TL::NT) void k_p2g(BatchMap m, int cur) {
         s = batch_find(m.tile_base, m.n, t);
         t -= m.tile_base[s];
     }
+    if (!member_active(m, s)) return;
     const KArgs a = load_args(m, s);
     const gptr<const uint32_t> __restrict__ order = glb<const uint32_t>(pick(a.order, cur));
     const gptr<const uint32_t> __restrict__ bstart = glb<const uint32_t>(pick(a.bstart, cur));
@@ -291,6 +292,7 @@ __device__ __forceinline__ void grid_block(const BatchMap& m, int gnb, int sbin,
         s = batch_find(m.node_base, m.n, nb);
         nb -= m.node_base[s];
     }
+    if (!member_active(m, s)) return;
     const KArgs a = load_args(m, s);
     if (flag_load(&a.st->finished[pass])) return;
     const gptr<const uint32_t> __restrict__ bstart = glb<const uint32_t>(pick(a.bstart, sbin));
@@ -368,6 +370,7 @@ __device__ __forceinline__ void g2p2g_tile(const BatchMap& m, int gt, int cur, i
         s = batch_find(m.tile_base, m.n, t);
         t -= m.tile_base[s];
     }
+    if (!member_active(m, s)) return;
     const KArgs a = load_args(m, s);
     if (flag_load(&a.st->finished[pass])) {
         // carry the flag to the next pass slot so that every later pass of the
@@ -686,6 +689,7 @@ __device__ __forceinline__ void running_members(const BatchMap& m, int pass, boo
     for (int w = threadIdx.x; w < (nm + 31) / 32; w += blockDim.x) live[w] = 0u;
     __syncthreads();
     for (int s = threadIdx.x; s < nm; s += blockDim.x) {
+        if (!member_active(m, s)) continue;
         if (!flag_load(&m.args[s].st->finished[pass])) atomicOr(&live[s >> 5], 1u << (s & 31));
         else if (carry && blockIdx.x == 0) m.args[s].st->finished[pass + 1] = 1;
     }
@@ -758,7 +762,8 @@ __global__ __launch_bounds__(TL::NT) void k_extra_passes(BatchMap m, int tiles, 
     cooperative_groups::grid_group grid = cooperative_groups::this_grid();
     for (int pass = 1; pass < npass; ++pass) {
         bool done = true;
-        for (int s = 0; s < m.n; ++s) done = done && flag_load(&m.args[s].st->finished[pass]) != 0;
+        for (int s = 0; s < m.n; ++s)
+            done = done && (!member_active(m, s) || flag_load(&m.args[s].st->finished[pass]) != 0);
         if (done) break;                      // the same decision in every block
         if (threadIdx.x < kBlock)
             for (int nb = blockIdx.x; nb < node_blocks; nb += gridDim.x) grid_block<TL, true>(m, nb, cur, step, pass);
@@ -781,6 +786,7 @@ __global__ __launch_bounds__(TL::NT) void k_extra_passes(BatchMap m, int tiles, 
 // consecutive counts of a 4096-entry chunk; the waves scan their thread totals
 // with cross-lane shifts, so a chunk costs two block barriers.
 __global__ __launch_bounds__(1024) void k_scan(BatchMap m, int next, int limit_slots) {
+    if (!member_active(m, blockIdx.x)) return;
     const KArgs& a = m.args[blockIdx.x];
     const gptr<uint32_t> __restrict__ bstart_next = glb(pick(a.bstart, next));
     __shared__ uint32_t wsum[16];
@@ -835,6 +841,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(BatchMap m, int cur) {
         s = batch_find(m.tile_base, m.n, t);
         t -= m.tile_base[s];
     }
+    if (!member_active(m, s)) return;
     const KArgs a = load_args(m, s);
     const gptr<const uint32_t> __restrict__ order = glb<const uint32_t>(pick(a.order, cur));
     const gptr<const uint32_t> __restrict__ bstart = glb<const uint32_t>(pick(a.bstart, cur));

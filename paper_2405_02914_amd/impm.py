@@ -60,7 +60,8 @@ EXPORTS = ("sim_params_default", "sim_create", "sim_destroy", "sim_set_indenter_
            "sim_batch_set_indenter_poses", "sim_batch_step", "sim_batch_synchronize",
            "sim_batch_heightmaps", "sim_batch_displacements", "sim_batch_last_error",
            "sim_autotune_tile", "sim_set_graph", "sim_set_compaction", "sim_batch_set_graph",
-           "sim_indenter_depthmap", "sim_batch_depthmaps", "sim_surface_heightmap_noalloc")
+           "sim_indenter_depthmap", "sim_batch_depthmaps", "sim_surface_heightmap_noalloc",
+           "sim_batch_set_active")
 
 _lib = None
 
@@ -102,6 +103,7 @@ def lib():
     L.sim_indenter_depthmap.argtypes = [vp, fp, i32, i32, C.c_double, i32]
     L.sim_batch_depthmaps.argtypes = [vp, fp, i32, i32, C.c_double, i32]
     L.sim_batch_set_graph.argtypes = [vp, i32]
+    L.sim_batch_set_active.argtypes = [vp, C.POINTER(C.c_int32)]
     L.sim_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     L.sim_last_error.argtypes = [vp]
     L.sim_last_error.restype = C.c_char_p
@@ -380,6 +382,11 @@ class Batch:
 
     def sim_batch_set_graph(self, on=True):
         self._chk(lib().sim_batch_set_graph(self.h, int(on)))
+
+    def sim_batch_set_active(self, flags):
+        """Members the following sim_batch_step calls advance (n booleans)."""
+        a = np.ascontiguousarray(np.asarray(flags).reshape(self.n) != 0, np.int32)
+        self._chk(lib().sim_batch_set_active(self.h, a.ctypes.data_as(C.POINTER(C.c_int32))))
 
     def sim_batch_step(self, n):
         self._chk(lib().sim_batch_step(self.h, int(n)))

@@ -11,9 +11,11 @@ from the area of the last IMPM frame (relative to at least `area_floor`
 pixels, so that a touch from zero contact counts as a large change).
 
 Sensors are grouped by resolution class (one impm.Batch each, since a batch
-shares its sub-cycle count); a re-solve runs for the whole group, because a
-batch advances its sensors together.  All simulation, network, depth-map and
-contact-area work runs in the library's kernels; torch holds the buffers.
+shares its sub-cycle count).  A scheduled re-solve runs for the whole group; a
+contact-area re-solve runs only for the sensors that triggered it (the other
+members sit the batch call out, sim_batch_set_active), except for a group's
+first re-solve, which steps every member.  All simulation, network, depth-map
+and contact-area work runs in the library's kernels; torch holds the buffers.
 """
 from __future__ import annotations
 
@@ -60,14 +62,28 @@ class Server:
         self.record = torch.zeros((self.N, self.F + 1, RES, RES, 3), device=dev) if record else None
         self.latency_ms, self.kind = [], []
         self.resolves = {"scheduled": 0, "contact_area": 0}
+        self.stepped = [False] * len(self.groups)
 
-    def _resolve(self, g, n_substeps):
+    def _resolve(self, gi, n_substeps, members=None):
+        """Advance group gi's IMPM state to the frame's poses (every member, or
+        the members flagged in `members`); returns how many were re-solved."""
         import torch
-        a, b, batch = g
+        a, b, batch = self.groups[gi]
+        if members is None or not self.stepped[gi]:
+            members = np.ones(b - a, bool)
+        batch.sim_batch_set_active(members)
         batch.sim_batch_step(n_substeps)
+        self.stepped[gi] = True
         batch.sim_batch_displacements(RES, RES, out=self.tmp3[a:b])
-        self.disp[a:b] = self.tmp3[a:b] * 1000.0
-        self.net.sur_contact_area(self.depth[a:b], self.disp[a:b], self.tol, out=self.area_ref[a:b])
+        area = self.net.sur_contact_area(self.depth[a:b], self.tmp3[a:b] * 1000.0, self.tol)
+        if members.all():
+            self.disp[a:b] = self.tmp3[a:b] * 1000.0
+            self.area_ref[a:b] = area
+        else:
+            idx = torch.from_numpy(np.nonzero(members)[0]).to(self.disp.device)
+            self.disp[a + idx] = self.tmp3[a + idx] * 1000.0
+            self.area_ref[a + idx] = area[idx]
+        return int(members.sum())
 
     def step(self):
         """Serve the next frame of every sensor; returns its latency (ms)."""
@@ -90,11 +106,12 @@ class Server:
                 self.disp.copy_(self.tmp3)
             n_sub = self.scheds[0][k][0]
             kinds = []
-            for g in self.groups:
-                a, b, _ = g
-                if scheduled or dev[a:b].any():
-                    self.resolves["scheduled" if scheduled else "contact_area"] += b - a
-                    self._resolve(g, n_sub)
+            for gi, (a, b, _) in enumerate(self.groups):
+                if scheduled:
+                    self.resolves["scheduled"] += self._resolve(gi, n_sub)
+                    kinds.append("impm")
+                elif dev[a:b].any():
+                    self.resolves["contact_area"] += self._resolve(gi, n_sub, dev[a:b])
                     kinds.append("impm")
                 else:
                     kinds.append("surrogate")

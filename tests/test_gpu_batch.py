@@ -129,3 +129,80 @@ def test_autotune_returns_compiled_shape(gpu):
     s = gpu.Sim(params[0])
     s.sim_set_tile(*tile)          # accepted: a compiled shape
     s.close()
+
+
+def four_segments(scheds):
+    """Press, then the slide of each schedule split into three targets."""
+    out = []
+    for s in scheds:
+        (n0, p0, q0), (_, p1, q1) = s[0], s[1]
+        p0, p1 = np.array(p0), np.array(p1)
+        out.append([(n0, tuple(p0), q0), (10, tuple(p0 + (p1 - p0) / 3), q1), (10, tuple(p0 + 2 * (p1 - p0) / 3), q1),
+                    (10, tuple(p1), q1)])
+    return out
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_members_sit_out_calls(gpu, graph):
+    """sim_batch_set_active: a member that sits a call out keeps its state
+    bitwise and its counters; its next call moves it from its last stepped pose
+    to the latest target, which is what the same sensor computes alone when it
+    skips that call; the members that run compute what they compute alone."""
+    params, scheds = small_batch(n=4)
+    segs = four_segments(scheds)
+    masks = [[1, 1, 1, 1], [1, 0, 1, 1], [1, 0, 1, 0], [1, 1, 1, 1]]
+    b = gpu.Batch(params, tiles=TILES[:len(params)])
+    b.sim_batch_set_graph(graph)
+    before = None
+    for k, mask in enumerate(masks):
+        b.sim_batch_set_indenter_poses(np.array([s[k][1] for s in segs]), np.array([s[k][2] for s in segs]))
+        b.sim_batch_set_active(mask)
+        snap = [m.sim_read_particles() for m in b.sensors] if k else None
+        stats = [m.sim_get_stats()["steps"] for m in b.sensors]
+        b.sim_batch_step(segs[0][k][0])
+        b.sim_batch_synchronize()
+        for i, a in enumerate(mask):
+            if not a:
+                for u, w in zip(b.sensors[i].sim_read_particles(), snap[i]):
+                    assert np.array_equal(u, w), f"segment {k}: member {i} moved while sitting out"
+                assert b.sensors[i].sim_get_stats()["steps"] == stats[i]
+    for i, p in enumerate(params):
+        s = gpu.Sim(p)
+        s.sim_set_tile(*TILES[i])
+        for k, mask in enumerate(masks):
+            if mask[i]:
+                s.sim_set_indenter_pose(segs[i][k][1], segs[i][k][2])
+                s.sim_step(segs[i][k][0])
+        s.sim_synchronize()
+        for u, w in zip(b.sensors[i].sim_read_particles(), s.sim_read_particles()):
+            assert np.array_equal(u, w), f"member {i}"
+        st_b, st_s = b.sensors[i].sim_get_stats(), s.sim_get_stats()
+        assert st_b["passes"] == st_s["passes"] and st_b["steps"] == st_s["steps"]
+        s.close()
+    b.close()
+
+
+def test_sitting_out_is_checked(gpu):
+    """A member cannot sit out the batch's first call or a call of an odd
+    number of executed steps; a call with no active member does nothing."""
+    p = W.small_sensor(cells=(8, 8, 3), subcycle=1)
+    b = gpu.Batch([p, p])
+    b.sim_batch_set_indenter_poses(np.array([p.pose0[:3]] * 2), np.array([p.pose0[3:]] * 2))
+    b.sim_batch_set_active([1, 0])
+    with pytest.raises(gpu.SimError) as e:
+        b.sim_batch_step(2)
+    assert e.value.code == gpu.SIM_ESTATE
+    b.sim_batch_set_active([1, 1])
+    b.sim_batch_step(2)
+    b.sim_batch_set_active([0, 1])
+    with pytest.raises(gpu.SimError) as e:
+        b.sim_batch_step(1)
+    assert e.value.code == gpu.SIM_EINVAL
+    b.sim_batch_step(2)
+    b.sim_batch_set_active([0, 0])
+    x = [m.sim_read_particles()[0] for m in b.sensors]
+    b.sim_batch_step(2)
+    b.sim_batch_synchronize()
+    assert all(np.array_equal(m.sim_read_particles()[0], xi) for m, xi in zip(b.sensors, x))
+    assert [m.sim_get_stats()["steps"] for m in b.sensors] == [2, 4]
+    b.close()
