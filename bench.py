@@ -106,6 +106,9 @@ def parse(argv=None):
     ap.add_argument("--sur-steps", type=int, default=6000, help="surrogate workload: Adam steps timed")
     ap.add_argument("--sur-rollout", type=int, default=4,
                     help="surrogate workload: pushforward depth (the network's own predictions fed back)")
+    ap.add_argument("--sur-mix", default="8",
+                    help="surrogate workload: sensors per class (64, 96, 128 cells across) in the mixed serving "
+                         "run, one count or three (86,85,85 is config 5's 256)")
     return ap.parse_args(argv)
 
 
@@ -287,10 +290,13 @@ def bench_surrogate(args):
         served[name] = r
         srv.close()
         err(f"[serve] {name}: {r['served_rms_mm']:.4f} mm, {r['speedup_vs_plain_impm']:.1f}x plain IMPM")
-    mp, ms = serving.sensor_mix(8, 40)
-    srv = serving.Server(mp, ms, net, st)
+    counts = [int(c) for c in args.sur_mix.split(",")]
+    mp, ms = serving.sensor_mix(counts[0] if len(counts) == 1 else counts, 40)
+    srv = serving.Server(mp, ms, net, st, log=err)
     mixed = srv.run()
     srv.close()
+    if "plain_impm_frames_per_s_est" in mixed:
+        mixed["served_vs_plain_impm_est"] = mixed["frames_per_s"] / mixed["plain_impm_frames_per_s_est"]
     fwd, trn = surrogate_flops()
     step_ms = 1e3 * secs / steps
     achieved = trn * batch / (step_ms * 1e-3) / 1e12

@@ -30,9 +30,10 @@ RES = 128
 
 class Server:
     def __init__(self, params, scheds, net, stream, resolve_every=20, area_tol=0.10, area_floor=16.0,
-                 contact_tol_mm=0.02, record=False):
+                 contact_tol_mm=0.02, record=False, log=None):
         import torch
         self.params, self.scheds, self.net, self.st = params, scheds, net, stream
+        self.log = log or (lambda *a, **k: None)
         self.N = len(params)
         self.F = len(scheds[0])
         self.resolve_every, self.area_tol, self.area_floor = resolve_every, area_tol, area_floor
@@ -48,8 +49,11 @@ class Server:
                 j = i
                 while j < self.N and (params[j].subcycle, params[j].cells) == (params[i].subcycle, params[i].cells):
                     j += 1
+                t0 = time.perf_counter()
                 tile, _ = impm.sim_autotune_tile(params[i], steps=8, stream=stream.cuda_stream)
                 self.groups.append([i, j, impm.Batch(params[i:j], tiles=[tile] * (j - i), stream=stream.cuda_stream)])
+                self.log(f"[serve] group of {j - i} sensors of {params[i].cells} cells ready in "
+                         f"{time.perf_counter() - t0:.1f} s", flush=True)
                 i = j
             self.disp = torch.zeros((self.N, RES, RES, 3), device=dev)
             self.depth = torch.zeros((self.N, RES, RES), device=dev)
@@ -63,6 +67,10 @@ class Server:
         self.latency_ms, self.kind = [], []
         self.resolves = {"scheduled": 0, "contact_area": 0}
         self.stepped = [False] * len(self.groups)
+        self.last_solved = np.zeros(self.N, np.int64)   # frame of each sensor's last IMPM state
+        self.max_gap = np.zeros(self.N, np.int64)       # longest jump a re-solve has taken, in frames
+        self.full_s = [0.0] * len(self.groups)     # wall time of whole-group re-solves (plain batched frames)
+        self.full_n = [0] * len(self.groups)
 
     def _resolve(self, gi, n_substeps, members=None):
         """Advance group gi's IMPM state to the frame's poses (every member, or
@@ -72,7 +80,18 @@ class Server:
         if members is None or not self.stepped[gi]:
             members = np.ones(b - a, bool)
         batch.sim_batch_set_active(members)
+        sel = a + np.nonzero(members)[0]
+        self.max_gap[sel] = np.maximum(self.max_gap[sel], self.k + 1 - self.last_solved[sel])
+        self.last_solved[sel] = self.k + 1
+        full = bool(members.all())
+        if full:
+            self.st.synchronize()
+            t0 = time.perf_counter()
         batch.sim_batch_step(n_substeps)
+        if full:
+            self.st.synchronize()
+            self.full_s[gi] += time.perf_counter() - t0
+            self.full_n[gi] += 1
         self.stepped[gi] = True
         batch.sim_batch_displacements(RES, RES, out=self.tmp3[a:b])
         area = self.net.sur_contact_area(self.depth[a:b], self.tmp3[a:b] * 1000.0, self.tol)
@@ -123,6 +142,7 @@ class Server:
         self.k += 1
         self.latency_ms.append(ms)
         self.kind.append(kinds)
+        self.log(f"[serve] frame {k + 1}: {ms:.1f} ms, {kinds}", flush=True)
         return ms
 
     def run(self, frames=None):
@@ -137,13 +157,33 @@ class Server:
         for _ in range(frames or self.F):
             self.step()
         wall = time.perf_counter() - t0
+        # a sensor whose IMPM state latched a numerical error (the library's range
+        # and finiteness guards) is reported, not served on silently
+        failed = []
         for a, b, batch in self.groups:
-            batch.sim_batch_synchronize()
+            try:
+                batch.sim_batch_synchronize()
+            except impm.SimError:
+                pass
+            for q, sen in enumerate(batch.sensors):
+                try:
+                    sen.sim_get_stats()
+                except impm.SimError:
+                    failed.append(a + q)
         lat = np.array(self.latency_ms)
-        return {"sensors": self.N, "frames": len(lat), "wall_s": wall, "frames_per_s": self.N * len(lat) / wall,
-                "latency_p50_ms": float(np.percentile(lat, 50)), "latency_p99_ms": float(np.percentile(lat, 99)),
-                "resolved_sensor_frames": dict(self.resolves),
-                "groups": [(b - a, self.params[a].cells) for a, b, _ in self.groups]}
+        out = {"sensors": self.N, "frames": len(lat), "wall_s": wall, "frames_per_s": self.N * len(lat) / wall,
+               "latency_p50_ms": float(np.percentile(lat, 50)), "latency_p99_ms": float(np.percentile(lat, 99)),
+               "resolved_sensor_frames": dict(self.resolves), "failed_sensors": failed,
+               "failed_sensor_details": [{"sensor": i, "cells": self.params[i].cells, "shape": self.params[i].shape,
+                                          "longest_jump_frames": int(self.max_gap[i])} for i in failed],
+               "longest_jump_frames": int(self.max_gap.max()),
+               "groups": [(b - a, self.params[a].cells) for a, b, _ in self.groups]}
+        if all(self.full_n):
+            # a whole-group re-solve is one plain batched IMPM frame of the group
+            frame = [t / n for t, n in zip(self.full_s, self.full_n)]
+            out["impm_group_frame_ms"] = [1e3 * f for f in frame]
+            out["plain_impm_frames_per_s_est"] = self.N / sum(frame)
+        return out
 
     def close(self):
         for g in self.groups:
@@ -155,10 +195,12 @@ def sensor_mix(n_per_class, frames, seed=5):
     """Config 5's sensors: the 32 x 32 x 8 mm footprint at 64 x 64 x 16,
     96 x 96 x 24 and 128 x 128 x 32 cells (dx 0.5, 1/3 and 0.25 mm; 2, 3 and 4
     executed steps per substep), random indenters and press / slip / rotate
-    schedules of `frames` frames."""
+    schedules of `frames` frames.  n_per_class: one count for every class, or
+    three counts."""
+    counts = [n_per_class] * 3 if np.isscalar(n_per_class) else list(n_per_class)
     params, scheds = [], []
     for c, (cells, sub) in enumerate((((64, 64, 16), 2), ((96, 96, 24), 3), ((128, 128, 32), 4))):
-        p, s = W.surrogate_trajectories(n_per_class, seed=seed * 10 + c, cells=cells, dx=32e-3 / cells[0],
+        p, s = W.surrogate_trajectories(counts[c], seed=seed * 10 + c, cells=cells, dx=32e-3 / cells[0],
                                         n_substeps=50 * frames, subcycle=sub)
         params += p
         scheds += s
