@@ -101,3 +101,33 @@ def test_renderer_host_validation():
     assert L.rt_render(ctypes.byref(p), None, lights, fake, fake, fake, 1 << 30, None) == -1
     flat = R.light_records([dict(c=(0, 0, 0), e1=(1, 0, 0), e2=(2, 0, 0), L=(1, 1, 1))] * 4)
     assert L.rt_render(ctypes.byref(p), fake, flat, fake, fake, fake, 1 << 30, None) == -1
+
+
+def test_sim_create_host_validation():
+    """sim_create checks its parameters on the host before any device call:
+    each invalid record returns SIM_EINVAL and no handle (runs without a GPU)."""
+    import numpy as np
+    from paper_2405_02914_amd import impm, workloads as W
+    L = impm.lib()
+    base = W.small_sensor(cells=(6, 6, 3))
+    hf = W.heightfield_table(5, 2.0e-3, 0.3e-3, 1.5e-3, 4e-3)
+    bad_hf = hf.copy()
+    bad_hf[2, 2] = np.nan
+    cases = [dict(cells=(0, 6, 3)), dict(ppc=5), dict(dx=0.0), dict(dt=-1e-5), dict(E=0.0), dict(rho=0.0),
+             dict(nu=0.5), dict(nu=0.0), dict(subcycle=0), dict(rest_limit=0), dict(rest_limit=33),
+             dict(rest_threshold=-1.0), dict(mode=7), dict(shape=9),
+             dict(shape=W.SHAPE_HEIGHTFIELD, hf=bad_hf, hf_half=2.0e-3),
+             dict(shape=W.SHAPE_HEIGHTFIELD, hf=hf, hf_half=0.0),
+             dict(cells=(1100, 6, 3)),                         # more than 1023 nodes along x
+             dict(cells=(1000, 1000, 300)),                    # 2.4e9 particles
+             dict(pose0=(8e-3, 8e-3, 8e-3, 0.0, 0.0, 0.0, 0.0)),
+             dict(columns=np.full((6, 6), 4, np.int32)),       # taller than cells[2]
+             dict(columns=np.zeros((6, 6), np.int32)),         # no cell at all
+             dict(object_mode=5), dict(object_mode=1, shape=W.SHAPE_NONE), dict(object_mode=1, object_density=0.0)]
+    for kw in cases:
+        rec = impm.to_params(base.replace(**kw))
+        h = ctypes.c_void_p()
+        rc = L.sim_create(ctypes.byref(rec), None, ctypes.byref(h))
+        assert rc == impm.SIM_EINVAL and not h.value, kw
+    h = ctypes.c_void_p()
+    assert L.sim_create(None, None, ctypes.byref(h)) == impm.SIM_EINVAL
