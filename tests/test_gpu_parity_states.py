@@ -292,3 +292,43 @@ def test_full_size_object_particles_substep(gpu, ref, case):
     if not forced:
         assert abs(st["last_r"] - oc["last_r"]) <= 1e-5 * oc["last_r"]
     compare_states(g, o, x, f"{case} substep", dx=p.dx)
+
+
+@pytest.mark.slow
+def test_config3_full_batch_press_matches_oracle(gpu, ref):
+    """The 64-sensor batch of config 3 (44,180,480 particles, 32 to 96 cells
+    across) in the benchmark's launch configuration (autotuned tile shapes,
+    graph replay, storage compaction every 100 executed steps) through the first
+    segment of its schedule (50 substeps of the press, 100 executed steps, one
+    pass each, then a compaction): the largest and the smallest member against
+    the oracle run alone, positions within 1e-3 dx."""
+    params, scheds = W.config3()
+    tuned = {}
+    for p in params:
+        if p.cells not in tuned:
+            tuned[p.cells] = gpu.sim_autotune_tile(p, steps=8)[0]
+    b = gpu.Batch(params, tiles=[tuned[p.cells] for p in params])
+    b.sim_batch_set_graph(True)
+    for m in b.sensors:
+        m.sim_set_compaction(100)
+    n0 = scheds[0][0][0]
+    b.sim_batch_set_indenter_poses(np.array([s[0][1] for s in scheds]), np.array([s[0][2] for s in scheds]))
+    b.sim_batch_step(n0)
+    b.sim_batch_synchronize()
+    sizes = [p.n_particles for p in params]
+    for i in (int(np.argmax(sizes)), int(np.argmin(sizes))):
+        p = params[i]
+        o = ref.OracleSim(p)
+        o.set_target_pose(scheds[i][0][1], scheds[i][0][2])
+        o.step(n0)
+        xg = b.sensors[i].sim_read_particles()[0]
+        xo, X0 = o.state()[0], o.rest()[0]
+        st = b.sensors[i].sim_get_stats()
+        err = np.abs(xg - xo).max() / p.dx
+        print(f"[config3] member {i}: {p.cells} cells, shape {p.shape}, tile {tuned[p.cells]}, "
+              f"max|dx| {err:.3e} dx, max displacement {np.abs(xo - X0).max() / p.dx:.2f} dx, "
+              f"passes {st['passes']} over {st['steps']} steps", flush=True)
+        assert err <= 1e-3
+        assert st["passes"] == st["steps"] == n0 * p.subcycle == o.counters()["passes"]
+        o.close()
+    b.close()
