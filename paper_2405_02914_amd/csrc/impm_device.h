@@ -63,6 +63,7 @@ __device__ __forceinline__ gptr<T> glb(T* p) { return (gptr<T>)p; }
 // float4 is a class whose members take generic references, so its buffers are
 // reached as the plain 4-float vector type instead.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ gptr<f32x4> glb4(float4* p) { return (gptr<f32x4>)p; }
 
 struct KArgs {

@@ -788,8 +788,9 @@ __global__ __launch_bounds__(TL::NT) void k_extra_passes(BatchMap m, int tiles, 
 // Counting sort, scan part: exclusive prefix sum of the next step's tile sizes
 // (accumulated by the fused kernel), one block of 16 waves per sensor; clears the
 // counts and the per-step loop flags for the next step.  Each thread takes four
-// consecutive counts of a 4096-entry chunk; the waves scan their thread totals
-// with cross-lane shifts, so a chunk costs two block barriers.
+// consecutive counts of a 4096-entry chunk (one 16-byte load, clear and store
+// where all four exist); the waves scan their thread totals with cross-lane
+// shifts, so a chunk costs two block barriers.
 __global__ __launch_bounds__(1024) void k_scan(BatchMap m, int next, int limit_slots) {
     if (!member_active(m, blockIdx.x)) return;
     const KArgs& a = m.args[blockIdx.x];
@@ -801,12 +802,19 @@ __global__ __launch_bounds__(1024) void k_scan(BatchMap m, int next, int limit_s
     for (int t0 = 0; t0 < a.n_tiles; t0 += 4096) {
         const int u0 = t0 + 4 * tid;
         uint32_t c[4];
+        if (u0 + 3 < a.n_tiles) {
+            // four counts in one 16-byte load, cleared with one 16-byte store
+            const u32x4 v = *(gptr<const u32x4>)(glb(a.newcnt) + u0);
+            *(gptr<u32x4>)(glb(a.newcnt) + u0) = u32x4{0u, 0u, 0u, 0u};
+            c[0] = v.x; c[1] = v.y; c[2] = v.z; c[3] = v.w;
+        } else {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            c[q] = 0;
-            if (u0 + q < a.n_tiles) {
-                c[q] = glb(a.newcnt)[u0 + q];
-                glb(a.newcnt)[u0 + q] = 0;
+            for (int q = 0; q < 4; ++q) {
+                c[q] = 0;
+                if (u0 + q < a.n_tiles) {
+                    c[q] = glb(a.newcnt)[u0 + q];
+                    glb(a.newcnt)[u0 + q] = 0;
+                }
             }
         }
         const uint32_t tot = c[0] + c[1] + c[2] + c[3];
@@ -825,10 +833,16 @@ __global__ __launch_bounds__(1024) void k_scan(BatchMap m, int next, int limit_s
             if (w < wid) run += ws;
             chunk += ws;
         }
+        if (u0 + 3 < a.n_tiles) {
+            const uint32_t r0 = run, r1 = r0 + c[0], r2 = r1 + c[1], r3 = r2 + c[2];
+            *(gptr<u32x4>)(bstart_next + u0) = u32x4{r0, r1, r2, r3};
+            run = r3 + c[3];
+        } else {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            if (u0 + q < a.n_tiles) bstart_next[u0 + q] = run;
-            run += c[q];
+            for (int q = 0; q < 4; ++q) {
+                if (u0 + q < a.n_tiles) bstart_next[u0 + q] = run;
+                run += c[q];
+            }
         }
         carry += chunk;
         __syncthreads();   // the next chunk rewrites wsum
