@@ -316,16 +316,30 @@ __device__ __forceinline__ void grid_block(const BatchMap& m, int gnb, int sbin,
         lo[q] = m <= 0 ? 0 : (m + T[q] - 1) / T[q];
         hi[q] = min((nd[q] + 1) / T[q], a.NT[q] - 1);
     }
-    float W = 0.f, P0 = 0.f, P1 = 0.f, P2 = 0.f;
-    for (int tz = lo[2]; tz <= hi[2]; ++tz)
-        for (int ty = lo[1]; ty <= hi[1]; ++ty)
-            for (int tx = lo[0]; tx <= hi[0]; ++tx) {
-                const int t = (tz * a.NT[1] + ty) * a.NT[0] + tx;
-                if (bstart[t + 1] == bstart[t]) continue;
+    // Up to K0 x K1 x K2 covering tiles (2 per axis, 3 along 2-cell axes): every
+    // candidate's tile-start pair and partial is loaded before any is summed, so
+    // the loads of all tiles are in flight together; the sum runs in (tz, ty, tx)
+    // order.
+    constexpr int K0 = (TL::T0 + 3) / TL::T0 + 1, K1 = (TL::T1 + 3) / TL::T1 + 1, K2 = (TL::T2 + 3) / TL::T2 + 1;
+    constexpr int KT = K0 * K1 * K2;
+    f32x4 part[KT];
+#pragma unroll
+    for (int q = 0; q < KT; ++q) {
+        const int tx = lo[0] + q % K0, ty = lo[1] + (q / K0) % K1, tz = lo[2] + q / (K0 * K1);
+        part[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+        if (tx <= hi[0] && ty <= hi[1] && tz <= hi[2]) {
+            const int t = (tz * a.NT[1] + ty) * a.NT[0] + tx;
+            if (bstart[t + 1] != bstart[t]) {
                 const int l0 = i - (tx * TL::T0 - 1), l1 = j - (ty * TL::T1 - 1), l2 = k - (tz * TL::T2 - 1);
-                const f32x4 c = glb4(a.scratch)[(size_t)t * TL::PVOL + (l2 * TL::PY + l1) * TL::PX + l0];
-                W += c.x; P0 += c.y; P1 += c.z; P2 += c.w;
+                part[q] = glb4(a.scratch)[(size_t)t * TL::PVOL + (l2 * TL::PY + l1) * TL::PX + l0];
             }
+        }
+    }
+    float W = 0.f, P0 = 0.f, P1 = 0.f, P2 = 0.f;
+#pragma unroll
+    for (int q = 0; q < KT; ++q) {
+        W += part[q].x; P0 += part[q].y; P1 += part[q].z; P2 += part[q].w;
+    }
     if (a.objW) {
         // the object particles' mass weight and its rigid momentum at this node
         // (read and cleared for the next exchange)
