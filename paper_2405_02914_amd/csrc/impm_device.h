@@ -179,6 +179,23 @@ __host__ __device__ __forceinline__ uint32_t pack_cell(const int c[3]) {
     return (uint32_t)c[0] | ((uint32_t)c[1] << 10) | ((uint32_t)c[2] << 20);
 }
 
+// Position of the base node (l0, l1, l2) of a tile in the round-robin storage
+// order of its particles (a permutation of the tile's base nodes), chosen so
+// that the lanes of one LDS atomic in the particle-to-grid block fall on
+// distinct banks.  8-cell-wide, 4-cell-deep tiles of even height: a wave's 64
+// lanes take two planes, each group of 8 lanes one row: rows 0 and 2 of the
+// first plane, rows 0 and 2 of the second, then rows 1 and 3 of both; with the
+// row pitch of 12 words and the plane pitch of 16 mod 32 words every 32 lanes
+// address 32 distinct 8-byte bank pairs.  Other 8-cell-wide tiles: rows in the
+// order 0, 2, 1, 3, 4, 6, 5, 7, ..., so that every 16 lanes do.  Otherwise
+// linear.
+__host__ __device__ __forceinline__ int tile_slot(int l0, int l1, int l2, int T0, int T1, int T2) {
+    if (T0 == 8 && T1 == 4 && (T2 & 1) == 0)
+        return (l2 >> 1) * 64 + (l1 & 1) * 32 + (l2 & 1) * 16 + (l1 >> 1) * 8 + l0;
+    if (T0 == 8 && (T1 & 3) == 0) l1 = (l1 & ~3) | ((l1 & 1) << 1) | ((l1 >> 1) & 1);
+    return (l2 * T1 + l1) * T0 + l0;
+}
+
 // Quadratic B-spline stencil along one axis (the 3x3x3 kernel of Eq. 1): the
 // particle sits at fx in [0.5, 1.5) from its base node; weights of base, +1, +2.
 __device__ __forceinline__ void bspline_axis(int cell, float f, int& base, float& fx,

@@ -486,7 +486,7 @@ static void tile_order(const sim_t* s, const std::vector<uint32_t>& cells, const
         const int b0 = (int)(node % s->nn[0]), b1 = (int)((node / s->nn[0]) % s->nn[1]);
         const int b2 = (int)(node / ((uint64_t)s->nn[0] * s->nn[1]));
         const uint64_t t = ((uint64_t)(b2 / T2) * s->NT[1] + b1 / T1) * s->NT[0] + b0 / T0;
-        const uint64_t local = ((uint64_t)(b2 % T2) * T1 + b1 % T1) * T0 + b0 % T0;   // < 512
+        const uint64_t local = (uint64_t)tile_slot(b0 % T0, b1 % T1, b2 % T2, T0, T1, T2);   // < 512
         ord[q] = {(t << 22) | ((uint64_t)std::min<uint32_t>(rank, 4095) << 10) | local,
                   (uint32_t)(key[q] & 0xFFFFFFFFu)};
     }

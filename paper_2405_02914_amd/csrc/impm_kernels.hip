@@ -86,12 +86,19 @@ struct Tile {
     static constexpr int PX = TX + 4, PY = TY + 4, PZ = TZ + 4, PVOL = PX * PY * PZ;
     static constexpr bool PAD = PX % 8 == 0;
     static constexpr int SY = PAD ? (PX | 1) : PX;
-    static constexpr int SZ = PAD ? SY * PY + ((9 - (SY * PY) % 16) + 16) % 16 : SY * PY;
+    static constexpr bool ROWS4 = TX == 8 && TY == 4;   // planes padded to 16 mod 32 words
+    static constexpr int SZ = PAD     ? SY * PY + ((9 - (SY * PY) % 16) + 16) % 16
+                              : ROWS4 ? SY * PY + ((16 - (SY * PY) % 32) + 32) % 32
+                                      : SY * PY;
     static constexpr int AVOL = SZ * PZ;          // words per LDS plane (>= PVOL)
     static constexpr int GX = TX + 2, GY = TY + 2, GZ = TZ + 2, GVOL = GX * GY * GZ;
+    // row pitch of the G2P block in LDS (16-byte records): 12 on 8-cell-wide
+    // tiles, so that the rows two apart that share 16 lanes of a gather fall
+    // on different banks
+    static constexpr int GXS = TX == 8 ? 12 : GX, GVOLS = GXS * GY * GZ;
     static constexpr size_t LDS_P2G = (size_t)4 * AVOL * 8;
     static constexpr int NW = NB / 64;
-    static constexpr size_t LDS_G2P2G = LDS_P2G + (size_t)GVOL * 16 + 81 * 4 + (NW * kDirs + kDirs + 4) * 4;
+    static constexpr size_t LDS_G2P2G = LDS_P2G + (size_t)GVOLS * 16 + 81 * 4 + (NW * kDirs + kDirs + 4) * 4;
 };
 
 // Particle-to-grid contribution of one particle (Eq. 1-4) into the LDS node
@@ -402,7 +409,7 @@ __device__ __forceinline__ void g2p2g_tile(const BatchMap& m, int gt, int cur, i
     extern __shared__ unsigned long long lds_u64[];
     unsigned long long* acc = lds_u64;                                   // 4 * PVOL
     f32x4* gv = reinterpret_cast<f32x4*>(lds_u64 + 4 * TL::AVOL);        // GVOL x (vx, vy, vz, 0)
-    float* ve_part = reinterpret_cast<float*>(gv + TL::GVOL);            // 27 * 3
+    float* ve_part = reinterpret_cast<float*>(gv + TL::GVOLS);            // 27 * 3
     int* wc = reinterpret_cast<int*>(ve_part + 81);                      // NW * 27 wave counts
     int* running = wc + TL::NW * kDirs;                                  // 27 per-direction counts
     int* sh = running + kDirs;                                           // [0] = final
@@ -480,7 +487,7 @@ __device__ __forceinline__ void g2p2g_tile(const BatchMap& m, int gt, int cur, i
         f32x4 V = {0.f, 0.f, 0.f, 0.f};
         if (gx >= 0 && gy >= 0 && gz >= 0 && gx < a.nn[0] && gy < a.nn[1] && gz < a.nn[2])
             V = glb4(a.gridV)[((long long)gz * a.nn[1] + gy) * a.nn[0] + gx];
-        gv[kk] = V;
+        gv[(lz * TL::GY + ly) * TL::GXS + lx] = V;
     }
     for (int kk = tid; kk < 4 * TL::AVOL; kk += TL::NT) acc[kk] = 0ull;
     __syncthreads();
@@ -524,21 +531,23 @@ __device__ __forceinline__ void g2p2g_tile(const BatchMap& m, int gt, int cur, i
                 for (int q = 0; q < 3; ++q)
 #pragma unroll
                     for (int r = 0; r < 3; ++r) { S[q][r] = 0.f; Tb[q][r] = 0.f; U[q][r] = 0.f; }
-                const f32x4* g0 = gv + ((l2 * TL::GY + l1) * TL::GX + l0);
+                const f32x4* g0 = gv + ((l2 * TL::GY + l1) * TL::GXS + l0);
+                // per row (b, c): R = sum_a w_a V_abc; S_a collects w_b w_c V_abc,
+                // T_b collects w_c R and U_c collects w_b R
 #pragma unroll
                 for (int cz = 0; cz < 3; ++cz)
 #pragma unroll
                     for (int cy = 0; cy < 3; ++cy) {
                         const float wbc = w[1][cy] * w[2][cz];
+                        float R[3] = {0.f, 0.f, 0.f};
 #pragma unroll
                         for (int cx = 0; cx < 3; ++cx) {
-                            const f32x4 V = g0[(cz * TL::GY + cy) * TL::GX + cx];
-                            
-                            const float wac = w[0][cx] * w[2][cz], wab = w[0][cx] * w[1][cy];
+                            const f32x4 V = g0[(cz * TL::GY + cy) * TL::GXS + cx];
                             S[cx][0] += wbc * V.x; S[cx][1] += wbc * V.y; S[cx][2] += wbc * V.z;
-                            Tb[cy][0] += wac * V.x; Tb[cy][1] += wac * V.y; Tb[cy][2] += wac * V.z;
-                            U[cz][0] += wab * V.x; U[cz][1] += wab * V.y; U[cz][2] += wab * V.z;
+                            R[0] += w[0][cx] * V.x; R[1] += w[0][cx] * V.y; R[2] += w[0][cx] * V.z;
                         }
+#pragma unroll
+                        for (int r = 0; r < 3; ++r) { Tb[cy][r] += w[2][cz] * R[r]; U[cz][r] += w[1][cy] * R[r]; }
                     }
 #pragma unroll
                 for (int r = 0; r < 3; ++r) v[r] = w[0][0] * S[0][r] + w[0][1] * S[1][r] + w[0][2] * S[2][r];
@@ -988,7 +997,7 @@ __global__ __launch_bounds__(kBlock) void k_compact(KArgs a, int cur, float* __r
             l[q] = cell[q] - 1 + (f[q] >= 0.5f ? 1 : 0) - tc[q] * a.T[q];
             if (l[q] < 0 || l[q] >= a.T[q]) { err |= DEV_CFL; l[q] = l[q] < 0 ? 0 : a.T[q] - 1; }
         }
-        const uint32_t local = (uint32_t)((l[2] * a.T[1] + l[1]) * a.T[0] + l[0]);
+        const uint32_t local = (uint32_t)tile_slot(l[0], l[1], l[2], a.T[0], a.T[1], a.T[2]);
         const uint32_t r = atomicAdd(&cnt[local], 1u);
         keys[s0 + i] = (r << 9) | local;
     }
