@@ -21,7 +21,7 @@ __global__ void k_fill(float* p, long long n, float val);
 __global__ void k_scan(BatchMap m, int next, int limit_slots);
 __global__ void k_scatter(BatchMap m, int cur);
 __global__ void k_compact(KArgs a, int cur, float* soa_dst, uint32_t* cell_dst, uint8_t* flags_dst,
-                          const uint32_t* id_src, uint32_t* id_dst, long long* e_out);
+                          const uint32_t* id_src, uint32_t* id_dst, long long* e_out, int move_vc);
 __global__ void k_surface_accum(KArgs a, SurfArgs s);
 __global__ void k_depthmap(KArgs a, DepthArgs g, float* out);
 __global__ void k_surface_finish(const unsigned long long* acc, int npix, int W, float top, float dx, int mode,
@@ -716,8 +716,12 @@ static void finish_call(sim_t* s, int32_t n_substeps, long long N) {
 
 // Move the state into binned order `cur`, the order of the next step (see
 // sim_s).  The order must be a permutation, so a latched device error is
-// reported first.
-static int compact_storage(sim_t* s, int cur) {
+// reported first.  With move_vc false the velocity and affine planes stay
+// behind (the new storage holds stale values there): only for a compaction
+// inside a sim_step call, whose last step stores v and C of every elastomer
+// particle before any reader, and only without object particles, whose v
+// and C no step stores.
+static int compact_storage(sim_t* s, int cur, bool move_vc = true) {
     const size_t n = (size_t)s->n;
     // each buffer on its own, so that a call after a failed allocation retries
     // exactly the missing ones
@@ -731,7 +735,7 @@ static int compact_storage(sim_t* s, int cur) {
     long long e_new = a.e;   // kept if the kernel does not report a slot
     HIPCHK(s, hipMemcpyAsync(s->d_e_slot, &e_new, sizeof(long long), hipMemcpyHostToDevice, s->stream));
     hipLaunchKernelGGL(k_compact, dim3(s->n_tiles), dim3(kBlock), 0, s->stream, a, cur, s->soa_alt, s->cell_alt,
-                       s->flags_alt, s->d_id_of, s->id_of_alt, s->d_e_slot);
+                       s->flags_alt, s->d_id_of, s->id_of_alt, s->d_e_slot, move_vc ? 1 : 0);
     HIPCHK(s, hipGetLastError());
     HIPCHK(s, hipMemcpyAsync(&e_new, s->d_e_slot, sizeof(long long), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(s, hipStreamSynchronize(s->stream));
@@ -1205,6 +1209,13 @@ int sim_step(sim_t* s, int32_t n_substeps) {
         finish_call(s, n_substeps, N);
         return after_call(s, N);
     }
+    // Eager calls compact inside the call, never at its end: a compaction that
+    // fell due at the end of the previous call runs here, after the transfer
+    // above (which reads v and C) and before the first step.
+    const bool move_vc = s->n_obj > 0;
+    if (s->compact_every > 0 && s->since_compact >= s->compact_every) {
+        if (int rc2 = compact_storage(s, cur, move_vc)) return rc2;
+    }
     for (long long j = 0; j < N; ++j) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (s->prof) {
@@ -1225,11 +1236,11 @@ int sim_step(sim_t* s, int32_t n_substeps) {
         // the next step read the moved state through the refreshed record
         s->since_compact += 1;
         if (j + 1 < N && s->compact_every > 0 && s->since_compact >= s->compact_every) {
-            if (int rc2 = compact_storage(s, cur)) return rc2;
+            if (int rc2 = compact_storage(s, cur, move_vc)) return rc2;
         }
     }
     finish_call(s, n_substeps, N);
-    return after_call(s, 0);
+    return SIM_OK;
 }
 
 int sim_synchronize(sim_t* s) {

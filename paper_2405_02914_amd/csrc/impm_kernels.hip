@@ -957,7 +957,9 @@ __global__ __launch_bounds__(kBlock) void k_scatter(BatchMap m, int cur) {
 // kernels add to different LDS nodes.  With r the rank of a particle among those
 // of its base node l and c[.] the base-node counts, the new position is
 // sum_l' min(c[l'], r) + #{l' < l : c[l'] > r}, a bijection onto the range.
-// Every state plane, the packed cell, the flags and the id map move together;
+// Every state plane (with move_vc == 0 all but the velocity and affine planes,
+// which the caller's next steps rewrite before anything reads them), the
+// packed cell, the flags and the id map move together;
 // the calibration particle's new slot goes to e_out.  The rank is taken with LDS
 // atomics, so the storage order may differ between runs; no result depends on
 // it (the node sums are exact).  dirrank, which the next fused kernel rewrites,
@@ -969,7 +971,8 @@ __global__ __launch_bounds__(kBlock) void k_compact(KArgs a, int cur, float* __r
                                                     uint32_t* __restrict__ cell_dst,
                                                     uint8_t* __restrict__ flags_dst,
                                                     const uint32_t* __restrict__ id_src,
-                                                    uint32_t* __restrict__ id_dst, long long* __restrict__ e_out) {
+                                                    uint32_t* __restrict__ id_dst, long long* __restrict__ e_out,
+                                                    int move_vc) {
     __shared__ uint32_t cnt[kMaxTileNodes];
     const int t = blockIdx.x, tid = threadIdx.x;
     const gptr<uint32_t> order = glb(pick(a.order, cur));
@@ -1016,7 +1019,8 @@ __global__ __launch_bounds__(kBlock) void k_compact(KArgs a, int cur, float* __r
         flags_dst[dst] = glb(a.flags)[src];
         id_dst[dst] = id_src[src];
 #pragma unroll
-        for (int p = 0; p < NPLANES; ++p) soa_dst[(size_t)p * n + dst] = soa[(size_t)p * n + src];
+        for (int p = 0; p < NPLANES; ++p)
+            if (move_vc || p < V0 || p >= G0) soa_dst[(size_t)p * n + dst] = soa[(size_t)p * n + src];
         if ((long long)src == a.e) *e_out = (long long)dst;
     }
     __syncthreads();
