@@ -60,9 +60,14 @@ __device__ __forceinline__ unsigned long long to_fixed_scaled(float y, double ma
 __device__ __forceinline__ unsigned long long to_fixed_product(double w, float y, double magic) {
     return (unsigned long long)__double_as_longlong(fma(w, (double)y, magic));
 }
+// The low 51 bits of a sum hold the two's complement of v = round(sum * 2^32);
+// xor with 2^50 turns them into v + 2^50 in [0, 2^51), which as the mantissa of
+// 1.5 * 2^52 gives the double 1.5 * 2^52 + 2^50 + v exactly.  One FMA removes
+// the offset and scales by 2^-32, both exact, so the float is (float)(v * 2^-32).
 __device__ __forceinline__ float from_fixed(unsigned long long a) {
-    const long long v = ((long long)(a << 13)) >> 13;
-    return (float)((double)v * (1.0 / kFixScale));
+    const unsigned long long m = ((a & ((1ull << 51) - 1ull)) ^ (1ull << 50)) | 0x4338000000000000ull;
+    return (float)fma(__longlong_as_double((long long)m), 1.0 / kFixScale,
+                      -(kFixMagic + 1125899906842624.0) / kFixScale);
 }
 
 // Compile-time tile geometry.  A tile holds the particles whose stencil base
@@ -489,7 +494,8 @@ __device__ __forceinline__ void g2p2g_tile(const BatchMap& m, int gt, int cur, i
             V = glb4(a.gridV)[((long long)gz * a.nn[1] + gy) * a.nn[0] + gx];
         gv[(lz * TL::GY + ly) * TL::GXS + lx] = V;
     }
-    for (int kk = tid; kk < 4 * TL::AVOL; kk += TL::NT) acc[kk] = 0ull;
+    // (four planes of AVOL words: 2 * AVOL 16-byte stores)
+    for (int kk = tid; kk < 2 * TL::AVOL; kk += TL::NT) reinterpret_cast<u32x4*>(acc)[kk] = u32x4{0u, 0u, 0u, 0u};
     __syncthreads();
 
     const bool with_stress = fin || a.stress_each_pass;
