@@ -57,3 +57,13 @@ def test_negative_frame_count_is_rejected():
 def test_kernel_source_hash_is_stable():
     a, b = bench.kernel_source_sha(), bench.kernel_source_sha()
     assert a == b and len(a) == 16
+
+
+def test_compaction_interval_defaults_per_workload():
+    # the single sensor compacts every 50 executed steps, the other workloads
+    # every 100, and an explicit value (0 included) is kept
+    assert bench.parse([]).compact_every == 50
+    assert bench.parse(["--workload", "batch"]).compact_every == 100
+    assert bench.parse(["--workload", "object"]).compact_every == 100
+    assert bench.parse(["--compact-every", "0"]).compact_every == 0
+    assert bench.parse(["--workload", "batch", "--compact-every", "25"]).compact_every == 25
