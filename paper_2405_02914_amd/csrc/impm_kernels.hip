@@ -413,7 +413,7 @@ __device__ __forceinline__ void g2p2g_tile(const BatchMap& m, int gt, int cur, i
     const gptr<const uint32_t> __restrict__ bstart = glb<const uint32_t>(pick(a.bstart, cur));
     extern __shared__ unsigned long long lds_u64[];
     unsigned long long* acc = lds_u64;                                   // 4 * PVOL
-    f32x4* gv = reinterpret_cast<f32x4*>(lds_u64 + 4 * TL::AVOL);        // GVOL x (vx, vy, vz, 0)
+    f32x4* gv = reinterpret_cast<f32x4*>(lds_u64 + 4 * TL::AVOL);        // GY*GZ rows of GXS (vx, vy, vz, -)
     float* ve_part = reinterpret_cast<float*>(gv + TL::GVOLS);            // 27 * 3
     int* wc = reinterpret_cast<int*>(ve_part + 81);                      // NW * 27 wave counts
     int* running = wc + TL::NW * kDirs;                                  // 27 per-direction counts
@@ -959,9 +959,10 @@ __global__ __launch_bounds__(kBlock) void k_scatter(BatchMap m, int cur) {
 // slots of its binned range, so that its loads fill consecutive cache lines
 // again, and the order over the range becomes the identity.  Inside the range
 // they go round-robin over the stencil base nodes (the first particle of every
-// base node, then the second, ...), so that adjacent lanes of the next fused
-// kernels add to different LDS nodes.  With r the rank of a particle among those
-// of its base node l and c[.] the base-node counts, the new position is
+// base node, then the second, ...), the base nodes taken in the order of
+// tile_slot, so that the lanes of the next fused kernels add to different LDS
+// nodes on different banks.  With r the rank of a particle among those of its
+// base node, l its slot and c[.] the slot counts, the new position is
 // sum_l' min(c[l'], r) + #{l' < l : c[l'] > r}, a bijection onto the range.
 // Every state plane (with move_vc == 0 all but the velocity and affine planes,
 // which the caller's next steps rewrite before anything reads them), the
