@@ -246,11 +246,15 @@ int sim_set_tile_threads(sim_t* s, int32_t tx, int32_t ty, int32_t tz, int32_t t
 int sim_set_graph(sim_t* s, int32_t on);
 
 /* Storage compaction (a layout choice; the method is unchanged).  every_steps > 0:
- * once every_steps executed steps have accumulated (between the steps of an
- * eager sim_step call, at the end of a graph-replayed or batched call), the
- * particle state (all planes, cells, flags, id map) is moved
- * on the device into the binned order of the next step, round-robin over the
- * stencil base nodes inside each tile.  Without it, particles that cross tiles
+ * once every_steps executed steps have accumulated, the particle state (cells,
+ * flags, id map and the state planes) is moved on the device into the binned
+ * order of the next step, round-robin over the stencil base nodes inside each
+ * tile.  An eager sim_step call compacts only between its steps or before its
+ * first step (a compaction that fell due at the end of the previous call), and
+ * there leaves the velocity and affine planes behind unless the sensor has
+ * object particles: the call's last step stores them for every elastomer
+ * particle.  A graph-replayed or batched call compacts at its end and moves
+ * every plane.  Without it, particles that cross tiles
  * leave a tile's data spread over other tiles' cache lines, and neighbouring
  * lanes come to share base nodes.  The results are bitwise those of a run
  * without compaction: the node sums are exact and order-independent.  The
@@ -263,10 +267,13 @@ int sim_set_graph(sim_t* s, int32_t on);
  * every_steps = 0 (the default) turns it off; negative values are SIM_EINVAL. */
 int sim_set_compaction(sim_t* s, int32_t every_steps);
 
-/* Time every first-pass fused exchange kernel (grid-to-particle, commit,
- * particle-to-grid) with HIP events on the handle's stream (on != 0).
- * sim_profile_read synchronises, returns the summed kernel time (ms) and the
- * number of timed launches since the last read, and resets them. */
+/* Time the first-pass fused exchange kernel (grid-to-particle, commit,
+ * particle-to-grid) with HIP events on the handle's stream, in eager calls:
+ * on = 1 every launch, on = k > 1 the launches of every k-th executed step (a
+ * uniform sample; the event markers cost wall time), on = 0 none; negative
+ * values are SIM_EINVAL.  sim_profile_read synchronises, returns the summed
+ * kernel time (ms) and the number of timed launches since the last read, and
+ * resets them. */
 int sim_profile(sim_t* s, int32_t on);
 int sim_profile_read(sim_t* s, double* ms_total, int64_t* launches);
 

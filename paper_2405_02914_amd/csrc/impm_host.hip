@@ -168,6 +168,7 @@ struct sim_s {
     int stage_next = 0;
     // optional timing of the first-pass fused kernel with events on the stream
     bool prof = false;
+    int prof_every = 1;            // time the launches of every prof_every-th executed step
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     double prof_ms = 0.0;
@@ -1218,7 +1219,7 @@ int sim_step(sim_t* s, int32_t n_substeps) {
     }
     for (long long j = 0; j < N; ++j) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (s->prof) {
+        if (s->prof && g % s->prof_every == 0) {
             while (s->ev_pool.size() < s->ev_used + 2) {
                 hipEvent_t e;
                 HIPCHK(s, hipEventCreate(&e));
@@ -1566,7 +1567,9 @@ int sim_set_graph(sim_t* s, int32_t on) {
 
 int sim_profile(sim_t* s, int32_t on) {
     if (!s) return SIM_EINVAL;
+    if (on < 0) return fail(s, SIM_EINVAL, "on must be >= 0");
     s->prof = on != 0;
+    s->prof_every = on > 1 ? on : 1;
     return SIM_OK;
 }
 
